@@ -1,0 +1,124 @@
+/*
+ * niv.h -- C interface of the MI355X Neural Irradiance Volume library
+ * (libniv.so).
+ *
+ * The library evaluates and trains the model of Coomans, Nazzaro et al.,
+ * "Real-time Rendering with a Neural Irradiance Volume" (Eurographics 2026):
+ * a multi-level hash-grid encoding of the position plus spherical-harmonic
+ * encoding of the normal, fed to a ReLU MLP with a linear RGB output
+ * (Sec. 3.1), queried per G-buffer pixel and shaded with albedo * E / pi
+ * (Sec. 4.4, Eq. 2).
+ *
+ * Conventions for every call:
+ *  - Pointers named "device" point to memory on the current HIP device.  The
+ *    caller owns every buffer it passes; the library never frees them.
+ *  - Calls that take a hipStream_t only enqueue work on that stream and
+ *    return; errors raised by a kernel surface as NIV_ERR_HIP on a later
+ *    call.  Arguments are validated on the host before anything is enqueued;
+ *    on an error nothing is enqueued.
+ *  - A handle may be used from one host thread at a time.
+ */
+#ifndef NIV_H
+#define NIV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NIV_OK = 0,
+    NIV_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, bad size or value */
+    NIV_ERR_UNSUPPORTED = 2,  /* valid model shape the kernels do not cover */
+    NIV_ERR_HIP = 3,          /* a HIP runtime call failed */
+    NIV_ERR_WORKSPACE = 4,    /* caller-provided scratch too small */
+    NIV_ERR_STATE = 5         /* call out of order (e.g. no prepared model) */
+} niv_status;
+
+typedef enum { NIV_FP32 = 0, NIV_FP16 = 1, NIV_BF16 = 2 } niv_precision;
+
+/* Model shape (Sec. 3.1).  Level l has resolution floor(base_res *
+ * per_level_scale^l); it is stored densely ((N+1)^3 entries, x fastest) when
+ * that fits in T = 2^log2_T entries, else hashed into T entries with the
+ * primes 1, 2654435761, 805459861.  The input vector is the concatenation
+ * of the n_levels * n_features grid features (level-major), sh_bands^2 real
+ * spherical harmonics of the unit normal, and for each scene variable the
+ * 2*extra_bands values sin(2^k pi t), cos(2^k pi t) (Sec. 6).  Hidden layers
+ * are width wide with ReLU, no biases; the output layer is linear.
+ * Supported by the kernels: n_features = 2, n_levels a multiple of 4 (<= 32),
+ * sh_bands = 4, width 64 or 128, 1 <= n_hidden <= 8, n_out = 3, and an input
+ * width that is a multiple of 16. */
+typedef struct {
+    int32_t n_levels, log2_T, n_features;
+    double  base_res, per_level_scale;
+    int32_t sh_bands;
+    int32_t n_extra, extra_bands;
+    int32_t width, n_hidden, n_out;
+    double  aabb_min[3], aabb_max[3];   /* box mapped onto every level */
+} niv_config;
+
+typedef struct niv_handle niv_handle;
+
+/* Validates `cfg` and builds the level table and parameter layout on the
+ * host.  *out receives a new handle (release with niv_destroy). */
+niv_status niv_create(const niv_config *cfg, niv_handle **out);
+void niv_destroy(niv_handle *h);
+
+/* Sizes: number of FP32 master parameters (layout [grid entries][F] then
+ * W_0, W_1, ... W_H row-major [out][in]), number of grid values, and the
+ * bytes of a prepared model for `prec` (see niv_prepare).  NULL outputs are
+ * skipped. */
+niv_status niv_sizes(const niv_handle *h, niv_precision prec, int64_t *n_params,
+                     int64_t *n_grid_values, int64_t *prepared_bytes);
+
+/* Per-level resolution, dense flag, first entry and entry count; each array
+ * has n_levels elements (host memory; NULL arrays are skipped). */
+niv_status niv_level_info(const niv_handle *h, int64_t *res, int32_t *dense,
+                          int64_t *offset, int64_t *size);
+
+/* Converts FP32 master parameters (device, n_params floats) into a prepared
+ * model (device, prepared_bytes, 256-byte aligned) for queries at `prec`:
+ * weights re-laid out as matrix-core operands, grid latents and weights
+ * rounded to nearest-even in FP16/BF16 (copied for FP32). */
+niv_status niv_prepare(niv_handle *h, const float *params, void *prepared,
+                       niv_precision prec, hipStream_t stream);
+
+/* One G-buffer (or any list of `count` query points).  All arrays device,
+ * row-major, 4-byte aligned:
+ *   pos, nrm     [count][3] float   world position, surface normal (any length)
+ *   albedo       [count][3] float   or NULL (then out_L must be NULL)
+ *   mask         [count]    uint8   1 = pixel covered, 0 = skip; NULL = all
+ *   extra_values                    the frame's scene variables (n_extra used)
+ *   model        prepared model for the precision of the call
+ *   out_E        [count][3] float   irradiance E_theta(x, n) (indirect, Sec. 3)
+ *   out_L        [count][3] float   albedo * E / pi (Eq. 2), or NULL
+ *   out_flags    [count]    uint8   or NULL: bit 0 position outside the box
+ *                (clamped), bit 1 non-finite input or zero normal (E set to
+ *                0), bit 2 non-finite E.  Masked-off pixels get E = L = 0,
+ *                flags 0. */
+typedef struct {
+    int64_t count;
+    const float *pos, *nrm, *albedo;
+    const uint8_t *mask;
+    float extra_values[4];
+    const void *model;
+    float *out_E, *out_L;
+    uint8_t *out_flags;
+} niv_frame;
+
+/* Evaluates every pixel of `n_frames` frames (Sec. 4.4: per-pixel E(x, n)
+ * from the position and normal buffers, then Eq. 2), arithmetic of `prec`:
+ * features in FP32, matrix products on the matrix cores with FP32
+ * accumulation (FP32 operands for NIV_FP32). */
+niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                     niv_precision prec, hipStream_t stream);
+
+const char *niv_status_string(niv_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NIV_H */

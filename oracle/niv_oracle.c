@@ -331,7 +331,8 @@ static void orc_mlp(const orc_config *c, const double *const *W, const double *x
 
 /* Batch query (Sec. 4.4 rendering): for every point with mask != 0 compute
  * E = E_theta(x, n[, extra]) and L = albedo * E / pi (Eq. 2).  Points with
- * mask == 0 or a degenerate input get E = L = 0.  `extra` is per point
+ * mask == 0 get E = L = 0 and no flags; a degenerate input (non-finite
+ * value, zero normal) gets E = L = 0 and the bad-input flag.  `extra` is per point
  * ([count][n_extra]) or NULL when n_extra == 0.  Any of albedo, mask,
  * out_L, out_flags may be NULL. */
 void orc_query(const orc_config *c, const double *params, int64_t count,
@@ -351,6 +352,7 @@ void orc_query(const orc_config *c, const double *params, int64_t count,
         double n[3] = {nrm[3 * q], nrm[3 * q + 1], nrm[3 * q + 2]};
         int flags = 0;
         int bad = 0;
+        int on = mask ? mask[q] != 0 : 1;
         for (int a = 0; a < 3; ++a) bad |= !isfinite(p[a]) || !isfinite(n[a]);
         if (!bad && c->sh_bands > 0 && n[0] == 0.0 && n[1] == 0.0 && n[2] == 0.0)
             bad = 1;
@@ -358,9 +360,8 @@ void orc_query(const orc_config *c, const double *params, int64_t count,
             ex[e] = extra ? extra[q * c->n_extra + e] : 0.0;
             bad |= !isfinite(ex[e]);
         }
-        int on = mask ? mask[q] != 0 : 1;
         for (int o = 0; o < c->n_out; ++o) E[o] = 0.0;
-        if (bad) flags |= ORC_FLAG_BAD_INPUT;
+        if (on && bad) flags |= ORC_FLAG_BAD_INPUT;
         if (on && !bad) {
             flags |= orc_encode(c, &lv, params, p, n, ex, x0);
             if (out_x0) memcpy(out_x0 + q * in, x0, sizeof(double) * in);

@@ -1,0 +1,209 @@
+// C interface of libniv: argument checking, model tables, launches.
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "niv_internal.h"
+
+using namespace niv;
+
+namespace {
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Level table (Sec. 3.1): resolution floor(N_min * b^l) (with a 2^-40
+// relative guard so an exact integer product is not floored down), dense
+// (N+1)^3 storage when it fits in T entries, else T hashed entries.
+void build_levels(Model &m)
+{
+    const niv_config &c = m.cfg;
+    const int64_t T = int64_t(1) << c.log2_T;
+    int64_t total = 0;
+    for (int l = 0; l < c.n_levels; ++l) {
+        double x = c.base_res * pow(c.per_level_scale, (double)l);
+        int64_t N = (int64_t)floor(x * (1.0 + 0x1p-40));
+        int64_t side = N + 1;
+        bool dense = side * side * side <= T;
+        m.res[l] = N;
+        m.dense[l] = dense ? 1 : 0;
+        m.size[l] = dense ? side * side * side : T;
+        m.offset[l] = total;
+        total += m.size[l];
+        LevelConst &lv = m.lv[l];
+        for (int a = 0; a < 3; ++a) {
+            double k = (double)N / (c.aabb_max[a] - c.aabb_min[a]);
+            lv.k[a] = k;
+            lv.o[a] = -(c.aabb_min[a] * k);
+        }
+        lv.nm1 = (int32_t)(N - 1);
+        lv.dense = dense ? 1 : 0;
+        lv.off = (uint32_t)m.offset[l];
+        lv.s1 = (uint32_t)side;
+        lv.s2 = (uint32_t)(side * side);
+        lv.pad = 0;
+    }
+    m.n_entries = total;
+    m.n_grid_values = total * c.n_features;
+    m.din = c.n_levels * c.n_features + c.sh_bands * c.sh_bands + c.n_extra * 2 * c.extra_bands;
+    m.n_params = m.n_grid_values + (int64_t)c.width * m.din +
+                 (int64_t)(c.n_hidden - 1) * c.width * c.width + (int64_t)c.n_out * c.width;
+}
+
+niv_status check_config(const niv_config *c)
+{
+    if (c->n_levels < 1 || c->n_levels > kMaxLevels || c->log2_T < 1 || c->log2_T > 24 ||
+        c->n_features < 1 || c->n_features > 8 || !(c->base_res >= 1.0) ||
+        !(c->per_level_scale >= 1.0) || c->sh_bands < 0 || c->sh_bands > 8 || c->n_extra < 0 ||
+        c->n_extra > 4 || c->extra_bands < 0 || c->extra_bands > 16 || c->width < 1 ||
+        c->n_hidden < 1 || c->n_out < 1 || c->n_out > 4)
+        return NIV_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (!(c->aabb_max[a] > c->aabb_min[a]) || !isfinite(c->aabb_min[a]) ||
+            !isfinite(c->aabb_max[a]))
+            return NIV_ERR_INVALID_ARG;
+    double top = c->base_res * pow(c->per_level_scale, (double)(c->n_levels - 1));
+    if (!(top < 2147483647.0 / 2)) return NIV_ERR_INVALID_ARG;
+    return NIV_OK;
+}
+
+// Which fused-kernel shape serves this configuration, or -1.
+int kernel_kind(const Model &m)
+{
+    const niv_config &c = m.cfg;
+    if (c.n_features != 2 || c.sh_bands != 4 || c.n_out != 3) return -1;
+    if (c.n_extra > 0 && c.extra_bands != 8) return -1;
+    // hashed levels rely on corner coordinates below T
+    for (int l = 0; l < c.n_levels; ++l)
+        if (!m.dense[l] && m.res[l] + 1 > (int64_t(1) << c.log2_T)) return -1;
+    if (m.n_entries > (int64_t)0xFFFFFFFF / 2) return -1;
+    if (c.n_levels == 8 && c.n_extra == 0 && c.width == 64 && c.n_hidden == 2) return kUnitCube;
+    if (c.n_levels == 16 && c.n_extra == 0 && c.width == 64 && c.n_hidden == 3) return kRoom;
+    if (c.n_levels == 16 && c.n_extra == 1 && c.width == 128 && c.n_hidden == 4) return kWide6D;
+    return -1;
+}
+
+niv_status hip_status(hipError_t e) { return e == hipSuccess ? NIV_OK : NIV_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+niv_status niv_create(const niv_config *cfg, niv_handle **out)
+{
+    if (!cfg || !out) return NIV_ERR_INVALID_ARG;
+    *out = nullptr;
+    niv_status s = check_config(cfg);
+    if (s != NIV_OK) return s;
+    niv_handle *h = new (std::nothrow) niv_handle;
+    if (!h) return NIV_ERR_INVALID_ARG;
+    memset(h, 0, sizeof(*h));
+    h->m.cfg = *cfg;
+    build_levels(h->m);
+    h->m.kind = kernel_kind(h->m);
+    *out = h;
+    return NIV_OK;
+}
+
+void niv_destroy(niv_handle *h) { delete h; }
+
+niv_status niv_sizes(const niv_handle *h, niv_precision prec, int64_t *n_params,
+                     int64_t *n_grid_values, int64_t *prepared_bytes)
+{
+    if (!h) return NIV_ERR_INVALID_ARG;
+    if (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16) return NIV_ERR_INVALID_ARG;
+    if (n_params) *n_params = h->m.n_params;
+    if (n_grid_values) *n_grid_values = h->m.n_grid_values;
+    if (prepared_bytes) {
+        if (h->m.kind < 0) return NIV_ERR_UNSUPPORTED;
+        OpLayout L = op_layout(h->m.kind, prec);
+        int64_t es = prec == NIV_FP32 ? 4 : 2;
+        *prepared_bytes = L.grid_off + h->m.n_grid_values * es;
+    }
+    return NIV_OK;
+}
+
+niv_status niv_level_info(const niv_handle *h, int64_t *res, int32_t *dense, int64_t *offset,
+                          int64_t *size)
+{
+    if (!h) return NIV_ERR_INVALID_ARG;
+    for (int l = 0; l < h->m.cfg.n_levels; ++l) {
+        if (res) res[l] = h->m.res[l];
+        if (dense) dense[l] = h->m.dense[l];
+        if (offset) offset[l] = h->m.offset[l];
+        if (size) size[l] = h->m.size[l];
+    }
+    return NIV_OK;
+}
+
+niv_status niv_prepare(niv_handle *h, const float *params, void *prepared, niv_precision prec,
+                       hipStream_t stream)
+{
+    if (!h || !params || !prepared) return NIV_ERR_INVALID_ARG;
+    if (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16) return NIV_ERR_INVALID_ARG;
+    if (!aligned(params, 4) || !aligned(prepared, 256)) return NIV_ERR_INVALID_ARG;
+    if (h->m.kind < 0) return NIV_ERR_UNSUPPORTED;
+    return hip_status(launch_prepare(h->m, params, prepared, prec, stream));
+}
+
+niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, niv_precision prec,
+                     hipStream_t stream)
+{
+    if (!h || n_frames < 0 || (n_frames > 0 && !frames)) return NIV_ERR_INVALID_ARG;
+    if (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16) return NIV_ERR_INVALID_ARG;
+    if (h->m.kind < 0) return NIV_ERR_UNSUPPORTED;
+    for (int f = 0; f < n_frames; ++f) {
+        const niv_frame &fr = frames[f];
+        if (fr.count < 0) return NIV_ERR_INVALID_ARG;
+        if (fr.count == 0) continue;
+        if (!fr.pos || !fr.nrm || !fr.out_E || !fr.model) return NIV_ERR_INVALID_ARG;
+        if (fr.out_L && !fr.albedo) return NIV_ERR_INVALID_ARG;
+        if (!aligned(fr.pos, 4) || !aligned(fr.nrm, 4) || !aligned(fr.out_E, 4) ||
+            (fr.albedo && !aligned(fr.albedo, 4)) || (fr.out_L && !aligned(fr.out_L, 4)) ||
+            !aligned(fr.model, 256))
+            return NIV_ERR_INVALID_ARG;
+        for (int e = 0; e < h->m.cfg.n_extra; ++e)
+            if (!isfinite(fr.extra_values[e])) return NIV_ERR_INVALID_ARG;
+    }
+    OpLayout L = op_layout(h->m.kind, prec);
+    for (int f = 0; f < n_frames; ++f) {
+        const niv_frame &fr = frames[f];
+        if (fr.count == 0) continue;
+        QueryArgs a;
+        memset(&a, 0, sizeof(a));
+        a.pos = fr.pos;
+        a.nrm = fr.nrm;
+        a.albedo = fr.albedo;
+        a.mask = fr.mask;
+        a.out_E = fr.out_E;
+        a.out_L = fr.out_L;
+        a.out_flags = fr.out_flags;
+        a.model = static_cast<const uint8_t *>(fr.model);
+        a.count = fr.count;
+        a.grid_off = (uint64_t)L.grid_off;
+        a.hash_mask = (uint32_t)((int64_t(1) << h->m.cfg.log2_T) - 1);
+        for (int e = 0; e < 4; ++e) a.extra[e] = fr.extra_values[e];
+        for (int c = 0; c < 3; ++c) {
+            a.lo[c] = h->m.cfg.aabb_min[c];
+            a.hi[c] = h->m.cfg.aabb_max[c];
+        }
+        memcpy(a.lv, h->m.lv, sizeof(a.lv));
+        hipError_t e = launch_query(h->m, a, prec, stream);
+        if (e != hipSuccess) return NIV_ERR_HIP;
+    }
+    return NIV_OK;
+}
+
+const char *niv_status_string(niv_status s)
+{
+    switch (s) {
+    case NIV_OK: return "ok";
+    case NIV_ERR_INVALID_ARG: return "invalid argument";
+    case NIV_ERR_UNSUPPORTED: return "model shape not supported by the kernels";
+    case NIV_ERR_HIP: return "HIP runtime error";
+    case NIV_ERR_WORKSPACE: return "workspace too small";
+    case NIV_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

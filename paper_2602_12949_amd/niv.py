@@ -1,0 +1,204 @@
+"""Python binding of libniv (the C interface in include/niv.h).
+
+Marshalling only: device memory comes from torch tensors, streams from
+torch's current stream; every step of the method runs in the library's HIP
+kernels.  There is no CPU fallback: importing works without a GPU, but any
+call that needs the library raises if libniv.so is missing.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libniv.so")
+
+NIV_OK, NIV_ERR_INVALID_ARG, NIV_ERR_UNSUPPORTED, NIV_ERR_HIP, NIV_ERR_WORKSPACE, NIV_ERR_STATE = range(6)
+FP32, FP16, BF16 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
+FLAG_OUTSIDE, FLAG_BAD_INPUT, FLAG_BAD_OUTPUT = 1, 2, 4
+
+
+class NivError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("log2_T", C.c_int32), ("n_features", C.c_int32),
+                ("base_res", C.c_double), ("per_level_scale", C.c_double),
+                ("sh_bands", C.c_int32), ("n_extra", C.c_int32), ("extra_bands", C.c_int32),
+                ("width", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32),
+                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("count", C.c_int64), ("pos", C.c_void_p), ("nrm", C.c_void_p),
+                ("albedo", C.c_void_p), ("mask", C.c_void_p),
+                ("extra_values", C.c_float * 4), ("model", C.c_void_p),
+                ("out_E", C.c_void_p), ("out_L", C.c_void_p), ("out_flags", C.c_void_p)]
+
+
+_lib = None
+_SYMBOLS = ["niv_create", "niv_destroy", "niv_sizes", "niv_level_info", "niv_prepare",
+            "niv_query", "niv_status_string"]
+
+
+def lib():
+    """The loaded libniv.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.niv_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.niv_destroy.argtypes = [vp]
+        L.niv_destroy.restype = None
+        L.niv_sizes.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64)]
+        L.niv_level_info.argtypes = [vp, vp, vp, vp, vp]
+        L.niv_prepare.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.niv_query.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp]
+        L.niv_status_string.argtypes = [C.c_int]
+        L.niv_status_string.restype = C.c_char_p
+        for f in _SYMBOLS:
+            if f != "niv_destroy":
+                getattr(L, f).restype = getattr(L, f).restype or C.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    return lib().niv_status_string(int(s)).decode()
+
+
+def _check(status, what):
+    if status != NIV_OK:
+        raise NivError(status, what)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def make_config(d) -> Config:
+    c = Config()
+    for k in ("n_levels", "log2_T", "n_features", "sh_bands", "n_extra", "extra_bands",
+              "width", "n_hidden", "n_out"):
+        setattr(c, k, int(d[k]))
+    c.base_res = float(d["base_res"])
+    c.per_level_scale = float(d["per_level_scale"])
+    c.aabb_min = (C.c_double * 3)(*[float(x) for x in d["aabb_min"]])
+    c.aabb_max = (C.c_double * 3)(*[float(x) for x in d["aabb_max"]])
+    return c
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class NIV:
+    """A model shape (niv_create); parameters live in caller-owned tensors."""
+
+    def __init__(self, cfg):
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        h = C.c_void_p()
+        _check(lib().niv_create(C.byref(self._c), C.byref(h)), "niv_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.niv_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------- sizes
+    def sizes(self, prec="fp16"):
+        n_p, n_g, nb = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().niv_sizes(self._h, _prec(prec), C.byref(n_p), C.byref(n_g), C.byref(nb)),
+               "niv_sizes")
+        return n_p.value, n_g.value, nb.value
+
+    @property
+    def n_params(self):
+        n_p, n_g = C.c_int64(), C.c_int64()
+        _check(lib().niv_sizes(self._h, FP32, C.byref(n_p), C.byref(n_g), None), "niv_sizes")
+        return n_p.value
+
+    @property
+    def n_grid_values(self):
+        n_p, n_g = C.c_int64(), C.c_int64()
+        _check(lib().niv_sizes(self._h, FP32, C.byref(n_p), C.byref(n_g), None), "niv_sizes")
+        return n_g.value
+
+    def level_info(self):
+        import numpy as np
+        L = self.cfg["n_levels"]
+        res = np.zeros(L, np.int64)
+        dense = np.zeros(L, np.int32)
+        off = np.zeros(L, np.int64)
+        size = np.zeros(L, np.int64)
+        _check(lib().niv_level_info(self._h, res.ctypes.data, dense.ctypes.data, off.ctypes.data,
+                                    size.ctypes.data), "niv_level_info")
+        return dict(res=res, dense=dense.astype(bool), offset=off, size=size)
+
+    # ---------------------------------------------------------- model
+    def prepare(self, params, prec="fp16", out=None):
+        """Prepared model for queries at `prec` from FP32 master parameters."""
+        assert params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()
+        assert params.numel() == self.n_params
+        nb = self.sizes(prec)[2]
+        if out is None:
+            out = torch.empty(nb, dtype=torch.uint8, device=params.device)
+        assert out.numel() >= nb and out.data_ptr() % 256 == 0
+        _check(lib().niv_prepare(self._h, _ptr(params), _ptr(out), _prec(prec), _stream()),
+               "niv_prepare")
+        return out
+
+    def frame(self, pos, nrm, model, albedo=None, mask=None, extra=(), out_E=None, out_L=None,
+              out_flags=None, want_L=True, want_flags=True):
+        """Builds a niv_frame (and the output tensors) for one G-buffer."""
+        n = pos.numel() // 3
+        dev = pos.device
+        for t in (pos, nrm, albedo):
+            if t is not None:
+                assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        if mask is not None:
+            assert mask.dtype == torch.uint8 and mask.is_contiguous()
+        if out_E is None:
+            out_E = torch.empty(pos.shape, dtype=torch.float32, device=dev)
+        if out_L is None and want_L and albedo is not None:
+            out_L = torch.empty(pos.shape, dtype=torch.float32, device=dev)
+        if out_flags is None and want_flags:
+            out_flags = torch.empty(pos.shape[:-1], dtype=torch.uint8, device=dev)
+        f = Frame()
+        f.count = n
+        f.pos, f.nrm, f.albedo, f.mask = (_ptr(pos).value, _ptr(nrm).value,
+                                          _ptr(albedo).value, _ptr(mask).value)
+        ev = list(extra) + [0.0] * (4 - len(extra))
+        f.extra_values = (C.c_float * 4)(*[float(x) for x in ev])
+        f.model = _ptr(model).value
+        f.out_E = _ptr(out_E).value
+        f.out_L = _ptr(out_L).value
+        f.out_flags = _ptr(out_flags).value
+        return f, (out_E, out_L, out_flags)
+
+    def query_frames(self, frames, prec="fp16"):
+        arr = (Frame * len(frames))(*frames)
+        _check(lib().niv_query(self._h, arr, len(frames), _prec(prec), _stream()), "niv_query")
+
+    def query(self, pos, nrm, model, prec="fp16", albedo=None, mask=None, extra=(),
+              want_flags=True):
+        """E, L (= albedo * E / pi or None) and flags for one G-buffer."""
+        f, outs = self.frame(pos, nrm, model, albedo=albedo, mask=mask, extra=extra,
+                             want_flags=want_flags)
+        self.query_frames([f], prec)
+        return outs
