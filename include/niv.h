@@ -98,7 +98,10 @@ niv_status niv_prepare(niv_handle *h, const float *params, void *prepared,
  *   out_flags    [count]    uint8   or NULL: bit 0 position outside the box
  *                (clamped), bit 1 non-finite input or zero normal (E set to
  *                0), bit 2 non-finite E.  Masked-off pixels get E = L = 0,
- *                flags 0. */
+ *                flags 0.
+ *   out_inputs   [count][din] float or NULL: the encoded input vector of each
+ *                pixel as fed to the network (grid features, SH, frequency
+ *                code; rounded to the operand precision), for inspection. */
 typedef struct {
     int64_t count;
     const float *pos, *nrm, *albedo;
@@ -107,6 +110,7 @@ typedef struct {
     const void *model;
     float *out_E, *out_L;
     uint8_t *out_flags;
+    float *out_inputs;
 } niv_frame;
 
 /* Evaluates every pixel of `n_frames` frames (Sec. 4.4: per-pixel E(x, n)

@@ -177,6 +177,7 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, n
         a.out_E = fr.out_E;
         a.out_L = fr.out_L;
         a.out_flags = fr.out_flags;
+        a.out_inputs = fr.out_inputs;
         a.model = static_cast<const uint8_t *>(fr.model);
         a.count = fr.count;
         a.grid_off = (uint64_t)L.grid_off;
@@ -186,7 +187,6 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, n
             a.lo[c] = h->m.cfg.aabb_min[c];
             a.hi[c] = h->m.cfg.aabb_max[c];
         }
-        memcpy(a.lv, h->m.lv, sizeof(a.lv));
         hipError_t e = launch_query(h->m, a, prec, stream);
         if (e != hipSuccess) return NIV_ERR_HIP;
     }

@@ -24,19 +24,27 @@ struct LevelConst {
     uint32_t pad;
 };
 
+// Prepared model: [level table, kLevelBytes][operand block][grid latents].
+constexpr int kLevelBytes = kMaxLevels * (int)sizeof(LevelConst);
+static_assert(kLevelBytes % 256 == 0, "level table keeps the operand block aligned");
+
+struct LevelTable {
+    LevelConst lv[kMaxLevels];
+};
+
 struct QueryArgs {
     const float *pos, *nrm, *albedo;
     const uint8_t *mask;
     float *out_E, *out_L;
     uint8_t *out_flags;
-    const uint8_t *model;     // prepared model: operand block, then grid
+    float *out_inputs;        // optional [count][din] encoded input vectors
+    const uint8_t *model;     // prepared model
     int64_t count;
     uint64_t grid_off;        // byte offset of the grid in the prepared model
     uint32_t hash_mask;       // T - 1
     int32_t pad0;
     float extra[4];           // scene variables of the frame
     double lo[3], hi[3];      // box the positions are clamped to
-    LevelConst lv[kMaxLevels];
 };
 
 // Shapes the fused kernels are instantiated for.

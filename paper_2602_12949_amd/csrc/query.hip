@@ -21,6 +21,7 @@
 // accumulator values, after ReLU and rounding, ARE its next B operand: no
 // cross-lane traffic between layers.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include "niv_internal.h"
 
@@ -36,6 +37,13 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+// Scalar bit casts.  They take their operand by value: this compiler reads
+// element 0 when __builtin_bit_cast is applied directly to an element of an
+// ext_vector_type value (v.y, v.z, ...), so vector elements are first copied
+// into a scalar.
+__device__ inline uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ inline float u2f(uint32_t x) { return __builtin_bit_cast(float, x); }
 
 // ---------------------------------------------------------------- precision
 template <int P> struct Prec;
@@ -206,6 +214,11 @@ __global__ void k_prepare_operands(const float *__restrict__ params, uint8_t *__
     }
 }
 
+__global__ void k_prepare_levels(const LevelTable t, LevelConst *__restrict__ out)
+{
+    if (threadIdx.x < kMaxLevels) out[threadIdx.x] = t.lv[threadIdx.x];
+}
+
 template <int P>
 __global__ void k_prepare_grid(const float *__restrict__ params, uint8_t *__restrict__ out,
                                int64_t n_grid)
@@ -255,8 +268,8 @@ __device__ inline f2 load_latent(const uint8_t *grid, uint32_t entry)
 }
 
 // Trilinear blend of one level (Sec. 3.1).  Returns the F = 2 features.
-template <int P>
-__device__ inline f2 encode_level(const LevelConst &lv, const double p[3], uint32_t hmask,
+template <int P, class LV>
+__device__ inline f2 encode_level(const LV &lv, const double p[3], uint32_t hmask,
                                   const uint8_t *grid)
 {
     int32_t ci[3];
@@ -318,8 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint8_t *model = a.model;
-    const uint8_t *grid = model + a.grid_off;
+    const uint8_t *model = a.model + kLevelBytes;   // operand block
+    const uint8_t *grid = a.model + a.grid_off;
 
     // Operand block -> LDS, once per workgroup.
     const uint8_t *wsrc = model;
@@ -356,14 +369,15 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
     for (int64_t chunk = wave_id; chunk < n_chunks; chunk += n_waves) {
         // Re-read the level constants from the argument segment every chunk
         // (scalar loads) instead of keeping 16 levels of them in registers.
-        const LevelConst *lvs = a.lv;
-        asm volatile("" : "+s"(lvs));
+        uint32_t zero = 0;
+        asm volatile("" : "+s"(zero));
+        // constant address space: uniform, read-only, so scalar loads
+        typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
+        ConstLevels lvs = (ConstLevels)(a.model + zero);
         const uint8_t *wop = wsrc;
         if constexpr (!WLDS) {
             // same for operands read from global memory: load them where used
-            uint32_t zero = 0;
-            asm volatile("" : "+s"(zero));
-            wop = a.model + zero;
+            wop = a.model + kLevelBytes + zero;
         }
         const int64_t q = chunk * 64 + lane;
         const bool live = q < a.count;
@@ -407,8 +421,8 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
                     f2 f = encode_level<P>(lvs[l], p, a.hash_mask, grid);
-                    row[2 * l] = __builtin_bit_cast(uint32_t, f.x);
-                    row[2 * l + 1] = __builtin_bit_cast(uint32_t, f.y);
+                    row[2 * l] = f2u(f.x);
+                    row[2 * l + 1] = f2u(f.y);
                 }
             } else {
 #pragma unroll
@@ -423,10 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
             constexpr int base = (P == NIV_FP32) ? 2 * S::L : S::L;
             if constexpr (P == NIV_FP32) {
 #pragma unroll
-                for (int k = 0; k < 16; ++k) row[base + k] = __builtin_bit_cast(uint32_t, sh[k]);
+                for (int k = 0; k < 16; ++k) row[base + k] = f2u(sh[k]);
 #pragma unroll
                 for (int k = 0; k < 16 * S::NEX; ++k)
-                    row[base + 16 + k] = __builtin_bit_cast(uint32_t, gam[k]);
+                    row[base + 16 + k] = f2u(gam[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) row[base + k] = Prec<P>::pack(sh[2 * k], sh[2 * k + 1]);
@@ -438,6 +452,20 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
             // no bias anywhere: an all-zero input gives E = 0
 #pragma unroll
             for (int k = 0; k < S::DIN * O::ES / 4; ++k) row[k] = 0u;
+        }
+        if (a.out_inputs && live) {
+            float *dst = a.out_inputs + q * S::DIN;
+            if constexpr (P == NIV_FP32) {
+#pragma unroll
+                for (int k = 0; k < S::DIN; ++k) dst[k] = u2f(row[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::DIN / 2; ++k) {
+                    f2 v = Prec<P>::unpack(row[k]);
+                    dst[2 * k] = v.x;
+                    dst[2 * k + 1] = v.y;
+                }
+            }
         }
         // LDS accesses of one wave complete in order; the fence keeps the
         // compiler from moving the operand reads above the row writes.
@@ -458,11 +486,11 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                     const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + O::LANE_DW * g;
 #pragma unroll
                     for (int k = 0; k < S::KLG; k += 4) {
-                        u4 v = *reinterpret_cast<const u4 *>(r + k);
-                        b0[t][k] = __builtin_bit_cast(float, v.x);
-                        b0[t][k + 1] = __builtin_bit_cast(float, v.y);
-                        b0[t][k + 2] = __builtin_bit_cast(float, v.z);
-                        b0[t][k + 3] = __builtin_bit_cast(float, v.w);
+                        f4 v = *reinterpret_cast<const f4 *>(r + k);
+                        b0[t][k] = v.x;
+                        b0[t][k + 1] = v.y;
+                        b0[t][k + 2] = v.z;
+                        b0[t][k + 3] = v.w;
                     }
                 }
 #pragma unroll
@@ -613,7 +641,7 @@ template <int P, class S> OpLayout layout_of()
     using O = Ops<P, S>;
     OpLayout L;
     L.w_bytes = O::W_BYTES;
-    L.grid_off = align256(O::W_BYTES);
+    L.grid_off = kLevelBytes + align256(O::W_BYTES);
     L.total = 0;
     return L;
 }
@@ -637,15 +665,20 @@ static hipError_t prepare_t(const Model &m, const float *params, void *prepared,
 {
     using O = Ops<P, S>;
     uint8_t *out = static_cast<uint8_t *>(prepared);
+    LevelTable lt;
+    memset(&lt, 0, sizeof(lt));
+    for (int l = 0; l < m.cfg.n_levels; ++l) lt.lv[l] = m.lv[l];
+    hipLaunchKernelGGL(k_prepare_levels, dim3(1), dim3(64), 0, st, lt,
+                       reinterpret_cast<LevelConst *>(out));
     int threads = O::N_OPS * 64;
     hipLaunchKernelGGL((k_prepare_operands<P, S>), dim3((threads + 255) / 256), dim3(256), 0, st,
-                       params, out, m.n_grid_values, m.cfg.n_out);
+                       params, out + kLevelBytes, m.n_grid_values, m.cfg.n_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int64_t blocks = (m.n_grid_values + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((k_prepare_grid<P>), dim3((unsigned)blocks), dim3(256), 0, st, params,
-                       out + align256(O::W_BYTES), m.n_grid_values);
+                       out + kLevelBytes + align256(O::W_BYTES), m.n_grid_values);
     return hipGetLastError();
 }
 

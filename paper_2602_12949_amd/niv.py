@@ -37,7 +37,8 @@ class Frame(C.Structure):
     _fields_ = [("count", C.c_int64), ("pos", C.c_void_p), ("nrm", C.c_void_p),
                 ("albedo", C.c_void_p), ("mask", C.c_void_p),
                 ("extra_values", C.c_float * 4), ("model", C.c_void_p),
-                ("out_E", C.c_void_p), ("out_L", C.c_void_p), ("out_flags", C.c_void_p)]
+                ("out_E", C.c_void_p), ("out_L", C.c_void_p), ("out_flags", C.c_void_p),
+                ("out_inputs", C.c_void_p)]
 
 
 _lib = None
@@ -164,7 +165,7 @@ class NIV:
         return out
 
     def frame(self, pos, nrm, model, albedo=None, mask=None, extra=(), out_E=None, out_L=None,
-              out_flags=None, want_L=True, want_flags=True):
+              out_flags=None, want_L=True, want_flags=True, out_inputs=None):
         """Builds a niv_frame (and the output tensors) for one G-buffer."""
         n = pos.numel() // 3
         dev = pos.device
@@ -189,16 +190,27 @@ class NIV:
         f.out_E = _ptr(out_E).value
         f.out_L = _ptr(out_L).value
         f.out_flags = _ptr(out_flags).value
+        f.out_inputs = _ptr(out_inputs).value
         return f, (out_E, out_L, out_flags)
 
     def query_frames(self, frames, prec="fp16"):
         arr = (Frame * len(frames))(*frames)
         _check(lib().niv_query(self._h, arr, len(frames), _prec(prec), _stream()), "niv_query")
 
+    @property
+    def input_dim(self):
+        c = self.cfg
+        return c["n_levels"] * c["n_features"] + c["sh_bands"] ** 2 + c["n_extra"] * 2 * c["extra_bands"]
+
     def query(self, pos, nrm, model, prec="fp16", albedo=None, mask=None, extra=(),
-              want_flags=True):
-        """E, L (= albedo * E / pi or None) and flags for one G-buffer."""
+              want_flags=True, want_inputs=False):
+        """E, L (= albedo * E / pi or None) and flags (and the encoded inputs if
+        asked) for one G-buffer."""
+        inputs = None
+        if want_inputs:
+            inputs = torch.empty((pos.numel() // 3, self.input_dim), dtype=torch.float32,
+                                 device=pos.device)
         f, outs = self.frame(pos, nrm, model, albedo=albedo, mask=mask, extra=extra,
-                             want_flags=want_flags)
+                             want_flags=want_flags, out_inputs=inputs)
         self.query_frames([f], prec)
-        return outs
+        return outs + (inputs,) if want_inputs else outs

@@ -85,6 +85,25 @@ def test_unit_cube_parity(unit_cube, prec):
     print(f"  err {err:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_unit_cube_encoded_inputs(unit_cube, prec):
+    """The input vector the kernel feeds the network (grid features, SH) against
+    the oracle's, before any matrix product."""
+    w, oc, pos, nrm, params = unit_cube
+    m = _niv()(w.model_dict())
+    p_d = torch.from_numpy(params).to(DEV)
+    prepared = m.prepare(p_d, prec)
+    E, L, fl, x_in = m.query(torch.from_numpy(pos).to(DEV), torch.from_numpy(nrm).to(DEV),
+                             prepared, prec, want_inputs=True)
+    torch.cuda.synchronize()
+    x_in = x_in.cpu().numpy().astype(np.float64)
+    _, _, _, x0 = O.query(oc, round_params(params, prec), pos, nrm, want_x0=True)
+    # the kernel rounds each input to the operand precision
+    tol = {"fp32": 2e-6, "fp16": 2.0 ** -10, "bf16": 2.0 ** -7}[prec]
+    err = np.abs(x_in - x0) / np.maximum(np.abs(x0), 1.0)
+    assert err.max() <= tol, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097])
 def test_ragged_counts(unit_cube, n):
     w, oc, pos, nrm, params = unit_cube
