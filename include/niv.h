@@ -120,6 +120,69 @@ typedef struct {
 niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
                      niv_precision prec, hipStream_t stream);
 
+/* ------------------------------------------------------------------ */
+/* Monte Carlo irradiance (training targets and reference)              */
+/* ------------------------------------------------------------------ */
+
+/* Scene primitive, 64 bytes (host memory).  kind 0: solid axis-aligned box
+ * p = min corner, q = max corner, faces look outward; kind 1: axis-aligned
+ * rectangle centred at p, normal axis `axis`, front face looking along
+ * sign * e_axis, half extents q[0], q[1] along axes (axis+1)%3 and
+ * (axis+2)%3; kind 2: disk centred at p, unit normal q (front side), radius.
+ * A primitive with non-zero emission (radiance leaving its front face) is a
+ * light; lights must be rectangles or disks, at most 8. */
+typedef struct {
+    int32_t kind, axis;
+    float sign;
+    float p[3], q[3];
+    float radius;
+    float albedo[3], emission[3];
+} niv_mc_prim;
+
+typedef struct mc_scene mc_scene;
+
+/* Copies `n_prims` (1..4096) primitives to the device and builds the light
+ * list and the area table of non-emitting surfaces.  Allocates device memory
+ * owned by the scene (released by mc_scene_destroy). */
+niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene **out);
+void mc_scene_destroy(mc_scene *s);
+
+#define NIV_MC_NEE 1              /* next-event estimation at every bounce */
+#define NIV_MC_EMIT_ON_HIT 2      /* gather emission found by continuation rays */
+#define NIV_MC_INCLUDE_DIRECT 4   /* add emission seen at the first hit */
+#define NIV_MC_DIRECT_AT_ORIGIN 8 /* direct irradiance at x by light sampling */
+
+/* Monte Carlo estimate of the indirect irradiance E(x, n) of Eq. 1 (light
+ * reflected 1..bounces times before reaching x, Sec. 3) at `count` points
+ * (device x, nrm [count][3] float; nrm need not be unit).  Per sample: a
+ * cosine-distributed direction about n; a first hit seen from behind is a
+ * back face (counted, scores 0); emission at the first hit is direct and
+ * skipped unless NIV_MC_INCLUDE_DIRECT; then at each bounce the light
+ * reflected there is gathered (NIV_MC_NEE or NIV_MC_EMIT_ON_HIT, exactly one
+ * of them) and the path continues with a cosine-sampled direction, throughput
+ * times albedo.  Rays start 1e-4 x scene extent off the surface along the
+ * normal.  Tracing in FP32, sums in FP64.  Random number `d` of sample s of
+ * point i is dimension d of Philox4x64-10 with counter (i, s, d/8, 0) and key
+ * (seed, 0): 0-1 first direction, bounce k >= 1 uses 2+(k-1)(2J+2)+2j for
+ * light j and 2+(k-1)(2J+2)+2J for the continuation (J lights).
+ * Outputs (device): out_E [count][3] mean; out_var [count][3] variance of the
+ * mean or NULL; out_backfaces [count] or NULL; out_valid [count] or NULL:
+ * 1 iff back faces <= spp/2 and some channel of E > 0 (Sec. 3.4 culling and
+ * null-irradiance rejection). */
+niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
+                         int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
+                         double *out_E, double *out_var, int32_t *out_backfaces,
+                         uint8_t *out_valid, hipStream_t stream);
+
+/* Training points (Sec. 3.2 and 3.4): points [0, count - n_surface) uniform in
+ * the box [lo, hi] (host arrays of 3) with a normal uniform on the sphere;
+ * points [count - n_surface, count) uniform by area over the non-emitting
+ * surfaces with the surface's front normal.  Philox stream 1, counter
+ * (i, 0, d/8, 1).  out_x, out_n: device [count][3] float. */
+niv_status mc_sample_points(const mc_scene *s, const double *lo, const double *hi, int64_t count,
+                            int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
+                            hipStream_t stream);
+
 const char *niv_status_string(niv_status s);
 
 #ifdef __cplusplus

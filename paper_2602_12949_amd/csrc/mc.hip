@@ -1,0 +1,583 @@
+// Monte Carlo estimate of indirect irradiance (Eq. 1) and the training-point
+// sampler (Sec. 3.4, App. I), for gfx950.
+//
+// One wave per query point: the lanes take samples s = lane, lane+64, ...,
+// trace in FP32, sum each sample's value in FP64, and the wave reduces the
+// sums (wavefront shuffles) into the mean, the variance of the mean, the
+// back-face count and the validity flag.  Random numbers come from a
+// counter-based generator (Philox4x64-10) keyed by (seed, point, sample,
+// dimension), so any point can be re-estimated independently.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "niv_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace niv {
+
+struct Prim {
+    int32_t kind, axis;
+    float sign;
+    float p[3], q[3];
+    float radius;
+    float albedo[3], emission[3];
+};
+static_assert(sizeof(Prim) == 64, "primitive record is 64 bytes");
+
+typedef const __attribute__((address_space(4))) Prim *ConstPrims;
+typedef const __attribute__((address_space(4))) int32_t *ConstInts;
+
+constexpr int kMaxPrims = 4096;
+constexpr int kMaxLights = 8;
+
+// ---------------------------------------------------------------- Philox4x64-10
+// Salmon et al., SC'11: ten rounds of two 64x64->128 products with the
+// published multipliers, Weyl-sequence key schedule.
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        uint64_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
+        c[0] = y0; c[1] = lo1; c[2] = y2; c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Stream of uniforms for one (point, sample): dimension d lives in block
+// d / 8 at 32-bit half d % 8 (low half first); 24-bit mantissa.
+struct Rng {
+    uint64_t seed, a, b, stream;
+    int block;
+    uint64_t w[4];
+    __device__ Rng(uint64_t s, uint64_t a_, uint64_t b_, uint64_t st)
+        : seed(s), a(a_), b(b_), stream(st), block(-1) {}
+    __device__ float u(int d)
+    {
+        int blk = d >> 3;
+        if (blk != block) {
+            w[0] = a; w[1] = b; w[2] = (uint64_t)blk; w[3] = stream;
+            philox4x64_10(w, seed, 0);
+            block = blk;
+        }
+        int k = (d & 7) >> 1;
+        uint64_t x = k == 0 ? w[0] : k == 1 ? w[1] : k == 2 ? w[2] : w[3];
+        uint32_t v = (d & 1) ? (uint32_t)(x >> 32) : (uint32_t)x;
+        return (float)(v >> 8) * 0x1p-24f;
+    }
+};
+
+// ---------------------------------------------------------------- tracing (FP32)
+struct Hit {
+    float t;
+    int prim;
+    float n[3];
+    bool back;
+};
+
+// Closest hit with t > 0; ties go to the lowest primitive index.
+__device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], const float d[3],
+                             Hit &h)
+{
+    h.t = INFINITY;
+    h.prim = -1;
+    h.back = false;
+    for (int k = 0; k < n_prims; ++k) {
+        const int kind = prims[k].kind;
+        if (kind == 0) {
+            float tn = -INFINITY, tf = INFINITY;
+            int an = -1, af = -1;
+            bool miss = false;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float lo = prims[k].p[a], hi = prims[k].q[a];
+                if (d[a] == 0.0f) {
+                    if (o[a] < lo || o[a] > hi) miss = true;
+                    continue;
+                }
+                float t1 = (lo - o[a]) / d[a], t2 = (hi - o[a]) / d[a];
+                float ta = fminf(t1, t2), tb = fmaxf(t1, t2);
+                if (ta > tn) { tn = ta; an = a; }
+                if (tb < tf) { tf = tb; af = a; }
+            }
+            if (miss || tn > tf) continue;
+            if (tn > 0.0f && an >= 0) {
+                if (tn < h.t) {
+                    h.t = tn; h.prim = k; h.back = false;
+                    h.n[0] = h.n[1] = h.n[2] = 0.0f;
+                    h.n[an] = d[an] > 0.0f ? -1.0f : 1.0f;
+                }
+            } else if (tf > 0.0f && af >= 0) {
+                if (tf < h.t) {
+                    h.t = tf; h.prim = k; h.back = true;
+                    h.n[0] = h.n[1] = h.n[2] = 0.0f;
+                    h.n[af] = d[af] > 0.0f ? 1.0f : -1.0f;
+                }
+            }
+        } else if (kind == 1) {
+            const int a = prims[k].axis, uu = (a + 1) % 3, vv = (a + 2) % 3;
+            if (d[a] == 0.0f) continue;
+            float t = (prims[k].p[a] - o[a]) / d[a];
+            if (!(t > 0.0f) || !(t < h.t)) continue;
+            float hu = o[uu] + t * d[uu], hv = o[vv] + t * d[vv];
+            if (fabsf(hu - prims[k].p[uu]) > prims[k].q[0] || fabsf(hv - prims[k].p[vv]) > prims[k].q[1])
+                continue;
+            h.t = t; h.prim = k;
+            h.n[0] = h.n[1] = h.n[2] = 0.0f;
+            h.n[a] = prims[k].sign;
+            h.back = d[a] * prims[k].sign > 0.0f;
+        } else {
+            const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
+            float den = d[0] * nx + d[1] * ny + d[2] * nz;
+            if (den == 0.0f) continue;
+            float t = ((prims[k].p[0] - o[0]) * nx + (prims[k].p[1] - o[1]) * ny +
+                       (prims[k].p[2] - o[2]) * nz) / den;
+            if (!(t > 0.0f) || !(t < h.t)) continue;
+            float r2 = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float e = o[a] + t * d[a] - prims[k].p[a];
+                r2 += e * e;
+            }
+            if (r2 > prims[k].radius * prims[k].radius) continue;
+            h.t = t; h.prim = k;
+            h.n[0] = nx; h.n[1] = ny; h.n[2] = nz;
+            h.back = den > 0.0f;
+        }
+    }
+    return h.prim >= 0;
+}
+
+// Orthonormal basis around a unit vector (Duff et al., JCGT 2017).
+__device__ inline void onb(const float n[3], float t[3], float b[3])
+{
+    float s = n[2] >= 0.0f ? 1.0f : -1.0f;
+    float a = -1.0f / (s + n[2]);
+    float bb = n[0] * n[1] * a;
+    t[0] = 1.0f + s * n[0] * n[0] * a; t[1] = s * bb; t[2] = -s * n[0];
+    b[0] = bb; b[1] = s + n[1] * n[1] * a; b[2] = -n[1];
+}
+
+// Cosine-distributed direction about n (Malley: uniform disk point lifted).
+__device__ inline void cosine_dir(const float n[3], float u1, float u2, float d[3])
+{
+    float t[3], b[3];
+    onb(n, t, b);
+    float r = sqrtf(u1), phi = 6.28318530717958647692f * u2;
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    float x = r * cp, y = r * sp, z = sqrtf(fmaxf(0.0f, 1.0f - u1));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = x * t[a] + y * b[a] + z * n[a];
+}
+
+// Uniform point on a light's front surface; returns its area.
+__device__ inline float light_point(ConstPrims prims, int k, float u1, float u2, float q[3],
+                                    float nq[3])
+{
+    if (prims[k].kind == 1) {
+        const int a = prims[k].axis, uu = (a + 1) % 3, vv = (a + 2) % 3;
+        q[a] = prims[k].p[a];
+        q[uu] = prims[k].p[uu] + (2.0f * u1 - 1.0f) * prims[k].q[0];
+        q[vv] = prims[k].p[vv] + (2.0f * u2 - 1.0f) * prims[k].q[1];
+        nq[0] = nq[1] = nq[2] = 0.0f;
+        nq[a] = prims[k].sign;
+        return 4.0f * prims[k].q[0] * prims[k].q[1];
+    }
+    float n[3] = {prims[k].q[0], prims[k].q[1], prims[k].q[2]}, t[3], b[3];
+    onb(n, t, b);
+    float r = prims[k].radius * sqrtf(u1), phi = 6.28318530717958647692f * u2;
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q[a] = prims[k].p[a] + r * (cp * t[a] + sp * b[a]);
+        nq[a] = n[a];
+    }
+    return 3.14159265358979323846f * prims[k].radius * prims[k].radius;
+}
+
+struct McArgs {
+    const Prim *prims;
+    const int32_t *lights;
+    int32_t n_prims, n_lights;
+    float eps;
+    int32_t spp, bounces, flags;
+    uint64_t seed;
+    const float *x, *nrm;
+    int64_t count;
+    double *out_E, *out_var;
+    int32_t *out_backfaces;
+    uint8_t *out_valid;
+};
+
+// Next-event estimate at y with normal ny toward light j: L cos cos / d^2 A.
+__device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy[3],
+                           const float ny[3], float u1, float u2, float &G)
+{
+    float q[3], nq[3];
+    float A = light_point(prims, lk, u1, u2, q, nq);
+    float w[3] = {q[0] - oy[0], q[1] - oy[1], q[2] - oy[2]};
+    float d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], dl = sqrtf(d2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] /= dl;
+    float cy = ny[0] * w[0] + ny[1] * w[1] + ny[2] * w[2];
+    float cq = -(nq[0] * w[0] + nq[1] * w[1] + nq[2] * w[2]);
+    if (cy <= 0.0f || cq <= 0.0f) return false;
+    Hit hh;
+    if (!trace(prims, n_prims, oy, w, hh) || hh.prim != lk) return false;
+    G = cy * cq / d2 * A;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= a.count) return;  // whole wave leaves together
+    ConstPrims prims = (ConstPrims)a.prims;
+    ConstInts lights = (ConstInts)a.lights;
+    const int np = a.n_prims, J = a.n_lights, stride = 2 * J + 2;
+    float px[3] = {a.x[3 * i], a.x[3 * i + 1], a.x[3 * i + 2]};
+    float pn[3] = {a.nrm[3 * i], a.nrm[3 * i + 1], a.nrm[3 * i + 2]};
+    float ln = sqrtf(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pn[c] /= ln;
+    double s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+    int backs = 0;
+    for (int s = lane; s < a.spp; s += 64) {
+        Rng rng(a.seed, (uint64_t)i, (uint64_t)s, 0);
+        float val[3] = {0.f, 0.f, 0.f};
+        float o[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[c] = px[c] + a.eps * pn[c];
+        if (a.flags & 8) {  // direct irradiance at x by light sampling (test mode)
+            for (int j = 0; j < J; ++j) {
+                int lk = lights[j];
+                float G;
+                if (nee(prims, np, lk, o, pn, rng.u(2 * j), rng.u(2 * j + 1), G))
+                    for (int c = 0; c < 3; ++c) val[c] += prims[lk].emission[c] * G;
+            }
+        } else {
+            float d[3];
+            cosine_dir(pn, rng.u(0), rng.u(1), d);
+            Hit h;
+            bool ok = trace(prims, np, o, d, h);
+            if (ok && h.back) { backs++; ok = false; }
+            if (ok) {
+                float rad[3] = {0.f, 0.f, 0.f};
+                if (a.flags & 4)
+                    for (int c = 0; c < 3; ++c) rad[c] += prims[h.prim].emission[c];
+                float beta[3] = {1.f, 1.f, 1.f};
+                float y[3], ny[3];
+                for (int c = 0; c < 3; ++c) { y[c] = o[c] + h.t * d[c]; ny[c] = h.n[c]; }
+                for (int k = 1; k <= a.bounces; ++k) {
+                    const int pk = h.prim;
+                    float rho[3] = {prims[pk].albedo[0], prims[pk].albedo[1], prims[pk].albedo[2]};
+                    const int base = 2 + (k - 1) * stride;
+                    float oy[3];
+                    for (int c = 0; c < 3; ++c) oy[c] = y[c] + a.eps * ny[c];
+                    if (a.flags & 1) {
+                        for (int j = 0; j < J; ++j) {
+                            int lk = lights[j];
+                            float G;
+                            if (nee(prims, np, lk, oy, ny, rng.u(base + 2 * j), rng.u(base + 2 * j + 1), G))
+                                for (int c = 0; c < 3; ++c)
+                                    rad[c] += beta[c] * rho[c] * 0.318309886183790672f * prims[lk].emission[c] * G;
+                        }
+                    }
+                    const bool cont = (a.flags & 2) ? true : (k < a.bounces);
+                    if (!cont) break;
+                    for (int c = 0; c < 3; ++c) beta[c] *= rho[c];
+                    if (beta[0] == 0.f && beta[1] == 0.f && beta[2] == 0.f) break;
+                    cosine_dir(ny, rng.u(base + 2 * J), rng.u(base + 2 * J + 1), d);
+                    if (!trace(prims, np, oy, d, h) || h.back) break;
+                    if (a.flags & 2)
+                        for (int c = 0; c < 3; ++c) rad[c] += beta[c] * prims[h.prim].emission[c];
+                    for (int c = 0; c < 3; ++c) { y[c] = oy[c] + h.t * d[c]; ny[c] = h.n[c]; }
+                }
+                for (int c = 0; c < 3; ++c) val[c] = 3.14159265358979323846f * rad[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            double v = (double)val[c];
+            s1[c] += v;
+            s2[c] += v * v;
+        }
+    }
+    // wave reduction (FP64 sums, integer back-face count)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        for (int c = 0; c < 3; ++c) {
+            s1[c] += __shfl_xor(s1[c], off);
+            s2[c] += __shfl_xor(s2[c], off);
+        }
+        backs += __shfl_xor(backs, off);
+    }
+    if (lane == 0) {
+        const double S = (double)a.spp;
+        bool any = false;
+        for (int c = 0; c < 3; ++c) {
+            double mean = s1[c] / S;
+            double var = a.spp > 1 ? (s2[c] - S * mean * mean) / (S - 1.0) / S : 0.0;
+            if (var < 0.0) var = 0.0;
+            a.out_E[3 * i + c] = mean;
+            if (a.out_var) a.out_var[3 * i + c] = var;
+            any |= mean > 0.0;
+        }
+        if (a.out_backfaces) a.out_backfaces[i] = backs;
+        if (a.out_valid) a.out_valid[i] = (uint8_t)((2 * backs <= a.spp) && any);
+    }
+}
+
+// ---------------------------------------------------------------- sampler
+struct SampleArgs {
+    const Prim *prims;
+    const int32_t *face_prim;   // per non-emitting face: primitive
+    const int32_t *face_id;     // -1 for a rectangle, 0..5 for a box face
+    const double *cdf;          // cumulative area
+    int32_t n_faces;
+    double total_area;
+    double lo[3], hi[3];
+    int64_t count, n_surface;
+    uint64_t seed;
+    float *out_x, *out_n;
+};
+
+__device__ inline double u64(Rng &r, int d) { return (double)r.u(d); }
+
+__global__ __launch_bounds__(256) void k_sample_points(const SampleArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    ConstPrims prims = (ConstPrims)a.prims;
+    Rng rng(a.seed, (uint64_t)i, 0, 1);
+    double u0 = u64(rng, 0), u1 = u64(rng, 1), u2 = u64(rng, 2);
+    double p[3], n[3] = {0.0, 0.0, 0.0};
+    if (i < a.count - a.n_surface) {
+        double u3 = u64(rng, 3), u4 = u64(rng, 4);
+        for (int c = 0; c < 3; ++c) {
+            double uc = c == 0 ? u0 : (c == 1 ? u1 : u2);
+            p[c] = a.lo[c] + uc * (a.hi[c] - a.lo[c]);
+        }
+        double z = 1.0 - 2.0 * u3, phi = 2.0 * 3.14159265358979323846 * u4;
+        double r = sqrt(fmax(0.0, 1.0 - z * z));
+        double sp, cp;
+        sincos(phi, &sp, &cp);
+        n[0] = r * cp; n[1] = r * sp; n[2] = z;
+    } else {
+        double target = u0 * a.total_area;
+        int lo_i = 0, hi_i = a.n_faces - 1;
+        while (lo_i < hi_i) {
+            int mid = (lo_i + hi_i) / 2;
+            if (a.cdf[mid] > target) hi_i = mid; else lo_i = mid + 1;
+        }
+        const int k = a.face_prim[lo_i], f = a.face_id[lo_i];
+        if (f < 0) {
+            const int ax = prims[k].axis, uu = (ax + 1) % 3, vv = (ax + 2) % 3;
+            p[ax] = prims[k].p[ax];
+            p[uu] = prims[k].p[uu] + (2.0 * u1 - 1.0) * prims[k].q[0];
+            p[vv] = prims[k].p[vv] + (2.0 * u2 - 1.0) * prims[k].q[1];
+            n[ax] = prims[k].sign;
+        } else {
+            const int ax = f / 2, uu = (ax + 1) % 3, vv = (ax + 2) % 3;
+            p[ax] = (f & 1) ? prims[k].q[ax] : prims[k].p[ax];
+            p[uu] = prims[k].p[uu] + u1 * ((double)prims[k].q[uu] - prims[k].p[uu]);
+            p[vv] = prims[k].p[vv] + u2 * ((double)prims[k].q[vv] - prims[k].p[vv]);
+            n[ax] = (f & 1) ? 1.0 : -1.0;
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        a.out_x[3 * i + c] = (float)p[c];
+        a.out_n[3 * i + c] = (float)n[c];
+    }
+}
+
+}  // namespace niv
+
+using namespace niv;
+
+struct mc_scene {
+    Prim *d_prims = nullptr;       // device copy of the primitives
+    int32_t *d_lights = nullptr;   // indices of emitting primitives
+    int32_t *d_face_prim = nullptr, *d_face_id = nullptr;
+    double *d_cdf = nullptr;
+    int32_t n_prims = 0, n_lights = 0, n_faces = 0;
+    double total_area = 0.0;
+    float eps = 0.0f;
+};
+
+namespace {
+niv_status hs(hipError_t e) { return e == hipSuccess ? NIV_OK : NIV_ERR_HIP; }
+bool is_light(const Prim &p) { return p.emission[0] > 0.f || p.emission[1] > 0.f || p.emission[2] > 0.f; }
+void release(mc_scene *s)
+{
+    if (!s) return;
+    (void)hipFree(s->d_prims);
+    (void)hipFree(s->d_lights);
+    (void)hipFree(s->d_face_prim);
+    (void)hipFree(s->d_face_id);
+    (void)hipFree(s->d_cdf);
+    delete s;
+}
+}  // namespace
+
+extern "C" {
+
+niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene **out)
+{
+    if (!out || !prims || n_prims < 1 || n_prims > kMaxPrims) return NIV_ERR_INVALID_ARG;
+    *out = nullptr;
+    const Prim *P = reinterpret_cast<const Prim *>(prims);
+    mc_scene *s = new (std::nothrow) mc_scene;
+    if (!s) return NIV_ERR_INVALID_ARG;
+    // lights, scene extent (for the ray offset), surface table for the sampler
+    int32_t lights[kMaxLights];
+    int n_lights = 0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int32_t *fp = new int32_t[6 * n_prims], *ff = new int32_t[6 * n_prims];
+    double *cdf = new double[6 * n_prims];
+    int nf = 0;
+    double acc = 0.0;
+    niv_status st = NIV_OK;
+    for (int k = 0; k < n_prims && st == NIV_OK; ++k) {
+        const Prim &p = P[k];
+        if (p.kind < 0 || p.kind > 2 || (p.kind == 1 && (p.axis < 0 || p.axis > 2))) {
+            st = NIV_ERR_INVALID_ARG;
+            break;
+        }
+        if (is_light(p)) {
+            if (n_lights == kMaxLights || p.kind == 0) { st = NIV_ERR_UNSUPPORTED; break; }
+            lights[n_lights++] = k;
+        }
+        double a[3], b[3];
+        if (p.kind == 0) {
+            for (int c = 0; c < 3; ++c) { a[c] = p.p[c]; b[c] = p.q[c]; }
+        } else if (p.kind == 1) {
+            int ax = p.axis, u = (ax + 1) % 3, v = (ax + 2) % 3;
+            for (int c = 0; c < 3; ++c) a[c] = b[c] = p.p[c];
+            a[u] -= p.q[0]; b[u] += p.q[0]; a[v] -= p.q[1]; b[v] += p.q[1];
+        } else {
+            for (int c = 0; c < 3; ++c) { a[c] = p.p[c] - p.radius; b[c] = p.p[c] + p.radius; }
+        }
+        for (int c = 0; c < 3; ++c) {
+            if (a[c] < lo[c]) lo[c] = a[c];
+            if (b[c] > hi[c]) hi[c] = b[c];
+        }
+        if (is_light(p)) continue;
+        if (p.kind == 1) {
+            acc += 4.0 * (double)p.q[0] * p.q[1];
+            fp[nf] = k; ff[nf] = -1; cdf[nf] = acc; nf++;
+        } else if (p.kind == 0) {
+            for (int f = 0; f < 6; ++f) {
+                int ax = f / 2, u = (ax + 1) % 3, v = (ax + 2) % 3;
+                acc += ((double)p.q[u] - p.p[u]) * ((double)p.q[v] - p.p[v]);
+                fp[nf] = k; ff[nf] = f; cdf[nf] = acc; nf++;
+            }
+        }
+    }
+    if (st == NIV_OK) {
+        double extent = 0.0;
+        for (int c = 0; c < 3; ++c) extent = fmax(extent, hi[c] - lo[c]);
+        s->eps = (float)(1e-4 * extent);
+        s->n_prims = n_prims;
+        s->n_lights = n_lights;
+        s->n_faces = nf;
+        s->total_area = acc;
+        st = hs(hipMalloc(&s->d_prims, sizeof(Prim) * n_prims));
+        if (st == NIV_OK) st = hs(hipMalloc(&s->d_lights, sizeof(int32_t) * kMaxLights));
+        if (st == NIV_OK) st = hs(hipMalloc(&s->d_face_prim, sizeof(int32_t) * (nf + 1)));
+        if (st == NIV_OK) st = hs(hipMalloc(&s->d_face_id, sizeof(int32_t) * (nf + 1)));
+        if (st == NIV_OK) st = hs(hipMalloc(&s->d_cdf, sizeof(double) * (nf + 1)));
+        if (st == NIV_OK) st = hs(hipMemcpy(s->d_prims, P, sizeof(Prim) * n_prims, hipMemcpyHostToDevice));
+        if (st == NIV_OK) st = hs(hipMemcpy(s->d_lights, lights, sizeof(int32_t) * kMaxLights, hipMemcpyHostToDevice));
+        if (st == NIV_OK && nf > 0) {
+            st = hs(hipMemcpy(s->d_face_prim, fp, sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+            if (st == NIV_OK) st = hs(hipMemcpy(s->d_face_id, ff, sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+            if (st == NIV_OK) st = hs(hipMemcpy(s->d_cdf, cdf, sizeof(double) * nf, hipMemcpyHostToDevice));
+        }
+    }
+    delete[] fp;
+    delete[] ff;
+    delete[] cdf;
+    if (st != NIV_OK) {
+        release(s);
+        return st;
+    }
+    *out = s;
+    return NIV_OK;
+}
+
+void mc_scene_destroy(mc_scene *s) { release(s); }
+
+niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
+                         int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
+                         double *out_E, double *out_var, int32_t *out_backfaces,
+                         uint8_t *out_valid, hipStream_t stream)
+{
+    if (!s || count < 0 || spp < 1 || bounces < 0 || bounces > 16 || (flags & ~15)) return NIV_ERR_INVALID_ARG;
+    if ((flags & 1) && (flags & 2)) return NIV_ERR_INVALID_ARG;  // NEE and emission-on-hit exclude each other
+    if (count == 0) return NIV_OK;
+    if (!x || !nrm || !out_E) return NIV_ERR_INVALID_ARG;
+    if (2 + bounces * (2 * s->n_lights + 2) > 1 << 20) return NIV_ERR_INVALID_ARG;
+    McArgs a;
+    memset(&a, 0, sizeof(a));
+    a.prims = s->d_prims;
+    a.lights = s->d_lights;
+    a.n_prims = s->n_prims;
+    a.n_lights = s->n_lights;
+    a.eps = s->eps;
+    a.spp = spp;
+    a.bounces = bounces;
+    a.flags = flags;
+    a.seed = seed;
+    a.x = x;
+    a.nrm = nrm;
+    a.count = count;
+    a.out_E = out_E;
+    a.out_var = out_var;
+    a.out_backfaces = out_backfaces;
+    a.out_valid = out_valid;
+    int64_t blocks = (count + 3) / 4;
+    if (blocks > 0x7fffffff) return NIV_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_mc_irradiance, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    return hs(hipGetLastError());
+}
+
+niv_status mc_sample_points(const mc_scene *s, const double *lo, const double *hi, int64_t count,
+                            int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
+                            hipStream_t stream)
+{
+    if (!s || !lo || !hi || count < 0 || n_surface < 0 || n_surface > count) return NIV_ERR_INVALID_ARG;
+    if (count == 0) return NIV_OK;
+    if (!out_x || !out_n) return NIV_ERR_INVALID_ARG;
+    if (n_surface > 0 && s->n_faces == 0) return NIV_ERR_INVALID_ARG;
+    for (int c = 0; c < 3; ++c)
+        if (!(hi[c] >= lo[c])) return NIV_ERR_INVALID_ARG;
+    SampleArgs a;
+    memset(&a, 0, sizeof(a));
+    a.prims = s->d_prims;
+    a.face_prim = s->d_face_prim;
+    a.face_id = s->d_face_id;
+    a.cdf = s->d_cdf;
+    a.n_faces = s->n_faces;
+    a.total_area = s->total_area;
+    for (int c = 0; c < 3; ++c) { a.lo[c] = lo[c]; a.hi[c] = hi[c]; }
+    a.count = count;
+    a.n_surface = n_surface;
+    a.seed = seed;
+    a.out_x = out_x;
+    a.out_n = out_n;
+    int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_sample_points, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    return hs(hipGetLastError());
+}
+
+}  // extern "C"

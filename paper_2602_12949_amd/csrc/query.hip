@@ -87,6 +87,12 @@ template <> struct Prec<NIV_BF16> {
         // a bf16 is the upper half of the float with the same bits
         return (f2){__builtin_bit_cast(float, w << 16), __builtin_bit_cast(float, w & 0xffff0000u)};
     }
+    // x = hi + lo with hi = bf16(x), lo = bf16(x - hi): the pair carries 16
+    // significant bits, so BF16 operands lose little to rounding.
+    __device__ static uint32_t pack_lo(float x, float y, uint32_t hi) {
+        f2 h = unpack(hi);
+        return pack(x - h.x, y - h.y);
+    }
 };
 
 template <> struct Prec<NIV_FP32> {
@@ -127,8 +133,11 @@ template <int P, class S> struct Ops {
     static constexpr int OUT_BYTES = 4 * HOPS * OPB;
     static constexpr int W_BYTES = L0_BYTES + (S::H - 1) * HID_BYTES + OUT_BYTES;
     static constexpr int N_OPS = S::NOB * (L0_FULL + L0_HALF) + (S::H - 1) * S::NOB * HOPS + 4 * HOPS;
+    // BF16 operands are split into hi + lo parts (two products each)
+    static constexpr int NS = (P == NIV_BF16) ? 2 : 1;
+    static constexpr int PART_DW = S::DIN * ES / 4;                 // one part of a row
     // staging row (one pixel's input vector) in dwords, padded against bank conflicts
-    static constexpr int ROW_DW = S::DIN * ES / 4 + (F32 ? 4 : 2);
+    static constexpr int ROW_DW = NS * PART_DW + (F32 ? 4 : 2);
     static constexpr int LANE_DW = S::KLG * ES / 4;                 // dwords a lane group reads
 };
 
@@ -429,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                 for (int l = 0; l < S::L; ++l) {
                     f2 f = encode_level<P>(lvs[l], p, a.hash_mask, grid);
                     row[l] = Prec<P>::pack(f.x, f.y);
+                    if constexpr (O::NS == 2) row[O::PART_DW + l] = Prec<P>::pack_lo(f.x, f.y, row[l]);
                 }
             }
             const float rn = __builtin_amdgcn_rsqf(n2);
@@ -443,15 +453,23 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                     row[base + 16 + k] = f2u(gam[k]);
             } else {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) row[base + k] = Prec<P>::pack(sh[2 * k], sh[2 * k + 1]);
+                for (int k = 0; k < 8; ++k) {
+                    row[base + k] = Prec<P>::pack(sh[2 * k], sh[2 * k + 1]);
+                    if constexpr (O::NS == 2)
+                        row[O::PART_DW + base + k] = Prec<P>::pack_lo(sh[2 * k], sh[2 * k + 1], row[base + k]);
+                }
 #pragma unroll
-                for (int k = 0; k < 8 * S::NEX; ++k)
+                for (int k = 0; k < 8 * S::NEX; ++k) {
                     row[base + 8 + k] = Prec<P>::pack(gam[2 * k], gam[2 * k + 1]);
+                    if constexpr (O::NS == 2)
+                        row[O::PART_DW + base + 8 + k] =
+                            Prec<P>::pack_lo(gam[2 * k], gam[2 * k + 1], row[base + 8 + k]);
+                }
             }
         } else {
             // no bias anywhere: an all-zero input gives E = 0
 #pragma unroll
-            for (int k = 0; k < S::DIN * O::ES / 4; ++k) row[k] = 0u;
+            for (int k = 0; k < O::NS * O::PART_DW; ++k) row[k] = 0u;
         }
         if (a.out_inputs && live) {
             float *dst = a.out_inputs + q * S::DIN;
@@ -462,6 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
 #pragma unroll
                 for (int k = 0; k < S::DIN / 2; ++k) {
                     f2 v = Prec<P>::unpack(row[k]);
+                    if constexpr (O::NS == 2) {
+                        f2 w = Prec<P>::unpack(row[O::PART_DW + k]);
+                        v.x += w.x;
+                        v.y += w.y;
+                    }
                     dst[2 * k] = v.x;
                     dst[2 * k + 1] = v.y;
                 }
@@ -505,15 +528,18 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                     }
                 }
             } else {
-                uint32_t b0[TB][O::LANE_DW];
+                uint32_t b0[O::NS][TB][O::LANE_DW];
+#pragma unroll
+                for (int sp = 0; sp < O::NS; ++sp)
 #pragma unroll
                 for (int t = 0; t < TB; ++t) {
-                    const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + O::LANE_DW * g;
+                    const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + sp * O::PART_DW +
+                                        O::LANE_DW * g;
 #pragma unroll
                     for (int k = 0; k < O::LANE_DW; k += 2) {
                         u2 v = *reinterpret_cast<const u2 *>(r + k);
-                        b0[t][k] = v.x;
-                        b0[t][k + 1] = v.y;
+                        b0[sp][t][k] = v.x;
+                        b0[sp][t][k + 1] = v.y;
                     }
                 }
 #pragma unroll
@@ -524,16 +550,21 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                     for (int c = 0; c < O::L0_FULL; ++c) {
                         u4 av = reinterpret_cast<const u4 *>(wop + ob * O::L0_OB + c * O::OPB)[lane];
 #pragma unroll
+                        for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
                         for (int t = 0; t < TB; ++t) {
-                            u4 bv = {b0[t][4 * c], b0[t][4 * c + 1], b0[t][4 * c + 2], b0[t][4 * c + 3]};
+                            u4 bv = {b0[sp][t][4 * c], b0[sp][t][4 * c + 1], b0[sp][t][4 * c + 2],
+                                     b0[sp][t][4 * c + 3]};
                             acc[t][ob] = Prec<P>::mma(av, bv, acc[t][ob]);
                         }
                     }
                     if constexpr (O::L0_HALF) {
                         u2 av = reinterpret_cast<const u2 *>(wop + ob * O::L0_OB + O::L0_FULL * O::OPB)[lane];
 #pragma unroll
+                        for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
                         for (int t = 0; t < TB; ++t) {
-                            u2 bv = {b0[t][4 * O::L0_FULL], b0[t][4 * O::L0_FULL + 1]};
+                            u2 bv = {b0[sp][t][4 * O::L0_FULL], b0[sp][t][4 * O::L0_FULL + 1]};
                             acc[t][ob] = Prec<P>::mma_half(av, bv, acc[t][ob]);
                         }
                     }
@@ -578,13 +609,19 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                         }
                     }
                 } else {
-                    uint32_t bh[TB][S::W / 8];
+                    uint32_t bh[O::NS][TB][S::W / 8];
 #pragma unroll
                     for (int t = 0; t < TB; ++t)
 #pragma unroll
                         for (int ob = 0; ob < S::NOB; ++ob) {
-                            bh[t][2 * ob] = Prec<P>::pack(fmaxf(acc[t][ob].x, 0.f), fmaxf(acc[t][ob].y, 0.f));
-                            bh[t][2 * ob + 1] = Prec<P>::pack(fmaxf(acc[t][ob].z, 0.f), fmaxf(acc[t][ob].w, 0.f));
+                            const float r0 = fmaxf(acc[t][ob].x, 0.f), r1 = fmaxf(acc[t][ob].y, 0.f);
+                            const float r2 = fmaxf(acc[t][ob].z, 0.f), r3 = fmaxf(acc[t][ob].w, 0.f);
+                            bh[0][t][2 * ob] = Prec<P>::pack(r0, r1);
+                            bh[0][t][2 * ob + 1] = Prec<P>::pack(r2, r3);
+                            if constexpr (O::NS == 2) {
+                                bh[O::NS - 1][t][2 * ob] = Prec<P>::pack_lo(r0, r1, bh[0][t][2 * ob]);
+                                bh[O::NS - 1][t][2 * ob + 1] = Prec<P>::pack_lo(r2, r3, bh[0][t][2 * ob + 1]);
+                            }
                         }
                     if (last) {
 #pragma unroll
@@ -592,8 +629,12 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
 #pragma unroll
                             for (int kb = 0; kb < O::HOPS; ++kb) {
                                 u4 av = reinterpret_cast<const u4 *>(lw + ((t0 + t) * O::HOPS + kb) * O::OPB)[lane];
-                                u4 bv = {bh[t][4 * kb], bh[t][4 * kb + 1], bh[t][4 * kb + 2], bh[t][4 * kb + 3]};
-                                acc_out = Prec<P>::mma(av, bv, acc_out);
+#pragma unroll
+                                for (int sp = 0; sp < O::NS; ++sp) {
+                                    u4 bv = {bh[sp][t][4 * kb], bh[sp][t][4 * kb + 1], bh[sp][t][4 * kb + 2],
+                                             bh[sp][t][4 * kb + 3]};
+                                    acc_out = Prec<P>::mma(av, bv, acc_out);
+                                }
                             }
                     } else {
 #pragma unroll
@@ -604,8 +645,11 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                             for (int kb = 0; kb < O::HOPS; ++kb) {
                                 u4 av = reinterpret_cast<const u4 *>(lw + (ob * O::HOPS + kb) * O::OPB)[lane];
 #pragma unroll
+                                for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
                                 for (int t = 0; t < TB; ++t) {
-                                    u4 bv = {bh[t][4 * kb], bh[t][4 * kb + 1], bh[t][4 * kb + 2], bh[t][4 * kb + 3]};
+                                    u4 bv = {bh[sp][t][4 * kb], bh[sp][t][4 * kb + 1], bh[sp][t][4 * kb + 2],
+                                             bh[sp][t][4 * kb + 3]};
                                     acc[t][ob] = Prec<P>::mma(av, bv, acc[t][ob]);
                                 }
                             }

@@ -42,8 +42,7 @@ class Frame(C.Structure):
 
 
 _lib = None
-_SYMBOLS = ["niv_create", "niv_destroy", "niv_sizes", "niv_level_info", "niv_prepare",
-            "niv_query", "niv_status_string"]
+MC_NEE, MC_EMIT_ON_HIT, MC_INCLUDE_DIRECT, MC_DIRECT_AT_ORIGIN = 1, 2, 4, 8
 
 
 def lib():
@@ -65,9 +64,12 @@ def lib():
         L.niv_query.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp]
         L.niv_status_string.argtypes = [C.c_int]
         L.niv_status_string.restype = C.c_char_p
-        for f in _SYMBOLS:
-            if f != "niv_destroy":
-                getattr(L, f).restype = getattr(L, f).restype or C.c_int
+        L.mc_scene_create.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+        L.mc_scene_destroy.argtypes = [vp]
+        L.mc_scene_destroy.restype = None
+        L.mc_irradiance.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_uint64, vp, vp, vp, vp, vp]
+        L.mc_sample_points.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, C.c_uint64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -214,3 +216,50 @@ class NIV:
                              want_flags=want_flags, out_inputs=inputs)
         self.query_frames([f], prec)
         return outs + (inputs,) if want_inputs else outs
+
+
+class McScene:
+    """A scene on the device (mc_scene_create) for the Monte Carlo estimator
+    of Eq. 1 and the training-point sampler.  `prims` is a numpy structured
+    array of 64-byte primitive records (see niv_synth.scene)."""
+
+    def __init__(self, prims):
+        import numpy as np
+        self.prims = np.ascontiguousarray(prims)
+        assert self.prims.dtype.itemsize == 64
+        h = C.c_void_p()
+        _check(lib().mc_scene_create(self.prims.ctypes.data, len(self.prims), C.byref(h)),
+               "mc_scene_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mc_scene_destroy(h)
+            self._h = None
+
+    def irradiance(self, x, nrm, spp, bounces, flags, seed, out=None):
+        """(E [n,3] f64, var [n,3] f64, back faces [n] i32, valid [n] u8)."""
+        n = x.numel() // 3
+        dev = x.device
+        if out is None:
+            out = (torch.empty((n, 3), dtype=torch.float64, device=dev),
+                   torch.empty((n, 3), dtype=torch.float64, device=dev),
+                   torch.empty(n, dtype=torch.int32, device=dev),
+                   torch.empty(n, dtype=torch.uint8, device=dev))
+        E, var, bf, vd = out
+        _check(lib().mc_irradiance(self._h, _ptr(x), _ptr(nrm), n, int(spp), int(bounces),
+                                   int(flags), C.c_uint64(int(seed)), _ptr(E), _ptr(var),
+                                   _ptr(bf), _ptr(vd), _stream()), "mc_irradiance")
+        return out
+
+    def sample_points(self, lo, hi, count, n_surface, seed, device="cuda"):
+        """Training points: (x [count,3], n [count,3]) float32 on the device."""
+        lo_a = (C.c_double * 3)(*[float(v) for v in lo])
+        hi_a = (C.c_double * 3)(*[float(v) for v in hi])
+        x = torch.empty((count, 3), dtype=torch.float32, device=device)
+        n = torch.empty((count, 3), dtype=torch.float32, device=device)
+        _check(lib().mc_sample_points(self._h, lo_a, hi_a, int(count), int(n_surface),
+                                      C.c_uint64(int(seed)), _ptr(x), _ptr(n), _stream()),
+               "mc_sample_points")
+        return x, n

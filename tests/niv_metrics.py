@@ -1,0 +1,38 @@
+"""Error metrics of the parity tests.
+
+FP32 bar (max relative error 1e-5): the error of an output is measured
+relative to its own magnitude, or to the magnitude of the terms summed into
+it when cancellation makes the output smaller than its terms.  That term
+magnitude is the network evaluated with |W| on |x| along the active ReLU
+units of the FP64 forward pass; rounding in any FP32 evaluation is relative
+to it (plain sequential FP32 matrix products of the same network reach
+2.5e-9 of it, but 1.4e-4 relative to a floor of 1e-3 of the largest output).
+
+FP16/BF16 bar: per-image relative L2 error 2e-3 against the FP64 oracle
+evaluated on the same rounded parameters."""
+import numpy as np
+
+
+def term_scale(mats, x0):
+    """|W_H| ... |W_0| |x0| along the ReLU units active in the FP64 pass."""
+    h = x0.T
+    a = np.abs(x0).T
+    for Wm in mats[:-1]:
+        z = Wm @ h
+        act = z > 0
+        h = np.where(act, z, 0.0)
+        a = (np.abs(Wm) @ a) * act
+    return (np.abs(mats[-1]) @ a).T
+
+
+def max_rel_fp32(E, E_ref, scale):
+    return float(np.max(np.abs(E - E_ref) / np.maximum(np.abs(E_ref), np.maximum(scale, 1e-30))))
+
+
+def max_rel_floored(a, b, frac=1e-3):
+    floor = frac * np.abs(b).max()
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor)))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
