@@ -121,6 +121,60 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
                      niv_precision prec, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
+/* Training (Sec. 3.4)                                                  */
+/* ------------------------------------------------------------------ */
+
+/* A batch of training samples (device arrays): x, nrm [count][3] float
+ * position and direction; extra [count][n_extra] scene variables (NULL when
+ * n_extra = 0); target [count][3] float irradiance; valid [count] uint8 or
+ * NULL (0 = sample contributes nothing but stays in the mean). */
+typedef struct {
+    int64_t count;
+    const float *x, *nrm, *extra, *target;
+    const uint8_t *valid;
+} niv_batch;
+
+/* Training state, all device memory owned by the caller: FP32 master
+ * parameters, their gradient, Adam moments (n_params floats each, moments
+ * zero before step 1), the prepared model of the training precision (kept
+ * equal to niv_prepare(params)), scratch of niv_train_sizes bytes (256-byte
+ * aligned) and a scalar receiving the batch loss. */
+typedef struct {
+    float *params, *grads, *adam_m, *adam_v;
+    void *model;
+    void *workspace;
+    int64_t workspace_bytes;
+    float *loss;
+} niv_train_state;
+
+/* Adam hyper-parameters for one update; step is the 1-based iteration. */
+typedef struct {
+    float lr, beta1, beta2, eps;
+    int64_t step;
+} niv_adam;
+
+/* Scratch bytes for batches of up to max_batch samples (FP32 or FP16
+ * training; BF16 is NIV_ERR_UNSUPPORTED). */
+niv_status niv_train_sizes(const niv_handle *h, niv_precision prec, int64_t max_batch,
+                           int64_t *workspace_bytes);
+
+/* Loss and gradient of one batch (Eq. 3): loss = mean over samples and RGB
+ * channels of (E - y)^2 / (E^2 + 0.01), the denominator held constant; the
+ * gradient of every parameter is written to st->grads (overwritten), the
+ * loss to st->loss.  The forward pass uses st->model at `prec` (matrix
+ * products on the matrix cores with FP32 accumulation); gradients are FP32. */
+niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state *st,
+                        niv_precision prec, hipStream_t stream);
+
+/* One Adam update (Kingma & Ba) of every parameter from st->grads. */
+niv_status niv_adam_update(niv_handle *h, const niv_train_state *st, const niv_adam *ad,
+                           hipStream_t stream);
+
+/* niv_backward, niv_adam_update, then niv_prepare of st->model. */
+niv_status niv_train_step(niv_handle *h, const niv_batch *b, const niv_train_state *st,
+                          const niv_adam *ad, niv_precision prec, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
 /* Monte Carlo irradiance (training targets and reference)              */
 /* ------------------------------------------------------------------ */
 

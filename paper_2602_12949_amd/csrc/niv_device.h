@@ -1,0 +1,281 @@
+// Device-side pieces shared by the query and training kernels of libniv:
+// vector types, precision traits, model shapes, the operand layout of a
+// prepared model and the per-level encoding (Sec. 3.1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "niv_internal.h"
+
+namespace niv {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+// Scalar bit casts.  They take their operand by value: this compiler reads
+// element 0 when __builtin_bit_cast is applied directly to an element of an
+// ext_vector_type value (v.y, v.z, ...), so vector elements are first copied
+// into a scalar.
+__device__ inline uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ inline float u2f(uint32_t x) { return __builtin_bit_cast(float, x); }
+
+// ---------------------------------------------------------------- precision
+template <int P> struct Prec;
+
+template <> struct Prec<NIV_FP16> {
+    static constexpr int ES = 2;    // bytes per element
+    static constexpr int EPO = 8;   // elements per lane of a full operand
+    __device__ static f4 mma(u4 a, u4 b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a),
+                                                      __builtin_bit_cast(h8, b), c, 0, 0, 0);
+    }
+    __device__ static f4 mma_half(u2 a, u2 b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a),
+                                                     __builtin_bit_cast(h4, b), c, 0, 0, 0);
+    }
+    __device__ static uint32_t pack(float x, float y) {
+        h2 v = __builtin_convertvector((f2){x, y}, h2);
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    __device__ static f2 unpack(uint32_t w) {
+        return __builtin_convertvector(__builtin_bit_cast(h2, w), f2);
+    }
+};
+
+template <> struct Prec<NIV_BF16> {
+    static constexpr int ES = 2;
+    static constexpr int EPO = 8;
+    __device__ static f4 mma(u4 a, u4 b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                       __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+    }
+    __device__ static f4 mma_half(u2 a, u2 b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a),
+                                                         __builtin_bit_cast(s4, b), c, 0, 0, 0);
+    }
+    __device__ static uint32_t pack(float x, float y) {
+        bf2 v = __builtin_convertvector((f2){x, y}, bf2);
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    __device__ static f2 unpack(uint32_t w) {
+        // a bf16 is the upper half of the float with the same bits
+        return (f2){__builtin_bit_cast(float, w << 16), __builtin_bit_cast(float, w & 0xffff0000u)};
+    }
+    // x = hi + lo with hi = bf16(x), lo = bf16(x - hi): the pair carries 16
+    // significant bits, so BF16 operands lose little to rounding.
+    __device__ static uint32_t pack_lo(float x, float y, uint32_t hi) {
+        f2 h = unpack(hi);
+        return pack(x - h.x, y - h.y);
+    }
+};
+
+template <> struct Prec<NIV_FP32> {
+    static constexpr int ES = 4;
+    static constexpr int EPO = 1;
+    __device__ static f4 mma1(float a, float b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// ---------------------------------------------------------------- shapes
+template <int L_, int NEX_, int W_, int H_> struct Shape {
+    static constexpr int L = L_, NEX = NEX_, W = W_, H = H_;
+    static constexpr int DIN = 2 * L + 16 + 16 * NEX;  // F = 2, 16 SH, 16 per variable
+    static constexpr int KLG = DIN / 4;                // input slots per lane group
+    static constexpr int NOB = W / 16;                 // 16-row output blocks
+    static_assert(DIN % 16 == 0, "input width must be a multiple of 16");
+    static_assert(L % 4 == 0 && W % 32 == 0, "shape");
+};
+
+using ShapeUnitCube = Shape<8, 0, 64, 2>;
+using ShapeRoom = Shape<16, 0, 64, 3>;
+using ShapeWide6D = Shape<16, 1, 128, 4>;
+
+// Byte layout of the operand block of a prepared model.
+template <int P, class S> struct Ops {
+    static constexpr bool F32 = (P == NIV_FP32);
+    static constexpr int ES = F32 ? 4 : 2;
+    static constexpr int EPO = F32 ? 1 : 8;
+    static constexpr int OPB = 64 * EPO * ES;                       // full operand
+    static constexpr int OPS = 64 * 4 * ES;                         // half-depth operand
+    static constexpr int L0_FULL = F32 ? S::KLG : S::KLG / 8;       // per output block
+    static constexpr int L0_HALF = F32 ? 0 : (S::KLG % 8) / 4;
+    static constexpr int L0_OB = L0_FULL * OPB + L0_HALF * OPS;    // bytes per output block
+    static constexpr int L0_BYTES = S::NOB * L0_OB;
+    static constexpr int HOPS = F32 ? S::W / 4 : S::W / 32;         // operands per block row
+    static constexpr int HID_BYTES = S::NOB * HOPS * OPB;
+    static constexpr int OUT_BYTES = 4 * HOPS * OPB;
+    static constexpr int W_BYTES = L0_BYTES + (S::H - 1) * HID_BYTES + OUT_BYTES;
+    static constexpr int N_OPS = S::NOB * (L0_FULL + L0_HALF) + (S::H - 1) * S::NOB * HOPS + 4 * HOPS;
+    // BF16 operands are split into hi + lo parts (two products each)
+    static constexpr int NS = (P == NIV_BF16) ? 2 : 1;
+    static constexpr int PART_DW = S::DIN * ES / 4;                 // one part of a row
+    // staging row (one pixel's input vector) in dwords, padded against bank conflicts
+    static constexpr int ROW_DW = NS * PART_DW + (F32 ? 4 : 2);
+    static constexpr int LANE_DW = S::KLG * ES / 4;                 // dwords a lane group reads
+};
+
+__host__ __device__ constexpr int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// ---------------------------------------------------------------- prepare
+// Source parameter index of element `e` of lane `lane` of operand `op`, or -1
+// for a zero.  Parameters: [grid][W_0 (W x DIN)][W_1..W_{H-1} (W x W)][W_H (3 x W)].
+template <int P, class S>
+__device__ int64_t operand_source(int op, int lane, int e, int64_t n_grid, int n_out)
+{
+    using O = Ops<P, S>;
+    const int i = lane & 15, g = lane >> 4;
+    const int64_t w0 = n_grid;
+    const int64_t wh = w0 + (int64_t)S::W * S::DIN;
+    const int64_t wo = wh + (int64_t)(S::H - 1) * S::W * S::W;
+    const int n0 = S::NOB * (O::L0_FULL + O::L0_HALF);
+    const int nh = (S::H - 1) * S::NOB * O::HOPS;
+    if (op < n0) {  // layer 0: [ob][chunk]
+        int ob = op / (O::L0_FULL + O::L0_HALF), c = op % (O::L0_FULL + O::L0_HALF);
+        int slot = O::F32 ? c : (c < O::L0_FULL ? c * 8 + e : O::L0_FULL * 8 + e);
+        int row = 16 * ob + i, col = S::KLG * g + slot;
+        return w0 + (int64_t)row * S::DIN + col;
+    }
+    op -= n0;
+    int col;
+    auto hidden_col = [&](int kb) {
+        return O::F32 ? 16 * (kb / 4) + 4 * g + (kb % 4)
+                      : 16 * (2 * kb + e / 4) + 4 * g + (e % 4);
+    };
+    if (op < nh) {  // hidden layers: [layer][ob][kb]
+        int layer = op / (S::NOB * O::HOPS);
+        int r = op % (S::NOB * O::HOPS);
+        int ob = r / O::HOPS, kb = r % O::HOPS;
+        col = hidden_col(kb);
+        int row = 16 * ob + i;
+        return wh + (int64_t)layer * S::W * S::W + (int64_t)row * S::W + col;
+    }
+    op -= nh;  // output layer: [tile][kb]; tile t occupies rows 4t..4t+n_out-1
+    int t = op / O::HOPS, kb = op % O::HOPS;
+    col = hidden_col(kb);
+    if ((i >> 2) != t || (i & 3) >= n_out) return -1;
+    return wo + (int64_t)(i & 3) * S::W + col;
+}
+
+// Byte offset and element count of operand `op`.
+template <int P, class S>
+__device__ void operand_place(int op, int64_t *off, int *n_elem)
+{
+    using O = Ops<P, S>;
+    const int n0 = S::NOB * (O::L0_FULL + O::L0_HALF);
+    if (op < n0) {
+        int ob = op / (O::L0_FULL + O::L0_HALF), c = op % (O::L0_FULL + O::L0_HALF);
+        *off = (int64_t)ob * O::L0_OB + (int64_t)c * O::OPB;
+        *n_elem = (c < O::L0_FULL) ? O::EPO : 4;
+        return;
+    }
+    *off = O::L0_BYTES + (int64_t)(op - n0) * O::OPB;
+    *n_elem = O::EPO;
+}
+
+// ---------------------------------------------------------------- encoding
+// Real SH of degree <= 3 with the Condon-Shortley phase, Cartesian form of
+// the unit normal (x, y, z); index l^2 + l + m.
+__device__ inline void sh16(float x, float y, float z, float *o)
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    o[0] = 0.28209479177387814f;
+    o[1] = -0.4886025119029199f * y;
+    o[2] = 0.4886025119029199f * z;
+    o[3] = -0.4886025119029199f * x;
+    o[4] = 1.0925484305920792f * x * y;
+    o[5] = -1.0925484305920792f * y * z;
+    o[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+    o[7] = -1.0925484305920792f * x * z;
+    o[8] = 0.5462742152960396f * (xx - yy);
+    o[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+    o[10] = 2.890611442640554f * x * y * z;
+    o[11] = -0.4570457994644658f * y * (5.0f * zz - 1.0f);
+    o[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+    o[13] = -0.4570457994644658f * x * (5.0f * zz - 1.0f);
+    o[14] = 1.445305721320277f * z * (xx - yy);
+    o[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+template <int P>
+__device__ inline f2 load_latent(const uint8_t *grid, uint32_t entry)
+{
+    if constexpr (P == NIV_FP32) {
+        return reinterpret_cast<const f2 *>(grid)[entry];
+    } else {
+        return Prec<P>::unpack(reinterpret_cast<const uint32_t *>(grid)[entry]);
+    }
+}
+
+// Cell, corner indices (within the whole grid) and trilinear weights of one
+// level (Sec. 3.1).  Corner c = cx + 2cy + 4cz.
+template <class LV>
+__device__ inline void level_corners(const LV &lv, const double p[3], uint32_t hmask,
+                                     uint32_t idx[8], float w[8])
+{
+    int32_t ci[3];
+    float fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+        int32_t c = (int32_t)s;               // s > -1, so truncation = floor clamped at 0
+        c = c < lv.nm1 ? c : lv.nm1;
+        ci[a] = c;
+        fr[a] = (float)(s - (double)c);
+    }
+    if (lv.dense) {
+        uint32_t b = (uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2]) + lv.off;
+        idx[0] = b;           idx[1] = b + 1;
+        idx[2] = b + lv.s1;   idx[3] = b + lv.s1 + 1;
+        idx[4] = b + lv.s2;   idx[5] = b + lv.s2 + 1;
+        idx[6] = b + lv.s2 + lv.s1;  idx[7] = b + lv.s2 + lv.s1 + 1;
+    } else {
+        uint32_t x0 = (uint32_t)ci[0], x1 = x0 + 1;
+        uint32_t y0 = (uint32_t)ci[1] * kPrime1, y1 = y0 + kPrime1;
+        uint32_t z0 = (uint32_t)ci[2] * kPrime2, z1 = z0 + kPrime2;
+        // x < T on every hashed level (checked on the host), so the mask
+        // can be applied to the y/z part alone.
+        uint32_t t00 = (y0 ^ z0) & hmask, t10 = (y1 ^ z0) & hmask;
+        uint32_t t01 = (y0 ^ z1) & hmask, t11 = (y1 ^ z1) & hmask;
+        idx[0] = (x0 ^ t00) + lv.off;  idx[1] = (x1 ^ t00) + lv.off;
+        idx[2] = (x0 ^ t10) + lv.off;  idx[3] = (x1 ^ t10) + lv.off;
+        idx[4] = (x0 ^ t01) + lv.off;  idx[5] = (x1 ^ t01) + lv.off;
+        idx[6] = (x0 ^ t11) + lv.off;  idx[7] = (x1 ^ t11) + lv.off;
+    }
+    const float wx1 = fr[0], wx0 = 1.0f - fr[0];
+    const float wy1 = fr[1], wy0 = 1.0f - fr[1];
+    const float wz1 = fr[2], wz0 = 1.0f - fr[2];
+    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+    w[0] = wx0 * w00; w[1] = wx1 * w00; w[2] = wx0 * w10; w[3] = wx1 * w10;
+    w[4] = wx0 * w01; w[5] = wx1 * w01; w[6] = wx0 * w11; w[7] = wx1 * w11;
+}
+
+// Trilinear blend of one level (Sec. 3.1).  Returns the F = 2 features.
+template <int P, class LV>
+__device__ inline f2 encode_level(const LV &lv, const double p[3], uint32_t hmask,
+                                  const uint8_t *grid)
+{
+    uint32_t idx[8];
+    float w[8];
+    level_corners(lv, p, hmask, idx, w);
+    f2 v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = load_latent<P>(grid, idx[c]);
+    f2 acc = {0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
+        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
+    }
+    return acc;
+}
+
+}  // namespace niv

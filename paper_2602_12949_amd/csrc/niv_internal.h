@@ -45,6 +45,16 @@ struct QueryArgs {
     int32_t pad0;
     float extra[4];           // scene variables of the frame
     double lo[3], hi[3];      // box the positions are clamped to
+    // training forward only (the fused kernel instantiated with TRAIN):
+    const float *extra_ps;    // per-sample scene variables [count][n_extra] or null
+    const float *target;      // [count][3] irradiance targets
+    const uint8_t *valid;     // [count] or null
+    uint8_t *x_save;          // activations, per 64-sample chunk [rows][64]
+    uint32_t *mask_save;      // ReLU masks, per chunk, layer, dword, lane
+    float *dE;                // [count][3] d(loss)/dE without the 1/(3n) factor
+    float *loss;              // device scalar, accumulates the Eq. 3 loss
+    float loss_scale;         // 1/(3n)
+    float loss_eps;           // 0.01 (Eq. 3)
 };
 
 // Shapes the fused kernels are instantiated for.

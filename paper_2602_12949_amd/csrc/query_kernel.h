@@ -1,0 +1,463 @@
+// Fused per-pixel Neural Irradiance Volume query for gfx950 (CDNA4).
+//
+// One launch evaluates E_theta(x, n) for every pixel of a G-buffer (Sec. 4.4)
+// and shades it with albedo * E / pi (Eq. 2):
+//   1. each lane loads one pixel (coalesced) and builds its input vector:
+//      per level the cell, the 8 corner indices (dense or spatially hashed),
+//      8 gathers and a trilinear blend in FP32 (Sec. 3.1); 16 real SH of the
+//      normal; the frequency code of the frame's scene variables (Sec. 6);
+//   2. the wave's 64 input vectors go through a per-wave LDS block into the
+//      operand layout of the matrix cores;
+//   3. the MLP runs on MFMA with FP32 accumulation, four 16-pixel tiles per
+//      wave, weights resident in LDS;
+//   4. each lane writes its pixel's E, albedo * E / pi and flags.
+//
+// Operand layout.  A layer y = W x is computed transposed, D = W * X^T, with
+// the weights as the A operand (16 output rows) and 16 pixels as the B
+// operand columns.  A 16x16 accumulator leaves lane (g = lane/16, j =
+// lane%16) holding rows 4g..4g+3 of pixel j.  The contraction index of the
+// next layer can be permuted freely as long as A and B agree, so the prepared
+// weights are stored with their input columns permuted such that a lane's own
+// accumulator values, after ReLU and rounding, ARE its next B operand: no
+// cross-lane traffic between layers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "niv_internal.h"
+#include "niv_device.h"
+
+namespace niv {
+
+// ---------------------------------------------------------------- fused query
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+
+template <int P, class S, bool WLDS, int TB, bool TRAIN>
+__global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
+{
+    using O = Ops<P, S>;
+    static_assert(!TRAIN || (TB == 4 && P != NIV_BF16), "training: four tiles, FP32 or FP16");
+    // training saves: per 64-sample chunk, X_0 (DIN rows) then X_1..X_H (W rows), each [row][64]
+    constexpr int64_t CHUNK_BYTES = (int64_t)(S::DIN + S::H * S::W) * 64 * O::ES;
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint8_t *model = a.model + kLevelBytes;   // operand block
+    const uint8_t *grid = a.model + a.grid_off;
+
+    // Operand block -> LDS, once per workgroup.
+    const uint8_t *wsrc = model;
+    uint32_t *stage;
+    if constexpr (WLDS) {
+        const u4 *src = reinterpret_cast<const u4 *>(model);
+        u4 *dst = reinterpret_cast<u4 *>(smem);
+        for (int k = threadIdx.x; k < O::W_BYTES / 16; k += kBlock) dst[k] = src[k];
+        __syncthreads();
+        wsrc = smem;
+        stage = reinterpret_cast<uint32_t *>(smem + O::W_BYTES) + wave * 64 * O::ROW_DW;
+    } else {
+        stage = reinterpret_cast<uint32_t *>(smem) + wave * 64 * O::ROW_DW;
+    }
+
+    const int64_t n_chunks = (a.count + 63) / 64;
+    const int64_t wave_id = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int g = lane >> 4, j = lane & 15;
+
+    // Frequency code of the frame's scene variables (uniform over the launch).
+    float gam[16 * (S::NEX > 0 ? S::NEX : 1)];
+    if constexpr (S::NEX > 0) {
+#pragma unroll
+        for (int e = 0; e < S::NEX; ++e)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                float t = a.extra[e] * (float)(1 << k);   // exact scaling by 2^k
+                gam[16 * e + 2 * k] = sinpif(t);
+                gam[16 * e + 2 * k + 1] = cospif(t);
+            }
+    }
+
+    for (int64_t chunk = wave_id; chunk < n_chunks; chunk += n_waves) {
+        // Re-read the level constants from the argument segment every chunk
+        // (scalar loads) instead of keeping 16 levels of them in registers.
+        uint32_t zero = 0;
+        asm volatile("" : "+s"(zero));
+        // constant address space: uniform, read-only, so scalar loads
+        typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
+        ConstLevels lvs = (ConstLevels)(a.model + zero);
+        const uint8_t *wop = wsrc;
+        if constexpr (!WLDS) {
+            // same for operands read from global memory: load them where used
+            wop = a.model + kLevelBytes + zero;
+        }
+        const int64_t q = chunk * 64 + lane;
+        const bool live = q < a.count;
+        // ---- 1. load and encode this lane's pixel
+        float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
+        bool on = false;
+        if (live) {
+            on = a.mask ? (a.mask[q] != 0) : true;
+            if constexpr (TRAIN) on = a.valid ? (a.valid[q] != 0) : true;
+            if (on) {
+                px = a.pos[3 * q]; py = a.pos[3 * q + 1]; pz = a.pos[3 * q + 2];
+                nx = a.nrm[3 * q]; ny = a.nrm[3 * q + 1]; nz = a.nrm[3 * q + 2];
+            }
+        }
+        bool bad = !(__builtin_isfinite(px) && __builtin_isfinite(py) && __builtin_isfinite(pz) &&
+                     __builtin_isfinite(nx) && __builtin_isfinite(ny) && __builtin_isfinite(nz));
+        if constexpr (S::NEX > 0) {
+            if (TRAIN && a.extra_ps) {
+#pragma unroll
+                for (int e = 0; e < S::NEX; ++e) {
+                    const float te = live ? a.extra_ps[q * S::NEX + e] : 0.0f;
+                    bad |= !__builtin_isfinite(te);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        float t = te * (float)(1 << k);
+                        gam[16 * e + 2 * k] = sinpif(t);
+                        gam[16 * e + 2 * k + 1] = cospif(t);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < S::NEX; ++e) bad |= !__builtin_isfinite(a.extra[e]);
+            }
+        }
+        // scale by the largest component first so that tiny or huge normals
+        // normalise without underflow or overflow
+        const float nm = fmaxf(fabsf(nx), fmaxf(fabsf(ny), fabsf(nz)));
+        bad |= !(nm > 0.0f);
+        const float ns = (nm > 0.0f) ? 1.0f / nm : 0.0f;
+        nx *= ns; ny *= ns; nz *= ns;
+        const float n2 = nx * nx + ny * ny + nz * nz;
+        const bool work = on && !bad;
+        uint32_t flags = (on && bad) ? 2u : 0u;
+        double p[3] = {px, py, pz};
+        bool outside = false;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            outside |= (p[c] < a.lo[c]) | (p[c] > a.hi[c]);
+            p[c] = p[c] < a.lo[c] ? a.lo[c] : (p[c] > a.hi[c] ? a.hi[c] : p[c]);
+        }
+        if (work && outside) flags |= 1u;
+
+        uint32_t *row = stage + lane * O::ROW_DW;
+        if (work) {
+            if constexpr (P == NIV_FP32) {
+#pragma unroll
+                for (int l = 0; l < S::L; ++l) {
+                    f2 f = encode_level<P>(lvs[l], p, a.hash_mask, grid);
+                    row[2 * l] = f2u(f.x);
+                    row[2 * l + 1] = f2u(f.y);
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < S::L; ++l) {
+                    f2 f = encode_level<P>(lvs[l], p, a.hash_mask, grid);
+                    row[l] = Prec<P>::pack(f.x, f.y);
+                    if constexpr (O::NS == 2) row[O::PART_DW + l] = Prec<P>::pack_lo(f.x, f.y, row[l]);
+                }
+            }
+            const float rn = __builtin_amdgcn_rsqf(n2);
+            float sh[16];
+            sh16(nx * rn, ny * rn, nz * rn, sh);
+            constexpr int base = (P == NIV_FP32) ? 2 * S::L : S::L;
+            if constexpr (P == NIV_FP32) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) row[base + k] = f2u(sh[k]);
+#pragma unroll
+                for (int k = 0; k < 16 * S::NEX; ++k)
+                    row[base + 16 + k] = f2u(gam[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    row[base + k] = Prec<P>::pack(sh[2 * k], sh[2 * k + 1]);
+                    if constexpr (O::NS == 2)
+                        row[O::PART_DW + base + k] = Prec<P>::pack_lo(sh[2 * k], sh[2 * k + 1], row[base + k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 8 * S::NEX; ++k) {
+                    row[base + 8 + k] = Prec<P>::pack(gam[2 * k], gam[2 * k + 1]);
+                    if constexpr (O::NS == 2)
+                        row[O::PART_DW + base + 8 + k] =
+                            Prec<P>::pack_lo(gam[2 * k], gam[2 * k + 1], row[base + 8 + k]);
+                }
+            }
+        } else {
+            // no bias anywhere: an all-zero input gives E = 0
+#pragma unroll
+            for (int k = 0; k < O::NS * O::PART_DW; ++k) row[k] = 0u;
+        }
+        if (a.out_inputs && live) {
+            float *dst = a.out_inputs + q * S::DIN;
+            if constexpr (P == NIV_FP32) {
+#pragma unroll
+                for (int k = 0; k < S::DIN; ++k) dst[k] = u2f(row[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::DIN / 2; ++k) {
+                    f2 v = Prec<P>::unpack(row[k]);
+                    if constexpr (O::NS == 2) {
+                        f2 w = Prec<P>::unpack(row[O::PART_DW + k]);
+                        v.x += w.x;
+                        v.y += w.y;
+                    }
+                    dst[2 * k] = v.x;
+                    dst[2 * k + 1] = v.y;
+                }
+            }
+        }
+        if constexpr (TRAIN) {
+            uint8_t *xs = a.x_save + chunk * CHUNK_BYTES;
+            if constexpr (P == NIV_FP32) {
+#pragma unroll
+                for (int k = 0; k < S::DIN; ++k)
+                    reinterpret_cast<uint32_t *>(xs)[k * 64 + lane] = row[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::DIN / 2; ++k) {
+                    reinterpret_cast<uint16_t *>(xs)[(2 * k) * 64 + lane] = (uint16_t)(row[k] & 0xffffu);
+                    reinterpret_cast<uint16_t *>(xs)[(2 * k + 1) * 64 + lane] = (uint16_t)(row[k] >> 16);
+                }
+            }
+        }
+        // LDS accesses of one wave complete in order; the fence keeps the
+        // compiler from moving the operand reads above the row writes.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // ---- 2/3. MLP on the matrix cores, TB tiles of 16 pixels at a time
+        f4 acc_out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t0 = 0; t0 < 4; t0 += TB) {
+            f4 acc[TB][S::NOB];
+            // layer 0
+            if constexpr (P == NIV_FP32) {
+                float b0[TB][S::KLG];
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + O::LANE_DW * g;
+#pragma unroll
+                    for (int k = 0; k < S::KLG; k += 4) {
+                        f4 v = *reinterpret_cast<const f4 *>(r + k);
+                        b0[t][k] = v.x;
+                        b0[t][k + 1] = v.y;
+                        b0[t][k + 2] = v.z;
+                        b0[t][k + 3] = v.w;
+                    }
+                }
+#pragma unroll
+                for (int ob = 0; ob < S::NOB; ++ob) {
+#pragma unroll
+                    for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int c = 0; c < S::KLG; ++c) {
+                        float av = reinterpret_cast<const float *>(wop + ob * O::L0_OB + c * O::OPB)[lane];
+#pragma unroll
+                        for (int t = 0; t < TB; ++t) acc[t][ob] = Prec<P>::mma1(av, b0[t][c], acc[t][ob]);
+                    }
+                }
+            } else {
+                uint32_t b0[O::NS][TB][O::LANE_DW];
+#pragma unroll
+                for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + sp * O::PART_DW +
+                                        O::LANE_DW * g;
+#pragma unroll
+                    for (int k = 0; k < O::LANE_DW; k += 2) {
+                        u2 v = *reinterpret_cast<const u2 *>(r + k);
+                        b0[sp][t][k] = v.x;
+                        b0[sp][t][k + 1] = v.y;
+                    }
+                }
+#pragma unroll
+                for (int ob = 0; ob < S::NOB; ++ob) {
+#pragma unroll
+                    for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int c = 0; c < O::L0_FULL; ++c) {
+                        u4 av = reinterpret_cast<const u4 *>(wop + ob * O::L0_OB + c * O::OPB)[lane];
+#pragma unroll
+                        for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
+                        for (int t = 0; t < TB; ++t) {
+                            u4 bv = {b0[sp][t][4 * c], b0[sp][t][4 * c + 1], b0[sp][t][4 * c + 2],
+                                     b0[sp][t][4 * c + 3]};
+                            acc[t][ob] = Prec<P>::mma(av, bv, acc[t][ob]);
+                        }
+                    }
+                    if constexpr (O::L0_HALF) {
+                        u2 av = reinterpret_cast<const u2 *>(wop + ob * O::L0_OB + O::L0_FULL * O::OPB)[lane];
+#pragma unroll
+                        for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
+                        for (int t = 0; t < TB; ++t) {
+                            u2 bv = {b0[sp][t][4 * O::L0_FULL], b0[sp][t][4 * O::L0_FULL + 1]};
+                            acc[t][ob] = Prec<P>::mma_half(av, bv, acc[t][ob]);
+                        }
+                    }
+                }
+            }
+            // hidden layers and output: the accumulator of a lane is its next operand
+#pragma unroll
+            for (int layer = 1; layer <= S::H; ++layer) {
+                const bool last = (layer == S::H);
+                const uint8_t *lw = last ? wop + O::L0_BYTES + (S::H - 1) * O::HID_BYTES
+                                         : wop + O::L0_BYTES + (layer - 1) * O::HID_BYTES;
+                if constexpr (P == NIV_FP32) {
+                    float bh[TB][S::W / 4];
+#pragma unroll
+                    for (int t = 0; t < TB; ++t)
+#pragma unroll
+                        for (int ob = 0; ob < S::NOB; ++ob) {
+                            bh[t][4 * ob] = fmaxf(acc[t][ob].x, 0.f);
+                            bh[t][4 * ob + 1] = fmaxf(acc[t][ob].y, 0.f);
+                            bh[t][4 * ob + 2] = fmaxf(acc[t][ob].z, 0.f);
+                            bh[t][4 * ob + 3] = fmaxf(acc[t][ob].w, 0.f);
+                        }
+                    if constexpr (TRAIN) {
+                        uint32_t *xs = reinterpret_cast<uint32_t *>(a.x_save + chunk * CHUNK_BYTES) +
+                                       (S::DIN + (layer - 1) * S::W) * 64;
+                        uint32_t mk[S::W / 32];
+#pragma unroll
+                        for (int d = 0; d < S::W / 32; ++d) mk[d] = 0u;
+#pragma unroll
+                        for (int t = 0; t < TB; ++t)
+#pragma unroll
+                            for (int ob = 0; ob < S::NOB; ++ob)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const float v = bh[t][4 * ob + r];
+                                    xs[(16 * ob + 4 * g + r) * 64 + 16 * t + j] = f2u(v);
+                                    const int bit = (t * S::NOB + ob) * 4 + r;
+                                    mk[bit >> 5] |= (v > 0.f ? 1u : 0u) << (bit & 31);
+                                }
+#pragma unroll
+                        for (int d = 0; d < S::W / 32; ++d)
+                            a.mask_save[((chunk * S::H + (layer - 1)) * (S::W / 32) + d) * 64 + lane] = mk[d];
+                    }
+                    if (last) {
+#pragma unroll
+                        for (int t = 0; t < TB; ++t)
+#pragma unroll
+                            for (int c = 0; c < O::HOPS; ++c) {
+                                float av = reinterpret_cast<const float *>(lw + ((t0 + t) * O::HOPS + c) * O::OPB)[lane];
+                                acc_out = Prec<P>::mma1(av, bh[t][c], acc_out);
+                            }
+                    } else {
+#pragma unroll
+                        for (int ob = 0; ob < S::NOB; ++ob) {
+#pragma unroll
+                            for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int c = 0; c < O::HOPS; ++c) {
+                                float av = reinterpret_cast<const float *>(lw + (ob * O::HOPS + c) * O::OPB)[lane];
+#pragma unroll
+                                for (int t = 0; t < TB; ++t) acc[t][ob] = Prec<P>::mma1(av, bh[t][c], acc[t][ob]);
+                            }
+                        }
+                    }
+                } else {
+                    uint32_t bh[O::NS][TB][S::W / 8];
+#pragma unroll
+                    for (int t = 0; t < TB; ++t)
+#pragma unroll
+                        for (int ob = 0; ob < S::NOB; ++ob) {
+                            const float r0 = fmaxf(acc[t][ob].x, 0.f), r1 = fmaxf(acc[t][ob].y, 0.f);
+                            const float r2 = fmaxf(acc[t][ob].z, 0.f), r3 = fmaxf(acc[t][ob].w, 0.f);
+                            bh[0][t][2 * ob] = Prec<P>::pack(r0, r1);
+                            bh[0][t][2 * ob + 1] = Prec<P>::pack(r2, r3);
+                            if constexpr (O::NS == 2) {
+                                bh[O::NS - 1][t][2 * ob] = Prec<P>::pack_lo(r0, r1, bh[0][t][2 * ob]);
+                                bh[O::NS - 1][t][2 * ob + 1] = Prec<P>::pack_lo(r2, r3, bh[0][t][2 * ob + 1]);
+                            }
+                        }
+                    if constexpr (TRAIN) {
+                        uint16_t *xs = reinterpret_cast<uint16_t *>(a.x_save + chunk * CHUNK_BYTES) +
+                                       (S::DIN + (layer - 1) * S::W) * 64;
+                        uint32_t mk[S::W / 32];
+#pragma unroll
+                        for (int d = 0; d < S::W / 32; ++d) mk[d] = 0u;
+#pragma unroll
+                        for (int t = 0; t < TB; ++t)
+#pragma unroll
+                            for (int ob = 0; ob < S::NOB; ++ob)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const uint32_t w2 = bh[0][t][2 * ob + (r >> 1)];
+                                    const uint16_t hv = (uint16_t)((r & 1) ? (w2 >> 16) : (w2 & 0xffffu));
+                                    xs[(16 * ob + 4 * g + r) * 64 + 16 * t + j] = hv;
+                                    const int bit = (t * S::NOB + ob) * 4 + r;
+                                    mk[bit >> 5] |= (hv != 0 ? 1u : 0u) << (bit & 31);
+                                }
+#pragma unroll
+                        for (int d = 0; d < S::W / 32; ++d)
+                            a.mask_save[((chunk * S::H + (layer - 1)) * (S::W / 32) + d) * 64 + lane] = mk[d];
+                    }
+                    if (last) {
+#pragma unroll
+                        for (int t = 0; t < TB; ++t)
+#pragma unroll
+                            for (int kb = 0; kb < O::HOPS; ++kb) {
+                                u4 av = reinterpret_cast<const u4 *>(lw + ((t0 + t) * O::HOPS + kb) * O::OPB)[lane];
+#pragma unroll
+                                for (int sp = 0; sp < O::NS; ++sp) {
+                                    u4 bv = {bh[sp][t][4 * kb], bh[sp][t][4 * kb + 1], bh[sp][t][4 * kb + 2],
+                                             bh[sp][t][4 * kb + 3]};
+                                    acc_out = Prec<P>::mma(av, bv, acc_out);
+                                }
+                            }
+                    } else {
+#pragma unroll
+                        for (int ob = 0; ob < S::NOB; ++ob) {
+#pragma unroll
+                            for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int kb = 0; kb < O::HOPS; ++kb) {
+                                u4 av = reinterpret_cast<const u4 *>(lw + (ob * O::HOPS + kb) * O::OPB)[lane];
+#pragma unroll
+                                for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
+                                for (int t = 0; t < TB; ++t) {
+                                    u4 bv = {bh[sp][t][4 * kb], bh[sp][t][4 * kb + 1], bh[sp][t][4 * kb + 2],
+                                             bh[sp][t][4 * kb + 3]};
+                                    acc[t][ob] = Prec<P>::mma(av, bv, acc[t][ob]);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // ---- 4. lane (g, j) holds rows 4g..4g+2 = RGB of pixel 16g + j = this lane's pixel
+        if constexpr (TRAIN) {
+            // Eq. 3: (E - y)^2 / (sg(E^2) + eps); d/dE = 2 (E - y) / (E^2 + eps)
+            float lsum = 0.0f;
+            if (live) {
+                const float Ev[3] = {acc_out.x, acc_out.y, acc_out.z};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float d = 0.0f;
+                    if (work) {
+                        const float r = Ev[c] - a.target[3 * q + c];
+                        const float den = Ev[c] * Ev[c] + a.loss_eps;
+                        d = 2.0f * r / den;
+                        lsum += r * r / den;
+                    }
+                    a.dE[3 * q + c] = d;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off);
+            if (lane == 0) atomicAdd(a.loss, lsum * a.loss_scale);
+            continue;
+        }
+        if (live) {            if (a.out_flags) a.out_flags[q] = (uint8_t)flags;
+        }
+    }
+}
+
+}  // namespace niv

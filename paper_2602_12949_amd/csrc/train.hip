@@ -1,0 +1,624 @@
+// On-GPU training of the Neural Irradiance Volume (Sec. 3.4): Eq. 3 loss,
+// backpropagation through the MLP on the matrix cores, scatter of the
+// encoding gradient into the hash grid, and Adam.
+//
+// A step runs three kernels on the caller's stream:
+//   1. the fused query kernel in training mode: encodes each sample, runs
+//      the MLP, saves every layer's input (per 64-sample chunk, row-major
+//      [neuron][sample], the layout the weight-gradient products read) and
+//      the ReLU masks, and writes d loss / dE (Eq. 3, stop-gradient
+//      denominator) and the loss;
+//   2. k_train_bwd: per chunk, the weight gradients dW_k = G_{k+1} X_k^T on
+//      MFMA (the gradient is transposed through LDS), the input gradients
+//      W_k^T G_{k+1} on MFMA with pre-permuted transposed weights so that
+//      they come out in the same lane layout as the forward activations,
+//      and the scatter of the grid-feature gradients to the 8 corners of
+//      every level with FP32 atomics.  Weight gradients accumulate in LDS
+//      per workgroup and are added to the global gradient once;
+//   3. k_adam over all parameters, then the prepared model is rebuilt.
+// Gradients are carried unscaled through the network and multiplied by
+// 1/(3n) when they are added to the gradient buffer, so FP16 operands do not
+// underflow.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include "niv_internal.h"
+#include "niv_device.h"
+#include "query_kernel.h"
+
+namespace niv {
+
+// ---------------------------------------------------------------- layouts
+template <int P, class S> struct Bwd {
+    static constexpr bool F32 = (P == NIV_FP32);
+    static constexpr int ES = F32 ? 4 : 2;
+    static constexpr int EPO = F32 ? 1 : 8;
+    static constexpr int OPB = 64 * EPO * ES;
+    static constexpr int NIB = S::W / 16;              // row blocks of a hidden input
+    static constexpr int NOB = S::W / 16;
+    static constexpr int GIB = 2 * S::L / 16;          // row blocks of the grid features
+    static constexpr int HOPS = F32 ? S::W / 4 : S::W / 32;
+    static constexpr int OUT_OP = F32 ? 256 : 512;     // K = output channels
+    static constexpr int OUT_BYTES = NIB * OUT_OP;
+    static constexpr int HID_BYTES = NIB * HOPS * OPB;
+    static constexpr int L0_BYTES = GIB * HOPS * OPB;
+    static constexpr int BYTES = OUT_BYTES + (S::H - 1) * HID_BYTES + L0_BYTES;
+    static constexpr int N_OPS = NIB + (S::H - 1) * NIB * HOPS + GIB * HOPS;
+    static constexpr int64_t CHUNK_BYTES = (int64_t)(S::DIN + S::H * S::W) * 64 * ES;
+    static constexpr int NMLP = S::W * S::DIN + (S::H - 1) * S::W * S::W + 3 * S::W;
+    static constexpr int GB_BYTES = S::W * 64 * ES;            // gradient, [neuron][64]
+    static constexpr int DX_BYTES = 64 * 2 * S::L * 4;         // grid-feature gradient, [64][2L]
+    static constexpr int WB_BYTES = (GB_BYTES > DX_BYTES ? GB_BYTES : DX_BYTES) + 3 * 64 * 4;
+    static constexpr int DW_BYTES = (NMLP * 4 + 15) / 16 * 16;
+    static_assert(S::L % 8 == 0, "grid rows come in blocks of 16");
+};
+
+// Source parameter of element e of lane `lane` of backward operand `op`:
+// the output layer's W_H^T (K = channels), then W_k^T for k = 1..H-1, then
+// the grid-feature rows of W_0^T; the K index is permuted to match the lane
+// layout of the gradient (as in the forward).
+template <int P, class S>
+__device__ int64_t bwd_source(int op, int lane, int e, int64_t n_grid)
+{
+    using B = Bwd<P, S>;
+    const int i = lane & 15, g = lane >> 4;
+    const int64_t w0 = n_grid;
+    const int64_t wo = w0 + (int64_t)S::W * S::DIN + (int64_t)(S::H - 1) * S::W * S::W;
+    auto out_neuron = [&](int kb) {
+        return B::F32 ? 16 * (kb / 4) + 4 * g + (kb % 4) : 16 * (2 * kb + e / 4) + 4 * g + (e % 4);
+    };
+    if (op < B::NIB) {
+        const int c = B::F32 ? g : 4 * g + e;
+        if (c >= 3) return -1;
+        return wo + (int64_t)c * S::W + 16 * op + i;
+    }
+    op -= B::NIB;
+    if (op < (S::H - 1) * B::NIB * B::HOPS) {
+        const int k = 1 + op / (B::NIB * B::HOPS);
+        const int r = op % (B::NIB * B::HOPS);
+        const int ib = r / B::HOPS, kb = r % B::HOPS;
+        const int64_t wk = w0 + (int64_t)S::W * S::DIN + (int64_t)(k - 1) * S::W * S::W;
+        return wk + (int64_t)out_neuron(kb) * S::W + 16 * ib + i;
+    }
+    op -= (S::H - 1) * B::NIB * B::HOPS;
+    const int ib = op / B::HOPS, kb = op % B::HOPS;
+    return w0 + (int64_t)out_neuron(kb) * S::DIN + 16 * ib + i;
+}
+
+template <int P, class S>
+__global__ void k_prepare_bwd(const float *__restrict__ params, uint8_t *__restrict__ out,
+                              int64_t n_grid)
+{
+    using B = Bwd<P, S>;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= B::N_OPS * 64) return;
+    const int op = tid / 64, lane = tid % 64;
+    int64_t off;
+    int ne;
+    if (op < B::NIB) {
+        off = (int64_t)op * B::OUT_OP;
+        ne = B::F32 ? 1 : 4;
+    } else {
+        off = B::OUT_BYTES + (int64_t)(op - B::NIB) * B::OPB;
+        ne = B::EPO;
+    }
+    for (int e = 0; e < ne; ++e) {
+        const int64_t src = bwd_source<P, S>(op, lane, e, n_grid);
+        const float v = src >= 0 ? params[src] : 0.0f;
+        if constexpr (B::F32) reinterpret_cast<float *>(out + off)[lane * ne + e] = v;
+        else reinterpret_cast<_Float16 *>(out + off)[lane * ne + e] = (_Float16)v;
+    }
+}
+
+__global__ void k_fill_zero(float *__restrict__ p, int64_t n)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; k < n; k += stride) p[k] = 0.0f;
+}
+
+// ---------------------------------------------------------------- backward
+struct BwdArgs {
+    const uint8_t *bwd;        // backward operands
+    const uint8_t *x_save;
+    const uint32_t *mask_save;
+    const float *dE;           // [n][3], without the 1/(3n) factor
+    const float *x;            // [n][3] sample positions
+    const uint8_t *model;      // prepared model (level table first)
+    float *grads;              // [n_params]
+    int64_t n, n_grid;
+    float loss_scale;
+    uint32_t hash_mask;
+    double lo[3], hi[3];
+};
+
+template <int P> struct Mm;
+template <> struct Mm<NIV_FP16> {
+    __device__ static u4 h8(const float *v) {
+        return (u4){Prec<NIV_FP16>::pack(v[0], v[1]), Prec<NIV_FP16>::pack(v[2], v[3]),
+                    Prec<NIV_FP16>::pack(v[4], v[5]), Prec<NIV_FP16>::pack(v[6], v[7])};
+    }
+};
+
+template <int P, class S>
+__global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
+{
+    using B = Bwd<P, S>;
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    float *dW = reinterpret_cast<float *>(smem);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    uint8_t *wbuf = smem + B::DW_BYTES + wave * B::WB_BYTES;
+    float *debuf = reinterpret_cast<float *>(wbuf + (B::GB_BYTES > B::DX_BYTES ? B::GB_BYTES : B::DX_BYTES));
+    for (int k = threadIdx.x; k < B::NMLP; k += 256) dW[k] = 0.0f;
+    __syncthreads();
+
+    typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
+    const int64_t n_chunks = (a.n + 63) / 64;
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave; chunk < n_chunks; chunk += n_waves) {
+        const int64_t q = chunk * 64 + lane;
+        const bool live = q < a.n;
+        float dEl[3] = {0.f, 0.f, 0.f};
+        if (live) {
+            dEl[0] = a.dE[3 * q]; dEl[1] = a.dE[3 * q + 1]; dEl[2] = a.dE[3 * q + 2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) debuf[c * 64 + lane] = dEl[c];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint8_t *xs = a.x_save + chunk * B::CHUNK_BYTES;
+        const uint8_t *bw = a.bwd;
+
+        // ---- output layer: dW_H[c][n] = sum_px dE[px][c] X_H[n][px]
+        {
+            const int xrow = S::DIN + (S::H - 1) * S::W;
+            const int woff = S::W * S::DIN + (S::H - 1) * S::W * S::W;
+#pragma unroll
+            for (int nb = 0; nb < S::W / 16; ++nb) {
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (B::F32) {
+                    const float *xf = reinterpret_cast<const float *>(xs);
+#pragma unroll
+                    for (int s = 0; s < 16; ++s) {
+                        const float av = j < 3 ? debuf[j * 64 + 4 * s + g] : 0.f;
+                        const float bv = xf[(xrow + 16 * nb + j) * 64 + 4 * s + g];
+                        acc = Prec<NIV_FP32>::mma1(av, bv, acc);
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        u4 av = {0u, 0u, 0u, 0u};
+                        if (j < 3) av = Mm<P>::h8(debuf + j * 64 + 32 * h + 8 * g);
+                        const u4 bv = *reinterpret_cast<const u4 *>(
+                            xs + ((int64_t)(xrow + 16 * nb + j) * 64 + 32 * h + 8 * g) * 2);
+                        acc = Prec<P>::mma(av, bv, acc);
+                    }
+                }
+                if (g == 0) {
+                    atomicAdd(&dW[woff + 0 * S::W + 16 * nb + j], acc.x);
+                    atomicAdd(&dW[woff + 1 * S::W + 16 * nb + j], acc.y);
+                    atomicAdd(&dW[woff + 2 * S::W + 16 * nb + j], acc.z);
+                }
+            }
+        }
+        // ---- gradient w.r.t. x_H = W_H^T dE, lane layout of the forward
+        f4 G[4][B::NOB];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int ib = 0; ib < B::NIB; ++ib) {
+                const f4 z = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (B::F32) {
+                    const float av = reinterpret_cast<const float *>(bw + ib * B::OUT_OP)[lane];
+                    const float bv = g < 3 ? debuf[g * 64 + 16 * t + j] : 0.f;
+                    G[t][ib] = Prec<NIV_FP32>::mma1(av, bv, z);
+                } else {
+                    const u2 av = reinterpret_cast<const u2 *>(bw + ib * B::OUT_OP)[lane];
+                    u2 bv = {0u, 0u};
+                    if (g == 0) {
+                        bv.x = Prec<P>::pack(debuf[16 * t + j], debuf[64 + 16 * t + j]);
+                        bv.y = Prec<P>::pack(debuf[128 + 16 * t + j], 0.f);
+                    }
+                    G[t][ib] = Prec<P>::mma_half(av, bv, z);
+                }
+            }
+        // ---- hidden layers k = H-1 .. 0
+#pragma unroll
+        for (int k = S::H - 1; k >= 0; --k) {
+            // G is d loss / d x_{k+1}; through the ReLU: x_{k+1} > 0
+            uint32_t mk[S::W / 32];
+#pragma unroll
+            for (int d = 0; d < S::W / 32; ++d)
+                mk[d] = a.mask_save[((chunk * S::H + k) * (S::W / 32) + d) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int ob = 0; ob < B::NOB; ++ob) {
+                    const int b0 = (t * B::NOB + ob) * 4;
+                    if (!((mk[(b0 + 0) >> 5] >> ((b0 + 0) & 31)) & 1u)) G[t][ob].x = 0.f;
+                    if (!((mk[(b0 + 1) >> 5] >> ((b0 + 1) & 31)) & 1u)) G[t][ob].y = 0.f;
+                    if (!((mk[(b0 + 2) >> 5] >> ((b0 + 2) & 31)) & 1u)) G[t][ob].z = 0.f;
+                    if (!((mk[(b0 + 3) >> 5] >> ((b0 + 3) & 31)) & 1u)) G[t][ob].w = 0.f;
+                }
+            // transpose G through LDS: [neuron][64 samples]
+            if constexpr (B::F32) {
+                float *gb = reinterpret_cast<float *>(wbuf);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int ob = 0; ob < B::NOB; ++ob) {
+                        gb[(16 * ob + 4 * g + 0) * 64 + 16 * t + j] = G[t][ob].x;
+                        gb[(16 * ob + 4 * g + 1) * 64 + 16 * t + j] = G[t][ob].y;
+                        gb[(16 * ob + 4 * g + 2) * 64 + 16 * t + j] = G[t][ob].z;
+                        gb[(16 * ob + 4 * g + 3) * 64 + 16 * t + j] = G[t][ob].w;
+                    }
+            } else {
+                _Float16 *gb = reinterpret_cast<_Float16 *>(wbuf);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int ob = 0; ob < B::NOB; ++ob) {
+                        gb[(16 * ob + 4 * g + 0) * 64 + 16 * t + j] = (_Float16)G[t][ob].x;
+                        gb[(16 * ob + 4 * g + 1) * 64 + 16 * t + j] = (_Float16)G[t][ob].y;
+                        gb[(16 * ob + 4 * g + 2) * 64 + 16 * t + j] = (_Float16)G[t][ob].z;
+                        gb[(16 * ob + 4 * g + 3) * 64 + 16 * t + j] = (_Float16)G[t][ob].w;
+                    }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // dW_k += G X_k^T over the chunk's 64 samples
+            constexpr int DK_MAX = S::DIN > S::W ? S::DIN : S::W;
+            const int dk = (k == 0) ? S::DIN : S::W;
+            const int xrow = (k == 0) ? 0 : S::DIN + (k - 1) * S::W;
+            const int woff = (k == 0) ? 0 : S::W * S::DIN + (k - 1) * S::W * S::W;
+#pragma unroll
+            for (int ob = 0; ob < B::NOB; ++ob)
+#pragma unroll
+                for (int ib = 0; ib < DK_MAX / 16; ++ib) {
+                    if (ib * 16 >= dk) break;
+                    f4 acc = {0.f, 0.f, 0.f, 0.f};
+                    if constexpr (B::F32) {
+                        const float *gb = reinterpret_cast<const float *>(wbuf);
+                        const float *xf = reinterpret_cast<const float *>(xs);
+#pragma unroll
+                        for (int s = 0; s < 16; ++s) {
+                            const float av = gb[(16 * ob + j) * 64 + 4 * s + g];
+                            const float bv = xf[(int64_t)(xrow + 16 * ib + j) * 64 + 4 * s + g];
+                            acc = Prec<NIV_FP32>::mma1(av, bv, acc);
+                        }
+                    } else {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const u4 av = *reinterpret_cast<const u4 *>(wbuf + ((16 * ob + j) * 64 + 32 * h + 8 * g) * 2);
+                            const u4 bv = *reinterpret_cast<const u4 *>(
+                                xs + ((int64_t)(xrow + 16 * ib + j) * 64 + 32 * h + 8 * g) * 2);
+                            acc = Prec<P>::mma(av, bv, acc);
+                        }
+                    }
+                    float *dst = dW + woff + (16 * ob + 4 * g) * dk + 16 * ib + j;
+                    atomicAdd(dst, acc.x);
+                    atomicAdd(dst + dk, acc.y);
+                    atomicAdd(dst + 2 * dk, acc.z);
+                    atomicAdd(dst + 3 * dk, acc.w);
+                }
+            // d loss / d x_k = W_k^T G (grid rows only for k = 0)
+            const int nib = (k == 0) ? B::GIB : B::NIB;
+            const uint8_t *bk = (k == 0) ? bw + B::OUT_BYTES + (S::H - 1) * B::HID_BYTES
+                                         : bw + B::OUT_BYTES + (k - 1) * B::HID_BYTES;
+            f4 Gn[4][B::NOB];
+            if constexpr (B::F32) {
+#pragma unroll
+                for (int ib = 0; ib < B::NIB; ++ib) {
+                    if (ib >= nib) break;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) Gn[t][ib] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int c = 0; c < B::HOPS; ++c) {
+                        const float av = reinterpret_cast<const float *>(bk + (ib * B::HOPS + c) * B::OPB)[lane];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const f4 gv = G[t][c / 4];
+                            const float bv = (c % 4 == 0) ? gv.x : (c % 4 == 1) ? gv.y : (c % 4 == 2) ? gv.z : gv.w;
+                            Gn[t][ib] = Prec<NIV_FP32>::mma1(av, bv, Gn[t][ib]);
+                        }
+                    }
+                }
+            } else {
+                uint32_t bg[4][S::W / 8];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int ob = 0; ob < B::NOB; ++ob) {
+                        bg[t][2 * ob] = Prec<P>::pack(G[t][ob].x, G[t][ob].y);
+                        bg[t][2 * ob + 1] = Prec<P>::pack(G[t][ob].z, G[t][ob].w);
+                    }
+#pragma unroll
+                for (int ib = 0; ib < B::NIB; ++ib) {
+                    if (ib >= nib) break;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) Gn[t][ib] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kb = 0; kb < B::HOPS; ++kb) {
+                        const u4 av = reinterpret_cast<const u4 *>(bk + (ib * B::HOPS + kb) * B::OPB)[lane];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const u4 bv = {bg[t][4 * kb], bg[t][4 * kb + 1], bg[t][4 * kb + 2], bg[t][4 * kb + 3]};
+                            Gn[t][ib] = Prec<P>::mma(av, bv, Gn[t][ib]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int ob = 0; ob < B::NOB; ++ob) G[t][ob] = Gn[t][ob];
+        }
+        // ---- grid-feature gradients: rows 16ib + 4g + r of sample 16t + j -> [sample][2L]
+        {
+            float *dx = reinterpret_cast<float *>(wbuf);
+            constexpr int NF = 2 * S::L;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int ib = 0; ib < B::GIB; ++ib) {
+                    float *d = dx + (16 * t + j) * NF + 16 * ib + 4 * g;
+                    d[0] = G[t][ib].x; d[1] = G[t][ib].y; d[2] = G[t][ib].z; d[3] = G[t][ib].w;
+                }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const bool scatter = live && (dEl[0] != 0.f || dEl[1] != 0.f || dEl[2] != 0.f);
+            if (scatter) {
+                double p[3] = {a.x[3 * q], a.x[3 * q + 1], a.x[3 * q + 2]};
+                bool finite = true;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    finite &= __builtin_isfinite(p[c]);
+                    p[c] = p[c] < a.lo[c] ? a.lo[c] : (p[c] > a.hi[c] ? a.hi[c] : p[c]);
+                }
+                if (finite) {
+                    ConstLevels lvs = (ConstLevels)a.model;
+                    const float *mine = dx + lane * NF;
+                    for (int l = 0; l < S::L; ++l) {
+                        uint32_t idx[8];
+                        float w[8];
+                        level_corners(lvs[l], p, a.hash_mask, idx, w);
+                        const float g0 = mine[2 * l] * a.loss_scale, g1 = mine[2 * l + 1] * a.loss_scale;
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            atomicAdd(&a.grads[2 * (int64_t)idx[c]], w[c] * g0);
+                            atomicAdd(&a.grads[2 * (int64_t)idx[c] + 1], w[c] * g1);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < B::NMLP; k += 256)
+        atomicAdd(&a.grads[a.n_grid + k], dW[k] * a.loss_scale);
+}
+
+// ---------------------------------------------------------------- Adam
+// Kingma & Ba, Algorithm 1, applied to every parameter; bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; k < n; k += stride) {
+        const float g = gr[k];
+        const float mk = b1 * m[k] + (1.0f - b1) * g;
+        const float vk = b2 * v[k] + (1.0f - b2) * g * g;
+        m[k] = mk;
+        v[k] = vk;
+        p[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------- host side
+struct TrainLayout {
+    int64_t bwd_off, x_off, mask_off, dE_off, total;
+};
+
+template <int P, class S> TrainLayout train_layout_t(int64_t n)
+{
+    using B = Bwd<P, S>;
+    const int64_t nc = (n + 63) / 64;
+    TrainLayout L;
+    L.bwd_off = 0;
+    L.x_off = align256(B::BYTES);
+    L.mask_off = L.x_off + align256(nc * B::CHUNK_BYTES);
+    L.dE_off = L.mask_off + align256(nc * S::H * (S::W / 32) * 64 * 4);
+    L.total = L.dE_off + align256(n * 3 * 4);
+    return L;
+}
+
+template <int P, class S>
+static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train_state &st,
+                             hipStream_t stream)
+{
+    using B = Bwd<P, S>;
+    using O = Ops<P, S>;
+    TrainLayout L = train_layout_t<P, S>(b.count);
+    uint8_t *ws = static_cast<uint8_t *>(st.workspace);
+    // zero the gradient and the loss (a kernel, so the step can be captured)
+    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, stream, st.grads, m.n_params);
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, stream, st.loss, (int64_t)1);
+    hipLaunchKernelGGL((k_prepare_bwd<P, S>), dim3((B::N_OPS * 64 + 255) / 256), dim3(256), 0,
+                       stream, st.params, ws + L.bwd_off, m.n_grid_values);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // 1. forward with saves, loss and d loss / dE
+    QueryArgs a;
+    memset(&a, 0, sizeof(a));
+    a.pos = b.x;
+    a.nrm = b.nrm;
+    a.model = static_cast<const uint8_t *>(st.model);
+    a.count = b.count;
+    a.grid_off = (uint64_t)op_layout(m.kind, (niv_precision)P).grid_off;
+    a.hash_mask = (uint32_t)((int64_t(1) << m.cfg.log2_T) - 1);
+    for (int c = 0; c < 3; ++c) {
+        a.lo[c] = m.cfg.aabb_min[c];
+        a.hi[c] = m.cfg.aabb_max[c];
+    }
+    a.extra_ps = b.extra;
+    a.target = b.target;
+    a.valid = b.valid;
+    a.x_save = ws + L.x_off;
+    a.mask_save = reinterpret_cast<uint32_t *>(ws + L.mask_off);
+    a.dE = reinterpret_cast<float *>(ws + L.dE_off);
+    a.loss = st.loss;
+    a.loss_scale = (float)(1.0 / (3.0 * (double)b.count));
+    a.loss_eps = 0.01f;
+    {
+        auto kern = k_query<P, S, true, 4, true>;
+        const size_t lds = O::W_BYTES + (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4;
+        static int max_blocks = -1, n_cu = 0;
+        if (max_blocks < 0) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            int dev = 0;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+            if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+                return e;
+            int nb = 0;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds)) != hipSuccess)
+                return e;
+            max_blocks = nb > 0 ? nb : 1;
+        }
+        const int64_t n_chunks = (b.count + 63) / 64;
+        int64_t blocks = (n_chunks + kWavesPerBlock - 1) / kWavesPerBlock;
+        blocks = blocks < (int64_t)max_blocks * n_cu ? blocks : (int64_t)max_blocks * n_cu;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(kBlock), lds, stream, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // 2. backward
+    BwdArgs ba;
+    memset(&ba, 0, sizeof(ba));
+    ba.bwd = ws + L.bwd_off;
+    ba.x_save = ws + L.x_off;
+    ba.mask_save = reinterpret_cast<const uint32_t *>(ws + L.mask_off);
+    ba.dE = reinterpret_cast<const float *>(ws + L.dE_off);
+    ba.x = b.x;
+    ba.model = static_cast<const uint8_t *>(st.model);
+    ba.grads = st.grads;
+    ba.n = b.count;
+    ba.n_grid = m.n_grid_values;
+    ba.loss_scale = a.loss_scale;
+    ba.hash_mask = a.hash_mask;
+    for (int c = 0; c < 3; ++c) { ba.lo[c] = a.lo[c]; ba.hi[c] = a.hi[c]; }
+    {
+        auto kern = k_train_bwd<P, S>;
+        const size_t lds = B::DW_BYTES + 4 * (size_t)B::WB_BYTES;
+        static int max_blocks = -1, n_cu = 0;
+        if (max_blocks < 0) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            int dev = 0;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+            if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+                return e;
+            int nb = 0;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, lds)) != hipSuccess)
+                return e;
+            max_blocks = nb > 0 ? nb : 1;
+        }
+        const int64_t n_chunks = (b.count + 63) / 64;
+        int64_t blocks = (n_chunks + 3) / 4;
+        blocks = blocks < (int64_t)max_blocks * n_cu ? blocks : (int64_t)max_blocks * n_cu;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), lds, stream, ba);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static int64_t train_bytes(const Model &m, niv_precision prec, int64_t n)
+{
+    if (m.kind == kUnitCube)
+        return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeUnitCube>(n).total
+                                : train_layout_t<NIV_FP16, ShapeUnitCube>(n).total;
+    return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom>(n).total
+                            : train_layout_t<NIV_FP16, ShapeRoom>(n).total;
+}
+
+}  // namespace niv
+
+using namespace niv;
+
+namespace {
+niv_status hst(hipError_t e) { return e == hipSuccess ? NIV_OK : NIV_ERR_HIP; }
+bool al(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+bool trainable(const Model &m) { return m.kind == kUnitCube || m.kind == kRoom; }
+}  // namespace
+
+extern "C" {
+
+niv_status niv_train_sizes(const niv_handle *h, niv_precision prec, int64_t max_batch,
+                           int64_t *workspace_bytes)
+{
+    if (!h || !workspace_bytes || max_batch < 1) return NIV_ERR_INVALID_ARG;
+    if (prec != NIV_FP32 && prec != NIV_FP16) return prec == NIV_BF16 ? NIV_ERR_UNSUPPORTED : NIV_ERR_INVALID_ARG;
+    if (!trainable(h->m)) return NIV_ERR_UNSUPPORTED;
+    *workspace_bytes = train_bytes(h->m, prec, max_batch);
+    return NIV_OK;
+}
+
+niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state *st,
+                        niv_precision prec, hipStream_t stream)
+{
+    if (!h || !b || !st) return NIV_ERR_INVALID_ARG;
+    if (prec != NIV_FP32 && prec != NIV_FP16) return prec == NIV_BF16 ? NIV_ERR_UNSUPPORTED : NIV_ERR_INVALID_ARG;
+    if (!trainable(h->m)) return NIV_ERR_UNSUPPORTED;
+    if (b->count < 1 || b->count > (int64_t(1) << 30)) return NIV_ERR_INVALID_ARG;
+    if (!b->x || !b->nrm || !b->target || (h->m.cfg.n_extra > 0 && !b->extra)) return NIV_ERR_INVALID_ARG;
+    if (!st->params || !st->grads || !st->model || !st->workspace || !st->loss) return NIV_ERR_INVALID_ARG;
+    if (!al(st->model, 256) || !al(st->workspace, 256) || !al(st->params, 4) || !al(st->grads, 4))
+        return NIV_ERR_INVALID_ARG;
+    if (st->workspace_bytes < train_bytes(h->m, prec, b->count)) return NIV_ERR_WORKSPACE;
+    const Model &m = h->m;
+    hipError_t e;
+    if (m.kind == kUnitCube)
+        e = prec == NIV_FP32 ? backward_t<NIV_FP32, ShapeUnitCube>(m, *b, *st, stream)
+                             : backward_t<NIV_FP16, ShapeUnitCube>(m, *b, *st, stream);
+    else
+        e = prec == NIV_FP32 ? backward_t<NIV_FP32, ShapeRoom>(m, *b, *st, stream)
+                             : backward_t<NIV_FP16, ShapeRoom>(m, *b, *st, stream);
+    return hst(e);
+}
+
+niv_status niv_adam_update(niv_handle *h, const niv_train_state *st, const niv_adam *ad,
+                           hipStream_t stream)
+{
+    if (!h || !st || !ad || !st->params || !st->grads || !st->adam_m || !st->adam_v)
+        return NIV_ERR_INVALID_ARG;
+    if (ad->step < 1 || !(ad->lr >= 0.f) || !(ad->beta1 >= 0.f && ad->beta1 < 1.f) ||
+        !(ad->beta2 >= 0.f && ad->beta2 < 1.f) || !(ad->eps > 0.f))
+        return NIV_ERR_INVALID_ARG;
+    const double bc1 = 1.0 - pow((double)ad->beta1, (double)ad->step);
+    const double bc2 = 1.0 - pow((double)ad->beta2, (double)ad->step);
+    hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, stream, st->params, st->grads, st->adam_m,
+                       st->adam_v, h->m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps, (float)bc1,
+                       (float)bc2);
+    return hst(hipGetLastError());
+}
+
+niv_status niv_train_step(niv_handle *h, const niv_batch *b, const niv_train_state *st,
+                          const niv_adam *ad, niv_precision prec, hipStream_t stream)
+{
+    niv_status s = niv_backward(h, b, st, prec, stream);
+    if (s != NIV_OK) return s;
+    s = niv_adam_update(h, st, ad, stream);
+    if (s != NIV_OK) return s;
+    return niv_prepare(h, st->params, st->model, prec, stream);
+}
+
+}  // extern "C"

@@ -41,6 +41,22 @@ class Frame(C.Structure):
                 ("out_inputs", C.c_void_p)]
 
 
+class Batch(C.Structure):
+    _fields_ = [("count", C.c_int64), ("x", C.c_void_p), ("nrm", C.c_void_p),
+                ("extra", C.c_void_p), ("target", C.c_void_p), ("valid", C.c_void_p)]
+
+
+class TrainState(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("grads", C.c_void_p), ("adam_m", C.c_void_p),
+                ("adam_v", C.c_void_p), ("model", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_int64), ("loss", C.c_void_p)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("step", C.c_int64)]
+
+
 _lib = None
 MC_NEE, MC_EMIT_ON_HIT, MC_INCLUDE_DIRECT, MC_DIRECT_AT_ORIGIN = 1, 2, 4, 8
 
@@ -64,6 +80,11 @@ def lib():
         L.niv_query.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp]
         L.niv_status_string.argtypes = [C.c_int]
         L.niv_status_string.restype = C.c_char_p
+        L.niv_train_sizes.argtypes = [vp, C.c_int, C.c_int64, C.POINTER(C.c_int64)]
+        L.niv_backward.argtypes = [vp, C.POINTER(Batch), C.POINTER(TrainState), C.c_int, vp]
+        L.niv_adam_update.argtypes = [vp, C.POINTER(TrainState), C.POINTER(Adam), vp]
+        L.niv_train_step.argtypes = [vp, C.POINTER(Batch), C.POINTER(TrainState), C.POINTER(Adam),
+                                     C.c_int, vp]
         L.mc_scene_create.argtypes = [vp, C.c_int32, C.POINTER(vp)]
         L.mc_scene_destroy.argtypes = [vp]
         L.mc_scene_destroy.restype = None
@@ -263,3 +284,65 @@ class McScene:
                                       C.c_uint64(int(seed)), _ptr(x), _ptr(n), _stream()),
                "mc_sample_points")
         return x, n
+
+
+class Trainer:
+    """Training state for one model (niv_backward / niv_adam_update /
+    niv_train_step): FP32 master parameters, gradient, Adam moments, the
+    prepared model of the training precision and the scratch buffer, all
+    torch tensors on the device."""
+
+    def __init__(self, niv, params, prec="fp16", max_batch=1 << 18):
+        assert params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()
+        self.niv, self.prec = niv, _prec(prec)
+        dev = params.device
+        self.params = params
+        self.grads = torch.zeros_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.model = niv.prepare(params, self.prec)
+        nb = C.c_int64()
+        _check(lib().niv_train_sizes(niv._h, self.prec, int(max_batch), C.byref(nb)), "niv_train_sizes")
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.max_batch = max_batch
+        self.step_count = 0
+        st = TrainState()
+        st.params, st.grads = params.data_ptr(), self.grads.data_ptr()
+        st.adam_m, st.adam_v = self.m.data_ptr(), self.v.data_ptr()
+        st.model, st.workspace = self.model.data_ptr(), self.workspace.data_ptr()
+        st.workspace_bytes = nb.value
+        st.loss = self.loss.data_ptr()
+        self._st = st
+
+    def _batch(self, x, nrm, target, valid=None, extra=None):
+        n = x.numel() // 3
+        assert n <= self.max_batch
+        b = Batch()
+        b.count = n
+        b.x, b.nrm, b.target = x.data_ptr(), nrm.data_ptr(), target.data_ptr()
+        b.extra = extra.data_ptr() if extra is not None else None
+        b.valid = valid.data_ptr() if valid is not None else None
+        return b
+
+    def backward(self, x, nrm, target, valid=None, extra=None):
+        """Loss (device scalar) and gradient (self.grads) of one batch."""
+        b = self._batch(x, nrm, target, valid, extra)
+        _check(lib().niv_backward(self.niv._h, C.byref(b), C.byref(self._st), self.prec, _stream()),
+               "niv_backward")
+        return self.loss
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=None):
+        self.step_count = step if step is not None else self.step_count + 1
+        ad = Adam(lr, beta1, beta2, eps, self.step_count)
+        _check(lib().niv_adam_update(self.niv._h, C.byref(self._st), C.byref(ad), _stream()),
+               "niv_adam_update")
+
+    def step(self, x, nrm, target, lr, valid=None, extra=None, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One training step; returns the batch loss (device scalar)."""
+        b = self._batch(x, nrm, target, valid, extra)
+        self.step_count += 1
+        ad = Adam(lr, beta1, beta2, eps, self.step_count)
+        _check(lib().niv_train_step(self.niv._h, C.byref(b), C.byref(self._st), C.byref(ad),
+                                    self.prec, _stream()), "niv_train_step")
+        return self.loss
