@@ -101,7 +101,12 @@ niv_status niv_prepare(niv_handle *h, const float *params, void *prepared,
  *                flags 0.
  *   out_inputs   [count][din] float or NULL: the encoded input vector of each
  *                pixel as fed to the network (grid features, SH, frequency
- *                code; rounded to the operand precision), for inspection. */
+ *                code; rounded to the operand precision), for inspection.
+ *   in_flags     [count] uint8 or NULL: caller's request (non-zero) to send a
+ *                pixel to the Monte Carlo fallback (niv_query_fallback only).
+ *   scene        scene of the frame for the fallback, or NULL (no fallback).
+ * count < 2^28. */
+struct mc_scene;
 typedef struct {
     int64_t count;
     const float *pos, *nrm, *albedo;
@@ -111,6 +116,8 @@ typedef struct {
     float *out_E, *out_L;
     uint8_t *out_flags;
     float *out_inputs;
+    const uint8_t *in_flags;
+    const struct mc_scene *scene;
 } niv_frame;
 
 /* Evaluates every pixel of `n_frames` frames (Sec. 4.4: per-pixel E(x, n)
@@ -119,6 +126,57 @@ typedef struct {
  * accumulation (FP32 operands for NIV_FP32). */
 niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
                      niv_precision prec, hipStream_t stream);
+/* Frames may differ in size and each may use its own prepared model of this
+ * shape and precision; up to 16 frames go into one persistent launch whose
+ * workgroups walk the frames' pixel tiles in order. */
+
+/* Monte Carlo fallback for pixels the network should not answer: after the
+ * query, pixels whose flags intersect `flag_mask` (bit 0 outside the box,
+ * bit 2 non-finite E) or whose in_flags are set are appended to a list, and
+ * their E is replaced by mc_irradiance(spp, bounces, mc_flags) of the frame's
+ * scene (L = albedo E / pi); their flags gain bit 3.  Random stream: point
+ * index (frame << 28) | pixel. */
+typedef struct {
+    uint32_t flag_mask;
+    int32_t spp, bounces, mc_flags;
+    uint64_t seed;
+} niv_fallback;
+
+/* Scratch for up to max_flagged fallback pixels per call. */
+niv_status niv_fallback_sizes(const niv_handle *h, int64_t max_flagged, int64_t *workspace_bytes);
+
+/* niv_query of up to 16 frames followed by the Monte Carlo fallback, all
+ * enqueued on `stream` without host synchronisation (pixels beyond the
+ * scratch capacity keep the network's answer).  workspace: device, 256-byte
+ * aligned, niv_fallback_sizes bytes. */
+niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                              niv_precision prec, const niv_fallback *fb, void *workspace,
+                              int64_t workspace_bytes, hipStream_t stream);
+
+/* Times the fused query on these frames for each candidate launch shape
+ * (workgroup of 256 or 512 threads x 1, 2 or all-resident workgroups per
+ * CU; best of 10 launches) and keeps the fastest for later calls at this
+ * precision.  Synchronises `stream`; the frames' outputs are overwritten. */
+typedef struct {
+    int32_t n;
+    int32_t block[8], blocks_per_cu[8];
+    float ms[8];
+    int32_t chosen_block, chosen_blocks_per_cu;
+    float chosen_ms;
+} niv_tune_result;
+niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                        niv_precision prec, hipStream_t stream, niv_tune_result *out);
+
+/* A frame captured as a HIP graph: niv_query (fb == NULL) or
+ * niv_query_fallback with the given buffers, replayed by niv_graph_launch.
+ * Capturing runs the frame once eagerly first.  Buffers must outlive the
+ * graph; their contents may change between launches. */
+typedef struct niv_graph niv_graph;
+niv_status niv_graph_capture(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                             niv_precision prec, const niv_fallback *fb, void *workspace,
+                             int64_t workspace_bytes, niv_graph **out);
+niv_status niv_graph_launch(niv_graph *g, hipStream_t stream);
+void niv_graph_destroy(niv_graph *g);
 
 /* ------------------------------------------------------------------ */
 /* Training (Sec. 3.4)                                                  */
@@ -219,13 +277,14 @@ void mc_scene_destroy(mc_scene *s);
  * point i is dimension d of Philox4x64-10 with counter (i, s, d/8, 0) and key
  * (seed, 0): 0-1 first direction, bounce k >= 1 uses 2+(k-1)(2J+2)+2j for
  * light j and 2+(k-1)(2J+2)+2J for the continuation (J lights).
- * Outputs (device): out_E [count][3] mean; out_var [count][3] variance of the
- * mean or NULL; out_backfaces [count] or NULL; out_valid [count] or NULL:
+ * Outputs (device): out_E [count][3] double mean and/or out_E32 [count][3]
+ * the same rounded to float (either may be NULL, not both); out_var
+ * [count][3] variance of the mean or NULL; out_backfaces [count] or NULL; out_valid [count] or NULL:
  * 1 iff back faces <= spp/2 and some channel of E > 0 (Sec. 3.4 culling and
  * null-irradiance rejection). */
 niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
                          int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
-                         double *out_E, double *out_var, int32_t *out_backfaces,
+                         double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
                          uint8_t *out_valid, hipStream_t stream);
 
 /* Training points (Sec. 3.2 and 3.4): points [0, count - n_surface) uniform in

@@ -1,0 +1,72 @@
+"""Baking a Neural Irradiance Volume on the GPU (Sec. 3.4).
+
+Each step draws training points (80 % uniform in the volume with a uniform
+direction, 20 % on surfaces with the surface normal, Sec. 3.2), estimates
+their indirect irradiance with the Monte Carlo estimator (culling points
+whose first hits are mostly back faces and points with null irradiance),
+and takes one Adam step on the Eq. 3 loss; the learning rate is held, then
+decays exponentially (Sec. 3.4).  This module only sequences library calls;
+every step runs in the library's kernels.
+"""
+import math
+
+import torch
+
+from .niv import McScene, Trainer, MC_NEE
+
+
+def lr_at(step, total, lr0=1e-2, lr1=1e-4, hold=0.2):
+    """lr0 for the first `hold` fraction of the steps, then exponential decay
+    reaching lr1 at the last step."""
+    s1 = int(hold * total)
+    if step <= s1 or total <= s1:
+        return lr0
+    t = min(1.0, (step - s1) / (total - s1))
+    return lr0 * (lr1 / lr0) ** t
+
+
+class Baker:
+    def __init__(self, niv, params, prims, lo, hi, prec="fp16", batch=1 << 18, spp=256,
+                 bounces=3, surface_frac=0.2, seed=0):
+        self.niv = niv
+        self.scene = McScene(prims)
+        self.trainer = Trainer(niv, params, prec, max_batch=batch)
+        self.lo, self.hi = [float(v) for v in lo], [float(v) for v in hi]
+        self.batch, self.spp, self.bounces = batch, spp, bounces
+        self.n_surface = int(round(surface_frac * batch))
+        self.seed = seed
+        dev = params.device
+        self.E = torch.empty((batch, 3), dtype=torch.float32, device=dev)
+        self.valid = torch.empty(batch, dtype=torch.uint8, device=dev)
+
+    def draw(self, step):
+        """Training points and their Monte Carlo targets for one step."""
+        x, n = self.scene.sample_points(self.lo, self.hi, self.batch, self.n_surface,
+                                        seed=(self.seed << 20) + step, device=self.E.device)
+        self.scene.targets(x, n, self.spp, self.bounces, seed=(self.seed << 20) + step + (1 << 19),
+                           flags=MC_NEE, out=(self.E, self.valid))
+        return x, n
+
+    def step(self, step, total):
+        x, n = self.draw(step)
+        return self.trainer.step(x, n, self.E, lr_at(step, total), valid=self.valid)
+
+    def run(self, total, log_every=0, log=print):
+        loss = None
+        for s in range(1, total + 1):
+            loss = self.step(s, total)
+            if log_every and s % log_every == 0:
+                log(f"step {s}: loss {float(loss.item()):.4e} lr {lr_at(s, total):.2e}")
+        return loss
+
+
+def held_out_error(niv, model, prec, x, n, E_ref, valid):
+    """Relative L2 error of the model against reference irradiance on the
+    valid held-out points, and the relative MSE of the paper's loss."""
+    E, _, _ = niv.query(x, n, model, prec, want_flags=True)
+    v = valid.bool()
+    d = (E - E_ref)[v].double()
+    r = E_ref[v].double()
+    rel_l2 = float(torch.linalg.norm(d) / torch.linalg.norm(r))
+    relmse = float((d ** 2 / (r ** 2 + 0.01)).mean())
+    return rel_l2, relmse

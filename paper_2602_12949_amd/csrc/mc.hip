@@ -214,6 +214,7 @@ struct McArgs {
     const float *x, *nrm;
     int64_t count;
     double *out_E, *out_var;
+    float *out_E32;
     int32_t *out_backfaces;
     uint8_t *out_valid;
 };
@@ -237,28 +238,28 @@ __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy
     return true;
 }
 
-__global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
+// Wave-cooperative estimate at one point: lanes take samples lane, lane+64,
+// ...; returns (in every lane) the FP64 sums of the sample values and of
+// their squares, and the back-face count.
+__device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int J, float eps,
+                                const float px[3], const float pn_in[3], int spp, int bounces,
+                                int flags, uint64_t seed, uint64_t point, int lane, double s1[3],
+                                double s2[3], int &backs)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= a.count) return;  // whole wave leaves together
-    ConstPrims prims = (ConstPrims)a.prims;
-    ConstInts lights = (ConstInts)a.lights;
-    const int np = a.n_prims, J = a.n_lights, stride = 2 * J + 2;
-    float px[3] = {a.x[3 * i], a.x[3 * i + 1], a.x[3 * i + 2]};
-    float pn[3] = {a.nrm[3 * i], a.nrm[3 * i + 1], a.nrm[3 * i + 2]};
-    float ln = sqrtf(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+    const int stride = 2 * J + 2;
+    float pn[3] = {pn_in[0], pn_in[1], pn_in[2]};
+    const float ln = sqrtf(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) pn[c] /= ln;
-    double s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
-    int backs = 0;
-    for (int s = lane; s < a.spp; s += 64) {
-        Rng rng(a.seed, (uint64_t)i, (uint64_t)s, 0);
+    for (int c = 0; c < 3; ++c) { s1[c] = 0.0; s2[c] = 0.0; }
+    backs = 0;
+    for (int s = lane; s < spp; s += 64) {
+        Rng rng(seed, point, (uint64_t)s, 0);
         float val[3] = {0.f, 0.f, 0.f};
         float o[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) o[c] = px[c] + a.eps * pn[c];
-        if (a.flags & 8) {  // direct irradiance at x by light sampling (test mode)
+        for (int c = 0; c < 3; ++c) o[c] = px[c] + eps * pn[c];
+        if (flags & 8) {  // direct irradiance at x by light sampling (test mode)
             for (int j = 0; j < J; ++j) {
                 int lk = lights[j];
                 float G;
@@ -273,18 +274,18 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
             if (ok && h.back) { backs++; ok = false; }
             if (ok) {
                 float rad[3] = {0.f, 0.f, 0.f};
-                if (a.flags & 4)
+                if (flags & 4)
                     for (int c = 0; c < 3; ++c) rad[c] += prims[h.prim].emission[c];
                 float beta[3] = {1.f, 1.f, 1.f};
                 float y[3], ny[3];
                 for (int c = 0; c < 3; ++c) { y[c] = o[c] + h.t * d[c]; ny[c] = h.n[c]; }
-                for (int k = 1; k <= a.bounces; ++k) {
+                for (int k = 1; k <= bounces; ++k) {
                     const int pk = h.prim;
                     float rho[3] = {prims[pk].albedo[0], prims[pk].albedo[1], prims[pk].albedo[2]};
                     const int base = 2 + (k - 1) * stride;
                     float oy[3];
-                    for (int c = 0; c < 3; ++c) oy[c] = y[c] + a.eps * ny[c];
-                    if (a.flags & 1) {
+                    for (int c = 0; c < 3; ++c) oy[c] = y[c] + eps * ny[c];
+                    if (flags & 1) {
                         for (int j = 0; j < J; ++j) {
                             int lk = lights[j];
                             float G;
@@ -293,13 +294,13 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
                                     rad[c] += beta[c] * rho[c] * 0.318309886183790672f * prims[lk].emission[c] * G;
                         }
                     }
-                    const bool cont = (a.flags & 2) ? true : (k < a.bounces);
+                    const bool cont = (flags & 2) ? true : (k < bounces);
                     if (!cont) break;
                     for (int c = 0; c < 3; ++c) beta[c] *= rho[c];
                     if (beta[0] == 0.f && beta[1] == 0.f && beta[2] == 0.f) break;
                     cosine_dir(ny, rng.u(base + 2 * J), rng.u(base + 2 * J + 1), d);
                     if (!trace(prims, np, oy, d, h) || h.back) break;
-                    if (a.flags & 2)
+                    if (flags & 2)
                         for (int c = 0; c < 3; ++c) rad[c] += beta[c] * prims[h.prim].emission[c];
                     for (int c = 0; c < 3; ++c) { y[c] = oy[c] + h.t * d[c]; ny[c] = h.n[c]; }
                 }
@@ -321,6 +322,21 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
         }
         backs += __shfl_xor(backs, off);
     }
+}
+
+__global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= a.count) return;  // whole wave leaves together
+    ConstPrims prims = (ConstPrims)a.prims;
+    ConstInts lights = (ConstInts)a.lights;
+    const float px[3] = {a.x[3 * i], a.x[3 * i + 1], a.x[3 * i + 2]};
+    const float pn[3] = {a.nrm[3 * i], a.nrm[3 * i + 1], a.nrm[3 * i + 2]};
+    double s1[3], s2[3];
+    int backs;
+    mc_point(prims, a.n_prims, lights, a.n_lights, a.eps, px, pn, a.spp, a.bounces, a.flags, a.seed,
+             (uint64_t)i, lane, s1, s2, backs);
     if (lane == 0) {
         const double S = (double)a.spp;
         bool any = false;
@@ -328,12 +344,49 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
             double mean = s1[c] / S;
             double var = a.spp > 1 ? (s2[c] - S * mean * mean) / (S - 1.0) / S : 0.0;
             if (var < 0.0) var = 0.0;
-            a.out_E[3 * i + c] = mean;
+            if (a.out_E) a.out_E[3 * i + c] = mean;
+            if (a.out_E32) a.out_E32[3 * i + c] = (float)mean;
             if (a.out_var) a.out_var[3 * i + c] = var;
             any |= mean > 0.0;
         }
         if (a.out_backfaces) a.out_backfaces[i] = backs;
         if (a.out_valid) a.out_valid[i] = (uint8_t)((2 * backs <= a.spp) && any);
+    }
+}
+
+// Monte Carlo replacement of the pixels a query appended to its fallback
+// list (one wave per pixel, persistent grid, length read on the device).
+__global__ __launch_bounds__(256) void k_mc_fallback(const FbArgs a)
+{
+    typedef const __attribute__((address_space(4))) FbArgs *ConstFb;
+    ConstFb ka = (ConstFb)__builtin_amdgcn_kernarg_segment_ptr();
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = *a.count < a.cap ? *a.count : a.cap;
+    for (uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < n; e += gridDim.x * 4) {
+        const uint32_t code = __builtin_amdgcn_readfirstlane(a.list[e]);
+        const int fi = (int)(code >> 28);
+        const int64_t q = code & 0x0fffffffu;
+        if (!ka->f[fi].prims) continue;
+        ConstPrims prims = (ConstPrims)ka->f[fi].prims;
+        ConstInts lights = (ConstInts)ka->f[fi].lights;
+        const float *pos = ka->f[fi].pos, *nrm = ka->f[fi].nrm;
+        const float px[3] = {pos[3 * q], pos[3 * q + 1], pos[3 * q + 2]};
+        const float pn[3] = {nrm[3 * q], nrm[3 * q + 1], nrm[3 * q + 2]};
+        double s1[3], s2[3];
+        int backs;
+        mc_point(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn, a.spp,
+                 a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs);
+        if (lane == 0) {
+            float *oE = ka->f[fi].out_E, *oL = ka->f[fi].out_L;
+            const float *alb = ka->f[fi].albedo;
+            for (int c = 0; c < 3; ++c) {
+                const float E = (float)(s1[c] / (double)a.spp);
+                oE[3 * q + c] = E;
+                if (oL) oL[3 * q + c] = alb[3 * q + c] * E * 0.3183098861837907f;
+            }
+            uint8_t *of = ka->f[fi].out_flags;
+            if (of) of[q] = (uint8_t)(of[q] | 8u);
+        }
     }
 }
 
@@ -413,6 +466,32 @@ struct mc_scene {
     double total_area = 0.0;
     float eps = 0.0f;
 };
+
+namespace niv {
+void mc_scene_device_view(const struct mc_scene *s, const void **prims, const int32_t **lights,
+                          int32_t *n_prims, int32_t *n_lights, float *eps)
+{
+    *prims = s ? s->d_prims : nullptr;
+    *lights = s ? s->d_lights : nullptr;
+    *n_prims = s ? s->n_prims : 0;
+    *n_lights = s ? s->n_lights : 0;
+    *eps = s ? s->eps : 0.0f;
+}
+
+hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream)
+{
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_mc_fallback, dim3((unsigned)(n_cu * 8)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+}  // namespace niv
 
 namespace {
 niv_status hs(hipError_t e) { return e == hipSuccess ? NIV_OK : NIV_ERR_HIP; }
@@ -519,13 +598,13 @@ void mc_scene_destroy(mc_scene *s) { release(s); }
 
 niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
                          int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
-                         double *out_E, double *out_var, int32_t *out_backfaces,
+                         double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
                          uint8_t *out_valid, hipStream_t stream)
 {
     if (!s || count < 0 || spp < 1 || bounces < 0 || bounces > 16 || (flags & ~15)) return NIV_ERR_INVALID_ARG;
     if ((flags & 1) && (flags & 2)) return NIV_ERR_INVALID_ARG;  // NEE and emission-on-hit exclude each other
     if (count == 0) return NIV_OK;
-    if (!x || !nrm || !out_E) return NIV_ERR_INVALID_ARG;
+    if (!x || !nrm || (!out_E && !out_E32)) return NIV_ERR_INVALID_ARG;
     if (2 + bounces * (2 * s->n_lights + 2) > 1 << 20) return NIV_ERR_INVALID_ARG;
     McArgs a;
     memset(&a, 0, sizeof(a));
@@ -542,6 +621,7 @@ niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, in
     a.nrm = nrm;
     a.count = count;
     a.out_E = out_E;
+    a.out_E32 = out_E32;
     a.out_var = out_var;
     a.out_backfaces = out_backfaces;
     a.out_valid = out_valid;

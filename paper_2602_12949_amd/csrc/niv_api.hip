@@ -145,52 +145,250 @@ niv_status niv_prepare(niv_handle *h, const float *params, void *prepared, niv_p
     return hip_status(launch_prepare(h->m, params, prepared, prec, stream));
 }
 
-niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, niv_precision prec,
-                     hipStream_t stream)
+static niv_status check_frames(const niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                               niv_precision prec)
 {
     if (!h || n_frames < 0 || (n_frames > 0 && !frames)) return NIV_ERR_INVALID_ARG;
     if (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16) return NIV_ERR_INVALID_ARG;
     if (h->m.kind < 0) return NIV_ERR_UNSUPPORTED;
     for (int f = 0; f < n_frames; ++f) {
         const niv_frame &fr = frames[f];
-        if (fr.count < 0) return NIV_ERR_INVALID_ARG;
+        if (fr.count < 0 || fr.count >= (int64_t(1) << 28)) return NIV_ERR_INVALID_ARG;
         if (fr.count == 0) continue;
         if (!fr.pos || !fr.nrm || !fr.out_E || !fr.model) return NIV_ERR_INVALID_ARG;
         if (fr.out_L && !fr.albedo) return NIV_ERR_INVALID_ARG;
         if (!aligned(fr.pos, 4) || !aligned(fr.nrm, 4) || !aligned(fr.out_E, 4) ||
             (fr.albedo && !aligned(fr.albedo, 4)) || (fr.out_L && !aligned(fr.out_L, 4)) ||
-            !aligned(fr.model, 256))
+            (fr.out_inputs && !aligned(fr.out_inputs, 4)) || !aligned(fr.model, 256))
             return NIV_ERR_INVALID_ARG;
         for (int e = 0; e < h->m.cfg.n_extra; ++e)
             if (!isfinite(fr.extra_values[e])) return NIV_ERR_INVALID_ARG;
     }
+    return NIV_OK;
+}
+
+// One launch for up to kMaxFrames frames.
+static void fill_args(const niv_handle *h, const niv_frame *frames, int n, niv_precision prec,
+                      QueryArgs &a)
+{
+    memset(&a, 0, sizeof(a));
     OpLayout L = op_layout(h->m.kind, prec);
-    for (int f = 0; f < n_frames; ++f) {
+    a.n_frames = n;
+    a.grid_off = (uint64_t)L.grid_off;
+    a.grid_bytes = (uint32_t)(h->m.n_grid_values * (prec == NIV_FP32 ? 4 : 2));
+    a.hash_mask = (uint32_t)((int64_t(1) << h->m.cfg.log2_T) - 1);
+    for (int c = 0; c < 3; ++c) {
+        a.lo[c] = h->m.cfg.aabb_min[c];
+        a.hi[c] = h->m.cfg.aabb_max[c];
+    }
+    for (int f = 0; f < n; ++f) {
         const niv_frame &fr = frames[f];
-        if (fr.count == 0) continue;
+        FrameArgs &d = a.f[f];
+        d.pos = fr.pos;
+        d.nrm = fr.nrm;
+        d.albedo = fr.albedo;
+        d.mask = fr.mask;
+        d.in_flags = fr.in_flags;
+        d.out_E = fr.out_E;
+        d.out_L = fr.out_L;
+        d.out_flags = fr.out_flags;
+        d.out_inputs = fr.out_inputs;
+        d.model = static_cast<const uint8_t *>(fr.model);
+        d.count = fr.count;
+        for (int e = 0; e < 4; ++e) d.extra[e] = fr.extra_values[e];
+    }
+}
+
+static LaunchTune tune_of(const niv_handle *h, niv_precision prec)
+{
+    return h->m.tuned[prec] ? h->m.tune[prec] : default_tune(h->m.kind, prec);
+}
+
+niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, niv_precision prec,
+                     hipStream_t stream)
+{
+    niv_status s = check_frames(h, frames, n_frames, prec);
+    if (s != NIV_OK) return s;
+    const LaunchTune tu = tune_of(h, prec);
+    for (int f0 = 0; f0 < n_frames; f0 += kMaxFrames) {
+        const int n = n_frames - f0 < kMaxFrames ? n_frames - f0 : kMaxFrames;
         QueryArgs a;
-        memset(&a, 0, sizeof(a));
-        a.pos = fr.pos;
-        a.nrm = fr.nrm;
-        a.albedo = fr.albedo;
-        a.mask = fr.mask;
-        a.out_E = fr.out_E;
-        a.out_L = fr.out_L;
-        a.out_flags = fr.out_flags;
-        a.out_inputs = fr.out_inputs;
-        a.model = static_cast<const uint8_t *>(fr.model);
-        a.count = fr.count;
-        a.grid_off = (uint64_t)L.grid_off;
-        a.hash_mask = (uint32_t)((int64_t(1) << h->m.cfg.log2_T) - 1);
-        for (int e = 0; e < 4; ++e) a.extra[e] = fr.extra_values[e];
-        for (int c = 0; c < 3; ++c) {
-            a.lo[c] = h->m.cfg.aabb_min[c];
-            a.hi[c] = h->m.cfg.aabb_max[c];
-        }
-        hipError_t e = launch_query(h->m, a, prec, stream);
-        if (e != hipSuccess) return NIV_ERR_HIP;
+        fill_args(h, frames + f0, n, prec, a);
+        if (launch_query(h->m, a, prec, tu, stream) != hipSuccess) return NIV_ERR_HIP;
     }
     return NIV_OK;
+}
+
+niv_status niv_fallback_sizes(const niv_handle *h, int64_t max_flagged, int64_t *workspace_bytes)
+{
+    if (!h || !workspace_bytes || max_flagged < 0 || max_flagged > 0x7fffffff) return NIV_ERR_INVALID_ARG;
+    *workspace_bytes = 256 + 4 * max_flagged;
+    return NIV_OK;
+}
+
+niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                              niv_precision prec, const niv_fallback *fb, void *workspace,
+                              int64_t workspace_bytes, hipStream_t stream)
+{
+    niv_status s = check_frames(h, frames, n_frames, prec);
+    if (s != NIV_OK) return s;
+    if (n_frames > kMaxFrames) return NIV_ERR_INVALID_ARG;
+    if (!fb || !workspace || !aligned(workspace, 256)) return NIV_ERR_INVALID_ARG;
+    if (workspace_bytes < 256 + 4) return NIV_ERR_WORKSPACE;
+    if (fb->spp < 1 || fb->bounces < 0 || fb->bounces > 16 || (fb->mc_flags & ~15) ||
+        ((fb->mc_flags & 1) && (fb->mc_flags & 2)) || (fb->flag_mask & ~7u))
+        return NIV_ERR_INVALID_ARG;
+    uint32_t *cnt = static_cast<uint32_t *>(workspace);
+    uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(workspace) + 256);
+    const int64_t cap64 = (workspace_bytes - 256) / 4;
+    const uint32_t cap = (uint32_t)(cap64 < 0x7fffffff ? cap64 : 0x7fffffff);
+    // the counter is cleared by a kernel so that the whole call can be captured in a graph
+    if (launch_zero_u32(cnt, 1, stream) != hipSuccess) return NIV_ERR_HIP;
+    QueryArgs a;
+    fill_args(h, frames, n_frames, prec, a);
+    a.fb_list = list;
+    a.fb_count = cnt;
+    a.fb_cap = cap;
+    a.fb_mask = fb->flag_mask;
+    if (launch_query(h->m, a, prec, tune_of(h, prec), stream) != hipSuccess) return NIV_ERR_HIP;
+    FbArgs b;
+    memset(&b, 0, sizeof(b));
+    b.list = list;
+    b.count = cnt;
+    b.cap = cap;
+    b.spp = fb->spp;
+    b.bounces = fb->bounces;
+    b.flags = fb->mc_flags;
+    b.seed = fb->seed;
+    for (int f = 0; f < n_frames; ++f) {
+        const niv_frame &fr = frames[f];
+        FbFrame &d = b.f[f];
+        d.pos = fr.pos;
+        d.nrm = fr.nrm;
+        d.albedo = fr.albedo;
+        d.out_E = fr.out_E;
+        d.out_L = fr.out_L;
+        d.out_flags = fr.out_flags;
+        mc_scene_device_view(fr.scene, &d.prims, &d.lights, &d.n_prims, &d.n_lights, &d.eps);
+    }
+    return launch_mc_fallback(b, stream) == hipSuccess ? NIV_OK : NIV_ERR_HIP;
+}
+
+niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                        niv_precision prec, hipStream_t stream, niv_tune_result *out)
+{
+    niv_status s = check_frames(h, frames, n_frames, prec);
+    if (s != NIV_OK) return s;
+    if (n_frames < 1 || n_frames > kMaxFrames) return NIV_ERR_INVALID_ARG;
+    static const int blocks[2] = {256, 512};
+    static const int per_cu[3] = {0, 1, 2};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return NIV_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NIV_ERR_HIP; }
+    LaunchTune best = default_tune(h->m.kind, prec);
+    float best_ms = 1e30f;
+    int k = 0;
+    niv_status st = NIV_OK;
+    for (int b = 0; b < 2 && st == NIV_OK; ++b)
+        for (int c = 0; c < 3 && st == NIV_OK; ++c, ++k) {
+            LaunchTune tu = {blocks[b], per_cu[c]};
+            QueryArgs a;
+            fill_args(h, frames, n_frames, prec, a);
+            float ms = 1e30f;
+            for (int rep = 0; rep < 12 && st == NIV_OK; ++rep) {
+                if (hipEventRecord(e0, stream) != hipSuccess ||
+                    launch_query(h->m, a, prec, tu, stream) != hipSuccess ||
+                    hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    st = NIV_ERR_HIP;
+                    break;
+                }
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = NIV_ERR_HIP; break; }
+                if (rep >= 2 && t < ms) ms = t;  // best of 10 after 2 warm-up launches
+            }
+            if (out && k < 8) {
+                out->block[k] = tu.block;
+                out->blocks_per_cu[k] = tu.blocks_per_cu;
+                out->ms[k] = ms;
+            }
+            if (ms < best_ms) { best_ms = ms; best = tu; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != NIV_OK) return st;
+    h->m.tune[prec] = best;
+    h->m.tuned[prec] = true;
+    if (out) {
+        out->n = k;
+        out->chosen_block = best.block;
+        out->chosen_blocks_per_cu = best.blocks_per_cu;
+        out->chosen_ms = best_ms;
+    }
+    return NIV_OK;
+}
+
+}  // extern "C"
+
+struct niv_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+niv_status niv_graph_capture(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                             niv_precision prec, const niv_fallback *fb, void *workspace,
+                             int64_t workspace_bytes, niv_graph **out)
+{
+    if (!out) return NIV_ERR_INVALID_ARG;
+    *out = nullptr;
+    niv_status s = check_frames(h, frames, n_frames, prec);
+    if (s != NIV_OK) return s;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return NIV_ERR_HIP;
+    auto run = [&]() {
+        return fb ? niv_query_fallback(h, frames, n_frames, prec, fb, workspace, workspace_bytes, cs)
+                  : niv_query(h, frames, n_frames, prec, cs);
+    };
+    // eager run: initialises every launch parameter outside the capture
+    s = run();
+    if (s == NIV_OK && hipStreamSynchronize(cs) != hipSuccess) s = NIV_ERR_HIP;
+    niv_graph *g = nullptr;
+    if (s == NIV_OK) {
+        g = new (std::nothrow) niv_graph;
+        if (!g) s = NIV_ERR_INVALID_ARG;
+    }
+    if (s == NIV_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        s = NIV_ERR_HIP;
+    if (s == NIV_OK) {
+        niv_status rs = run();
+        hipError_t e = hipStreamEndCapture(cs, &g->graph);
+        if (rs != NIV_OK) s = rs;
+        else if (e != hipSuccess) s = NIV_ERR_HIP;
+    }
+    if (s == NIV_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        s = NIV_ERR_HIP;
+    (void)hipStreamDestroy(cs);
+    if (s != NIV_OK) {
+        niv_graph_destroy(g);
+        return s;
+    }
+    *out = g;
+    return NIV_OK;
+}
+
+niv_status niv_graph_launch(niv_graph *g, hipStream_t stream)
+{
+    if (!g || !g->exec) return NIV_ERR_INVALID_ARG;
+    return hipGraphLaunch(g->exec, stream) == hipSuccess ? NIV_OK : NIV_ERR_HIP;
+}
+
+void niv_graph_destroy(niv_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 const char *niv_status_string(niv_status s)

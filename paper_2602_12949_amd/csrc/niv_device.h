@@ -112,9 +112,9 @@ template <int P, class S> struct Ops {
     static constexpr int L0_BYTES = S::NOB * L0_OB;
     static constexpr int HOPS = F32 ? S::W / 4 : S::W / 32;         // operands per block row
     static constexpr int HID_BYTES = S::NOB * HOPS * OPB;
-    static constexpr int OUT_BYTES = 4 * HOPS * OPB;
+    static constexpr int OUT_BYTES = HOPS * OPB;                    // rows 0..2 = W_H
     static constexpr int W_BYTES = L0_BYTES + (S::H - 1) * HID_BYTES + OUT_BYTES;
-    static constexpr int N_OPS = S::NOB * (L0_FULL + L0_HALF) + (S::H - 1) * S::NOB * HOPS + 4 * HOPS;
+    static constexpr int N_OPS = S::NOB * (L0_FULL + L0_HALF) + (S::H - 1) * S::NOB * HOPS + HOPS;
     // BF16 operands are split into hi + lo parts (two products each)
     static constexpr int NS = (P == NIV_BF16) ? 2 : 1;
     static constexpr int PART_DW = S::DIN * ES / 4;                 // one part of a row
@@ -158,11 +158,11 @@ __device__ int64_t operand_source(int op, int lane, int e, int64_t n_grid, int n
         int row = 16 * ob + i;
         return wh + (int64_t)layer * S::W * S::W + (int64_t)row * S::W + col;
     }
-    op -= nh;  // output layer: [tile][kb]; tile t occupies rows 4t..4t+n_out-1
-    int t = op / O::HOPS, kb = op % O::HOPS;
+    op -= nh;  // output layer: [kb]; rows 0..n_out-1 hold W_H, the rest zero
+    const int kb = op;
     col = hidden_col(kb);
-    if ((i >> 2) != t || (i & 3) >= n_out) return -1;
-    return wo + (int64_t)(i & 3) * S::W + col;
+    if (i >= n_out) return -1;
+    return wo + (int64_t)i * S::W + col;
 }
 
 // Byte offset and element count of operand `op`.
@@ -256,6 +256,71 @@ __device__ inline void level_corners(const LV &lv, const double p[3], uint32_t h
     const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
     w[0] = wx0 * w00; w[1] = wx1 * w00; w[2] = wx0 * w10; w[3] = wx1 * w10;
     w[4] = wx0 * w01; w[5] = wx1 * w01; w[6] = wx0 * w11; w[7] = wx1 * w11;
+}
+
+// The same blend with the 8 latents fetched by buffer loads: the per-level
+// table offset rides in the scalar offset of the load, the hash primes are
+// pre-scaled by the entry size, and dense corners differ only by scalar or
+// immediate offsets, so no 64-bit address arithmetic is spent per corner.
+template <int P, class LV>
+__device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t hmask,
+                                      __amdgpu_buffer_rsrc_t rsrc)
+{
+    constexpr int SH = (P == NIV_FP32) ? 3 : 2;   // log2 of the entry size in bytes
+    constexpr uint32_t EB = 1u << SH;
+    int32_t ci[3];
+    float fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+        int32_t c = (int32_t)s;
+        c = c < lv.nm1 ? c : lv.nm1;
+        ci[a] = c;
+        fr[a] = (float)(s - (double)c);
+    }
+    f2 v[8];
+    auto ld = [&](uint32_t voff, uint32_t soff) -> f2 {
+        if constexpr (P == NIV_FP32) {
+            u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
+            return (f2){u2f(w.x), u2f(w.y)};
+        } else {
+            return Prec<P>::unpack(__builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0));
+        }
+    };
+    if (lv.dense) {
+        const uint32_t b = ((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH;
+        const uint32_t o00 = lv.off << SH, o10 = (lv.off + lv.s1) << SH;
+        const uint32_t o01 = (lv.off + lv.s2) << SH, o11 = (lv.off + lv.s2 + lv.s1) << SH;
+        v[0] = ld(b, o00); v[1] = ld(b + EB, o00);
+        v[2] = ld(b, o10); v[3] = ld(b + EB, o10);
+        v[4] = ld(b, o01); v[5] = ld(b + EB, o01);
+        v[6] = ld(b, o11); v[7] = ld(b + EB, o11);
+    } else {
+        const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH, m = hmask << SH;
+        const uint32_t x0 = (uint32_t)ci[0] << SH, x1 = x0 + EB;
+        const uint32_t y0 = (uint32_t)ci[1] * p1, y1 = y0 + p1;
+        const uint32_t z0 = (uint32_t)ci[2] * p2, z1 = z0 + p2;
+        const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
+        const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
+        const uint32_t o = lv.off << SH;
+        v[0] = ld(x0 ^ t00, o); v[1] = ld(x1 ^ t00, o);
+        v[2] = ld(x0 ^ t10, o); v[3] = ld(x1 ^ t10, o);
+        v[4] = ld(x0 ^ t01, o); v[5] = ld(x1 ^ t01, o);
+        v[6] = ld(x0 ^ t11, o); v[7] = ld(x1 ^ t11, o);
+    }
+    const float wx1 = fr[0], wx0 = 1.0f - fr[0];
+    const float wy1 = fr[1], wy0 = 1.0f - fr[1];
+    const float wz1 = fr[2], wz0 = 1.0f - fr[2];
+    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+    const float w[8] = {wx0 * w00, wx1 * w00, wx0 * w10, wx1 * w10,
+                        wx0 * w01, wx1 * w01, wx0 * w11, wx1 * w11};
+    f2 acc = {0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
+        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
+    }
+    return acc;
 }
 
 // Trilinear blend of one level (Sec. 3.1).  Returns the F = 2 features.

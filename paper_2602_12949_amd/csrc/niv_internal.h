@@ -32,20 +32,35 @@ struct LevelTable {
     LevelConst lv[kMaxLevels];
 };
 
-struct QueryArgs {
+constexpr int kMaxFrames = 16;
+
+// One G-buffer of a launch.  Pixels are split into tiles of (waves per
+// block) x 64; the frame's tiles are [tile_begin, tile_begin + tiles).
+struct FrameArgs {
     const float *pos, *nrm, *albedo;
-    const uint8_t *mask;
+    const uint8_t *mask, *in_flags;
     float *out_E, *out_L;
     uint8_t *out_flags;
     float *out_inputs;        // optional [count][din] encoded input vectors
-    const uint8_t *model;     // prepared model
+    const uint8_t *model;     // prepared model of this frame
     int64_t count;
-    uint64_t grid_off;        // byte offset of the grid in the prepared model
-    uint32_t hash_mask;       // T - 1
-    int32_t pad0;
+    int64_t tile_begin;
     float extra[4];           // scene variables of the frame
+};
+
+struct QueryArgs {
+    int32_t n_frames;
+    uint32_t hash_mask;       // T - 1
+    int64_t n_tiles;
+    uint64_t grid_off;        // byte offset of the grid in a prepared model
+    uint32_t grid_bytes;      // size of the grid latents (bounds of the buffer loads)
+    uint32_t fb_mask;         // flag bits that send a pixel to the Monte Carlo fallback
     double lo[3], hi[3];      // box the positions are clamped to
-    // training forward only (the fused kernel instantiated with TRAIN):
+    uint32_t *fb_list;        // fallback list: (frame << 28) | pixel, or null
+    uint32_t *fb_count;       // entries appended (may exceed fb_cap)
+    uint32_t fb_cap;
+    float loss_scale;         // training: 1/(3n)
+    // training forward only (the fused kernel instantiated with TRAIN, frame 0):
     const float *extra_ps;    // per-sample scene variables [count][n_extra] or null
     const float *target;      // [count][3] irradiance targets
     const uint8_t *valid;     // [count] or null
@@ -53,12 +68,20 @@ struct QueryArgs {
     uint32_t *mask_save;      // ReLU masks, per chunk, layer, dword, lane
     float *dE;                // [count][3] d(loss)/dE without the 1/(3n) factor
     float *loss;              // device scalar, accumulates the Eq. 3 loss
-    float loss_scale;         // 1/(3n)
     float loss_eps;           // 0.01 (Eq. 3)
+    int32_t pad1;
+    FrameArgs f[kMaxFrames];
 };
 
 // Shapes the fused kernels are instantiated for.
 enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kNumKinds = 3 };
+
+// Launch shape of the fused query: workgroup size and resident workgroups
+// per CU (0 = as many as fit); chosen by niv_autotune, else defaults.
+struct LaunchTune {
+    int block;
+    int blocks_per_cu;
+};
 
 // Operand-block layout of a prepared model (see the prepare kernel).
 struct OpLayout {
@@ -75,14 +98,41 @@ struct Model {
     int32_t dense[kMaxLevels];
     int64_t n_entries, n_grid_values, n_params;
     LevelConst lv[kMaxLevels];
+    LaunchTune tune[3];  // per precision
+    bool tuned[3];
 };
 
 // Defined in query.hip.
 OpLayout op_layout(int kind, niv_precision prec);
 hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
                           niv_precision prec, hipStream_t stream);
-hipError_t launch_query(const Model &m, const QueryArgs &a, niv_precision prec,
+LaunchTune default_tune(int kind, niv_precision prec);
+hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
                         hipStream_t stream);
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t stream);
+
+// Monte Carlo fallback of flagged pixels (mc.hip).
+struct FbFrame {
+    const float *pos, *nrm, *albedo;
+    float *out_E, *out_L;
+    uint8_t *out_flags;
+    const void *prims;        // device primitives of the frame's scene, or null
+    const int32_t *lights;
+    int32_t n_prims, n_lights;
+    float eps;
+    int32_t pad;
+};
+struct FbArgs {
+    const uint32_t *list;
+    const uint32_t *count;
+    uint32_t cap;
+    int32_t spp, bounces, flags;
+    uint64_t seed;
+    FbFrame f[kMaxFrames];
+};
+hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream);
+void mc_scene_device_view(const struct mc_scene *s, const void **prims, const int32_t **lights,
+                          int32_t *n_prims, int32_t *n_lights, float *eps);
 
 }  // namespace niv
 

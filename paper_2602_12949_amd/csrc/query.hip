@@ -113,11 +113,12 @@ hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
 #undef NIV_PREP
 }
 
-template <int P, class S, bool WLDS, int TB>
-static hipError_t query_t(const QueryArgs &a, hipStream_t st)
+template <int P, class S, bool WLDS, int TB, int BLOCK>
+static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
 {
     using O = Ops<P, S>;
-    auto kern = k_query<P, S, WLDS, TB, false>;
+    constexpr int kWavesPerBlock = BLOCK / 64;
+    auto kern = k_query<P, S, WLDS, TB, false, BLOCK>;
     const size_t lds = (WLDS ? O::W_BYTES : 0) + (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4;
     static int max_blocks = -1;  // resident workgroups per CU for this instantiation
     static int n_cu = 0;
@@ -131,36 +132,71 @@ static hipError_t query_t(const QueryArgs &a, hipStream_t st)
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
         int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, lds);
         if (e != hipSuccess) return e;
         max_blocks = nb > 0 ? nb : 1;
     }
-    const int64_t n_chunks = (a.count + 63) / 64;
-    int64_t want = (n_chunks + kWavesPerBlock - 1) / kWavesPerBlock;
-    int64_t cap = (int64_t)max_blocks * n_cu;
-    int64_t blocks = want < cap ? want : cap;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), lds, st, a);
+    // tiles: each block handles kWavesPerBlock chunks of 64 pixels of one frame
+    int64_t t = 0;
+    for (int f = 0; f < a.n_frames; ++f) {
+        a.f[f].tile_begin = t;
+        const int64_t chunks = (a.f[f].count + 63) / 64;
+        t += (chunks + kWavesPerBlock - 1) / kWavesPerBlock;
+    }
+    a.n_tiles = t;
+    if (t == 0) return hipSuccess;
+    const int per_cu = (blocks_per_cu > 0 && blocks_per_cu < max_blocks) ? blocks_per_cu : max_blocks;
+    const int64_t cap = (int64_t)per_cu * n_cu;
+    const int64_t blocks = t < cap ? t : cap;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), lds, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_query(const Model &m, const QueryArgs &a, niv_precision prec, hipStream_t st)
+template <int P, class S, bool WLDS, int TB>
+static hipError_t query_b(QueryArgs &a, const LaunchTune &tu, hipStream_t st)
 {
-    if (a.count <= 0) return hipSuccess;
+    if (tu.block == 256) return query_t<P, S, WLDS, TB, 256>(a, tu.blocks_per_cu, st);
+    return query_t<P, S, WLDS, TB, 512>(a, tu.blocks_per_cu, st);
+}
+
+LaunchTune default_tune(int kind, niv_precision prec)
+{
+    LaunchTune t;
+    // FP32 operands need twice the LDS per wave; smaller workgroups fit more of them
+    t.block = (prec == NIV_FP32 && kind != kWide6D) ? 256 : 512;
+    t.blocks_per_cu = 0;
+    return t;
+}
+
+hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
+                        hipStream_t st)
+{
     switch (m.kind) {
     case kUnitCube:
-        if (prec == NIV_FP32) return query_t<NIV_FP32, ShapeUnitCube, true, 4>(a, st);
-        if (prec == NIV_FP16) return query_t<NIV_FP16, ShapeUnitCube, true, 4>(a, st);
-        return query_t<NIV_BF16, ShapeUnitCube, true, 4>(a, st);
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeUnitCube, true, 4>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeUnitCube, true, 4>(a, tu, st);
+        return query_b<NIV_BF16, ShapeUnitCube, true, 4>(a, tu, st);
     case kRoom:
-        if (prec == NIV_FP32) return query_t<NIV_FP32, ShapeRoom, true, 4>(a, st);
-        if (prec == NIV_FP16) return query_t<NIV_FP16, ShapeRoom, true, 4>(a, st);
-        return query_t<NIV_BF16, ShapeRoom, true, 4>(a, st);
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeRoom, true, 4>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeRoom, true, 4>(a, tu, st);
+        return query_b<NIV_BF16, ShapeRoom, true, 4>(a, tu, st);
     default:
-        if (prec == NIV_FP32) return query_t<NIV_FP32, ShapeWide6D, false, 2>(a, st);
-        if (prec == NIV_FP16) return query_t<NIV_FP16, ShapeWide6D, false, 2>(a, st);
-        return query_t<NIV_BF16, ShapeWide6D, false, 2>(a, st);
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6D, false, 2>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeWide6D, false, 2>(a, tu, st);
+        return query_b<NIV_BF16, ShapeWide6D, false, 2>(a, tu, st);
     }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
 }
 
 }  // namespace niv

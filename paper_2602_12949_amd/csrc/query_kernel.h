@@ -10,7 +10,9 @@
 //      operand layout of the matrix cores;
 //   3. the MLP runs on MFMA with FP32 accumulation, four 16-pixel tiles per
 //      wave, weights resident in LDS;
-//   4. each lane writes its pixel's E, albedo * E / pi and flags.
+//   4. the RGB of tile t sits in lanes 0..15 after the output layer; one
+//      shuffle per channel hands every lane its own pixel's value, and each
+//      lane writes its pixel's E, albedo * E / pi and flags.
 //
 // Operand layout.  A layer y = W x is computed transposed, D = W * X^T, with
 // the weights as the A operand (16 output rows) and 16 pixels as the B
@@ -29,12 +31,10 @@
 namespace niv {
 
 // ---------------------------------------------------------------- fused query
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / 64;
-
-template <int P, class S, bool WLDS, int TB, bool TRAIN>
-__global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
+template <int P, class S, bool WLDS, int TB, bool TRAIN, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
 {
+    constexpr int kWavesPerBlock = BLOCK / 64;
     using O = Ops<P, S>;
     static_assert(!TRAIN || (TB == 4 && P != NIV_BF16), "training: four tiles, FP32 or FP16");
     // training saves: per 64-sample chunk, X_0 (DIN rows) then X_1..X_H (W rows), each [row][64]
@@ -42,65 +42,63 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint8_t *model = a.model + kLevelBytes;   // operand block
-    const uint8_t *grid = a.model + a.grid_off;
-
-    // Operand block -> LDS, once per workgroup.
-    const uint8_t *wsrc = model;
-    uint32_t *stage;
-    if constexpr (WLDS) {
-        const u4 *src = reinterpret_cast<const u4 *>(model);
-        u4 *dst = reinterpret_cast<u4 *>(smem);
-        for (int k = threadIdx.x; k < O::W_BYTES / 16; k += kBlock) dst[k] = src[k];
-        __syncthreads();
-        wsrc = smem;
-        stage = reinterpret_cast<uint32_t *>(smem + O::W_BYTES) + wave * 64 * O::ROW_DW;
-    } else {
-        stage = reinterpret_cast<uint32_t *>(smem) + wave * 64 * O::ROW_DW;
-    }
-
-    const int64_t n_chunks = (a.count + 63) / 64;
-    const int64_t wave_id = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
     const int g = lane >> 4, j = lane & 15;
+    // The frame table is read from the argument segment with scalar loads,
+    // indexed by the (block-uniform) frame of the current tile.
+    typedef const __attribute__((address_space(4))) QueryArgs *ConstArgs;
+    typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
+    ConstArgs ka = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
 
-    // Frequency code of the frame's scene variables (uniform over the launch).
-    float gam[16 * (S::NEX > 0 ? S::NEX : 1)];
-    if constexpr (S::NEX > 0) {
-#pragma unroll
-        for (int e = 0; e < S::NEX; ++e)
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                float t = a.extra[e] * (float)(1 << k);   // exact scaling by 2^k
-                gam[16 * e + 2 * k] = sinpif(t);
-                gam[16 * e + 2 * k + 1] = cospif(t);
+    uint32_t *stage = reinterpret_cast<uint32_t *>(smem + (WLDS ? O::W_BYTES : 0)) + wave * 64 * O::ROW_DW;
+    int staged = -1;  // frame whose operand block is in LDS (block-uniform)
+
+    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        int fi = 0;
+        for (int k = 1; k < a.n_frames; ++k)
+            if (tile >= ka->f[k].tile_begin) fi = k;
+        const uint8_t *fmodel = ka->f[fi].model;
+        if constexpr (WLDS) {
+            if (fi != staged) {  // operand block of this frame's model -> LDS
+                __syncthreads();
+                const u4 *src = reinterpret_cast<const u4 *>(fmodel + kLevelBytes);
+                u4 *dst = reinterpret_cast<u4 *>(smem);
+                for (int k = threadIdx.x; k < O::W_BYTES / 16; k += BLOCK) dst[k] = src[k];
+                __syncthreads();
+                staged = fi;
             }
-    }
-
-    for (int64_t chunk = wave_id; chunk < n_chunks; chunk += n_waves) {
-        // Re-read the level constants from the argument segment every chunk
-        // (scalar loads) instead of keeping 16 levels of them in registers.
-        uint32_t zero = 0;
-        asm volatile("" : "+s"(zero));
-        // constant address space: uniform, read-only, so scalar loads
-        typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
-        ConstLevels lvs = (ConstLevels)(a.model + zero);
-        const uint8_t *wop = wsrc;
-        if constexpr (!WLDS) {
-            // same for operands read from global memory: load them where used
-            wop = a.model + kLevelBytes + zero;
         }
+        const int64_t count = ka->f[fi].count;
+        const int64_t chunk = (tile - ka->f[fi].tile_begin) * kWavesPerBlock + wave;
+        if (chunk * 64 >= count) continue;   // this wave has no pixels in the frame's last tile
+        const __amdgpu_buffer_rsrc_t grid_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(fmodel + a.grid_off), (short)0, (int)a.grid_bytes, 0x00020000);
+        // frequency code of the frame's scene variables
+        float gam[16 * (S::NEX > 0 ? S::NEX : 1)];
+        if constexpr (S::NEX > 0) {
+#pragma unroll
+            for (int e = 0; e < S::NEX; ++e)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    float t = ka->f[fi].extra[e] * (float)(1 << k);   // exact scaling by 2^k
+                    gam[16 * e + 2 * k] = sinpif(t);
+                    gam[16 * e + 2 * k + 1] = cospif(t);
+                }
+        }
+        ConstLevels lvs = (ConstLevels)fmodel;
+        const uint8_t *wop = WLDS ? smem : fmodel + kLevelBytes;
+        const float *f_pos = ka->f[fi].pos, *f_nrm = ka->f[fi].nrm, *f_alb = ka->f[fi].albedo;
+        const uint8_t *f_mask = ka->f[fi].mask;
         const int64_t q = chunk * 64 + lane;
-        const bool live = q < a.count;
+        const bool live = q < count;
         // ---- 1. load and encode this lane's pixel
         float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
         bool on = false;
         if (live) {
-            on = a.mask ? (a.mask[q] != 0) : true;
+            on = f_mask ? (f_mask[q] != 0) : true;
             if constexpr (TRAIN) on = a.valid ? (a.valid[q] != 0) : true;
             if (on) {
-                px = a.pos[3 * q]; py = a.pos[3 * q + 1]; pz = a.pos[3 * q + 2];
-                nx = a.nrm[3 * q]; ny = a.nrm[3 * q + 1]; nz = a.nrm[3 * q + 2];
+                px = f_pos[3 * q]; py = f_pos[3 * q + 1]; pz = f_pos[3 * q + 2];
+                nx = f_nrm[3 * q]; ny = f_nrm[3 * q + 1]; nz = f_nrm[3 * q + 2];
             }
         }
         bool bad = !(__builtin_isfinite(px) && __builtin_isfinite(py) && __builtin_isfinite(pz) &&
@@ -120,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < S::NEX; ++e) bad |= !__builtin_isfinite(a.extra[e]);
+                for (int e = 0; e < S::NEX; ++e) bad |= !__builtin_isfinite(ka->f[fi].extra[e]);
             }
         }
         // scale by the largest component first so that tiny or huge normals
@@ -146,14 +144,14 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
             if constexpr (P == NIV_FP32) {
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
-                    f2 f = encode_level<P>(lvs[l], p, a.hash_mask, grid);
+                    f2 f = encode_level_buf<P>(lvs[l], p, a.hash_mask, grid_rsrc);
                     row[2 * l] = f2u(f.x);
                     row[2 * l + 1] = f2u(f.y);
                 }
             } else {
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
-                    f2 f = encode_level<P>(lvs[l], p, a.hash_mask, grid);
+                    f2 f = encode_level_buf<P>(lvs[l], p, a.hash_mask, grid_rsrc);
                     row[l] = Prec<P>::pack(f.x, f.y);
                     if constexpr (O::NS == 2) row[O::PART_DW + l] = Prec<P>::pack_lo(f.x, f.y, row[l]);
                 }
@@ -188,8 +186,9 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
 #pragma unroll
             for (int k = 0; k < O::NS * O::PART_DW; ++k) row[k] = 0u;
         }
-        if (a.out_inputs && live) {
-            float *dst = a.out_inputs + q * S::DIN;
+        float *f_inputs = ka->f[fi].out_inputs;
+        if (f_inputs && live) {
+            float *dst = f_inputs + q * S::DIN;
             if constexpr (P == NIV_FP32) {
 #pragma unroll
                 for (int k = 0; k < S::DIN; ++k) dst[k] = u2f(row[k]);
@@ -228,7 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         // ---- 2/3. MLP on the matrix cores, TB tiles of 16 pixels at a time
-        f4 acc_out = {0.f, 0.f, 0.f, 0.f};
+        f4 acc_o[4];  // output layer per tile: RGB of pixel 16t + j in lane j
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc_o[t] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t0 = 0; t0 < 4; t0 += TB) {
             f4 acc[TB][S::NOB];
@@ -344,8 +345,8 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                         for (int t = 0; t < TB; ++t)
 #pragma unroll
                             for (int c = 0; c < O::HOPS; ++c) {
-                                float av = reinterpret_cast<const float *>(lw + ((t0 + t) * O::HOPS + c) * O::OPB)[lane];
-                                acc_out = Prec<P>::mma1(av, bh[t][c], acc_out);
+                                float av = reinterpret_cast<const float *>(lw + c * O::OPB)[lane];
+                                acc_o[t0 + t] = Prec<P>::mma1(av, bh[t][c], acc_o[t0 + t]);
                             }
                     } else {
 #pragma unroll
@@ -402,12 +403,12 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                         for (int t = 0; t < TB; ++t)
 #pragma unroll
                             for (int kb = 0; kb < O::HOPS; ++kb) {
-                                u4 av = reinterpret_cast<const u4 *>(lw + ((t0 + t) * O::HOPS + kb) * O::OPB)[lane];
+                                u4 av = reinterpret_cast<const u4 *>(lw + kb * O::OPB)[lane];
 #pragma unroll
                                 for (int sp = 0; sp < O::NS; ++sp) {
                                     u4 bv = {bh[sp][t][4 * kb], bh[sp][t][4 * kb + 1], bh[sp][t][4 * kb + 2],
                                              bh[sp][t][4 * kb + 3]};
-                                    acc_out = Prec<P>::mma(av, bv, acc_out);
+                                    acc_o[t0 + t] = Prec<P>::mma(av, bv, acc_o[t0 + t]);
                                 }
                             }
                     } else {
@@ -432,7 +433,28 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
                 }
             }
         }
-        // ---- 4. lane (g, j) holds rows 4g..4g+2 = RGB of pixel 16g + j = this lane's pixel
+        // ---- 4. lane j (g = 0) holds the RGB of pixel 16t + j in acc_o[t]:
+        // lane (g, j) takes channel c of its pixel 16g + j from lane j.
+        f4 acc_out;
+        {
+            const int src = j << 2;  // byte address of lane j for ds_bpermute
+            auto from_j = [&](float x) {
+                return u2f((uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)f2u(x)));
+            };
+            float ch[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float e[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const f4 v = acc_o[t];
+                    const float x = c == 0 ? v.x : (c == 1 ? v.y : v.z);
+                    e[t] = from_j(x);
+                }
+                ch[c] = g == 0 ? e[0] : g == 1 ? e[1] : g == 2 ? e[2] : e[3];
+            }
+            acc_out = (f4){ch[0], ch[1], ch[2], 0.f};
+        }
         if constexpr (TRAIN) {
             // Eq. 3: (E - y)^2 / (sg(E^2) + eps); d/dE = 2 (E - y) / (E^2 + eps)
             float lsum = 0.0f;
@@ -455,7 +477,42 @@ __global__ __launch_bounds__(kBlock) void k_query(const QueryArgs a)
             if (lane == 0) atomicAdd(a.loss, lsum * a.loss_scale);
             continue;
         }
-        if (live) {            if (a.out_flags) a.out_flags[q] = (uint8_t)flags;
+        float *f_E = ka->f[fi].out_E, *f_L = ka->f[fi].out_L;
+        uint8_t *f_flags = ka->f[fi].out_flags;
+        if (live) {
+            float E0 = work ? acc_out.x : 0.f, E1 = work ? acc_out.y : 0.f, E2 = work ? acc_out.z : 0.f;
+            if (work && !(__builtin_isfinite(E0) && __builtin_isfinite(E1) && __builtin_isfinite(E2)))
+                flags |= 4u;
+            f_E[3 * q] = E0;
+            f_E[3 * q + 1] = E1;
+            f_E[3 * q + 2] = E2;
+            if (f_L) {
+                const float ip = 0.3183098861837907f;  // 1/pi
+                float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+                if (on) { r0 = f_alb[3 * q]; r1 = f_alb[3 * q + 1]; r2 = f_alb[3 * q + 2]; }
+                f_L[3 * q] = r0 * E0 * ip;
+                f_L[3 * q + 1] = r1 * E1 * ip;
+                f_L[3 * q + 2] = r2 * E2 * ip;
+            }
+            if (f_flags) f_flags[q] = (uint8_t)flags;
+        }
+        // pixels the network should not be trusted with go to the Monte Carlo
+        // fallback list: wave ballot, one atomic per wave
+        if (a.fb_list) {
+            const uint8_t *f_in = ka->f[fi].in_flags;
+            // a pixel whose own inputs are not finite has nothing to estimate
+            const bool fb = live && on && (flags & 2u) == 0u &&
+                            (((flags & a.fb_mask) != 0u) || (f_in && f_in[q] != 0));
+            const uint64_t bal = __ballot(fb);
+            if (bal) {
+                const uint32_t n = (uint32_t)__popcll(bal);
+                const uint32_t before = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(a.fb_count, n);
+                base = __shfl(base, 0);
+                if (fb && base + before < a.fb_cap)
+                    a.fb_list[base + before] = ((uint32_t)fi << 28) | (uint32_t)q;
+            }
         }
     }
 }

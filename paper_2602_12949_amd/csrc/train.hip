@@ -458,11 +458,14 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     // 1. forward with saves, loss and d loss / dE
     QueryArgs a;
     memset(&a, 0, sizeof(a));
-    a.pos = b.x;
-    a.nrm = b.nrm;
-    a.model = static_cast<const uint8_t *>(st.model);
-    a.count = b.count;
+    a.n_frames = 1;
+    a.f[0].pos = b.x;
+    a.f[0].nrm = b.nrm;
+    a.f[0].model = static_cast<const uint8_t *>(st.model);
+    a.f[0].count = b.count;
+    a.f[0].tile_begin = 0;
     a.grid_off = (uint64_t)op_layout(m.kind, (niv_precision)P).grid_off;
+    a.grid_bytes = (uint32_t)(m.n_grid_values * (P == NIV_FP32 ? 4 : 2));
     a.hash_mask = (uint32_t)((int64_t(1) << m.cfg.log2_T) - 1);
     for (int c = 0; c < 3; ++c) {
         a.lo[c] = m.cfg.aabb_min[c];
@@ -475,10 +478,11 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     a.mask_save = reinterpret_cast<uint32_t *>(ws + L.mask_off);
     a.dE = reinterpret_cast<float *>(ws + L.dE_off);
     a.loss = st.loss;
-    a.loss_scale = (float)(1.0 / (3.0 * (double)b.count));
+    a.loss_scale = (float)(1.0 / (3.0 * (double)b.count));  // used by the forward's loss sum
     a.loss_eps = 0.01f;
     {
-        auto kern = k_query<P, S, true, 4, true>;
+        constexpr int kBlock = 256, kWavesPerBlock = 4;
+        auto kern = k_query<P, S, true, 4, true, kBlock>;
         const size_t lds = O::W_BYTES + (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4;
         static int max_blocks = -1, n_cu = 0;
         if (max_blocks < 0) {
@@ -495,8 +499,8 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
             max_blocks = nb > 0 ? nb : 1;
         }
         const int64_t n_chunks = (b.count + 63) / 64;
-        int64_t blocks = (n_chunks + kWavesPerBlock - 1) / kWavesPerBlock;
-        blocks = blocks < (int64_t)max_blocks * n_cu ? blocks : (int64_t)max_blocks * n_cu;
+        a.n_tiles = (n_chunks + kWavesPerBlock - 1) / kWavesPerBlock;
+        int64_t blocks = a.n_tiles < (int64_t)max_blocks * n_cu ? a.n_tiles : (int64_t)max_blocks * n_cu;
         hipLaunchKernelGGL(kern, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(kBlock), lds, stream, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -509,10 +513,11 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     ba.dE = reinterpret_cast<const float *>(ws + L.dE_off);
     ba.x = b.x;
     ba.model = static_cast<const uint8_t *>(st.model);
+    const float loss_scale = (float)(1.0 / (3.0 * (double)b.count));
     ba.grads = st.grads;
     ba.n = b.count;
     ba.n_grid = m.n_grid_values;
-    ba.loss_scale = a.loss_scale;
+    ba.loss_scale = loss_scale;
     ba.hash_mask = a.hash_mask;
     for (int c = 0; c < 3; ++c) { ba.lo[c] = a.lo[c]; ba.hi[c] = a.hi[c]; }
     {

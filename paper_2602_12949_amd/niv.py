@@ -38,7 +38,18 @@ class Frame(C.Structure):
                 ("albedo", C.c_void_p), ("mask", C.c_void_p),
                 ("extra_values", C.c_float * 4), ("model", C.c_void_p),
                 ("out_E", C.c_void_p), ("out_L", C.c_void_p), ("out_flags", C.c_void_p),
-                ("out_inputs", C.c_void_p)]
+                ("out_inputs", C.c_void_p), ("in_flags", C.c_void_p), ("scene", C.c_void_p)]
+
+
+class Fallback(C.Structure):
+    _fields_ = [("flag_mask", C.c_uint32), ("spp", C.c_int32), ("bounces", C.c_int32),
+                ("mc_flags", C.c_int32), ("seed", C.c_uint64)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("n", C.c_int32), ("block", C.c_int32 * 8), ("blocks_per_cu", C.c_int32 * 8),
+                ("ms", C.c_float * 8), ("chosen_block", C.c_int32),
+                ("chosen_blocks_per_cu", C.c_int32), ("chosen_ms", C.c_float)]
 
 
 class Batch(C.Structure):
@@ -80,6 +91,16 @@ def lib():
         L.niv_query.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp]
         L.niv_status_string.argtypes = [C.c_int]
         L.niv_status_string.restype = C.c_char_p
+        L.niv_fallback_sizes.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.niv_query_fallback.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
+                                         C.POINTER(Fallback), vp, C.c_int64, vp]
+        L.niv_autotune.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp,
+                                   C.POINTER(TuneResult)]
+        L.niv_graph_capture.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
+                                        C.POINTER(Fallback), vp, C.c_int64, C.POINTER(vp)]
+        L.niv_graph_launch.argtypes = [vp, vp]
+        L.niv_graph_destroy.argtypes = [vp]
+        L.niv_graph_destroy.restype = None
         L.niv_train_sizes.argtypes = [vp, C.c_int, C.c_int64, C.POINTER(C.c_int64)]
         L.niv_backward.argtypes = [vp, C.POINTER(Batch), C.POINTER(TrainState), C.c_int, vp]
         L.niv_adam_update.argtypes = [vp, C.POINTER(TrainState), C.POINTER(Adam), vp]
@@ -89,7 +110,7 @@ def lib():
         L.mc_scene_destroy.argtypes = [vp]
         L.mc_scene_destroy.restype = None
         L.mc_irradiance.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
-                                    C.c_uint64, vp, vp, vp, vp, vp]
+                                    C.c_uint64, vp, vp, vp, vp, vp, vp]
         L.mc_sample_points.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, C.c_uint64, vp, vp, vp]
         _lib = L
     return _lib
@@ -188,7 +209,8 @@ class NIV:
         return out
 
     def frame(self, pos, nrm, model, albedo=None, mask=None, extra=(), out_E=None, out_L=None,
-              out_flags=None, want_L=True, want_flags=True, out_inputs=None):
+              out_flags=None, want_L=True, want_flags=True, out_inputs=None, in_flags=None,
+              scene=None):
         """Builds a niv_frame (and the output tensors) for one G-buffer."""
         n = pos.numel() // 3
         dev = pos.device
@@ -214,11 +236,44 @@ class NIV:
         f.out_L = _ptr(out_L).value
         f.out_flags = _ptr(out_flags).value
         f.out_inputs = _ptr(out_inputs).value
+        f.in_flags = _ptr(in_flags).value
+        f.scene = scene._h.value if scene is not None else None
         return f, (out_E, out_L, out_flags)
 
     def query_frames(self, frames, prec="fp16"):
         arr = (Frame * len(frames))(*frames)
         _check(lib().niv_query(self._h, arr, len(frames), _prec(prec), _stream()), "niv_query")
+
+    def fallback_workspace(self, max_flagged, device="cuda"):
+        nb = C.c_int64()
+        _check(lib().niv_fallback_sizes(self._h, int(max_flagged), C.byref(nb)), "niv_fallback_sizes")
+        return torch.empty(nb.value, dtype=torch.uint8, device=device)
+
+    @staticmethod
+    def fallback(flag_mask=FLAG_OUTSIDE | FLAG_BAD_OUTPUT, spp=64, bounces=3, mc_flags=MC_NEE,
+                 seed=0):
+        return Fallback(int(flag_mask), int(spp), int(bounces), int(mc_flags), int(seed))
+
+    def query_fallback(self, frames, prec, fb, workspace):
+        """niv_query_fallback: query, then Monte Carlo for flagged pixels."""
+        arr = (Frame * len(frames))(*frames)
+        _check(lib().niv_query_fallback(self._h, arr, len(frames), _prec(prec), C.byref(fb),
+                                        _ptr(workspace), workspace.numel(), _stream()),
+               "niv_query_fallback")
+
+    def autotune(self, frames, prec):
+        """Times the launch shapes on these frames, keeps the fastest."""
+        arr = (Frame * len(frames))(*frames)
+        r = TuneResult()
+        _check(lib().niv_autotune(self._h, arr, len(frames), _prec(prec), _stream(), C.byref(r)),
+               "niv_autotune")
+        return {"candidates": [(r.block[k], r.blocks_per_cu[k], r.ms[k]) for k in range(r.n)],
+                "block": r.chosen_block, "blocks_per_cu": r.chosen_blocks_per_cu,
+                "ms": r.chosen_ms}
+
+    def capture(self, frames, prec, fb=None, workspace=None):
+        """A HIP graph of one frame's query (and fallback); see Graph."""
+        return Graph(self, frames, prec, fb, workspace)
 
     @property
     def input_dim(self):
@@ -270,20 +325,57 @@ class McScene:
                    torch.empty(n, dtype=torch.uint8, device=dev))
         E, var, bf, vd = out
         _check(lib().mc_irradiance(self._h, _ptr(x), _ptr(nrm), n, int(spp), int(bounces),
-                                   int(flags), C.c_uint64(int(seed)), _ptr(E), _ptr(var),
+                                   int(flags), C.c_uint64(int(seed)), _ptr(E), None, _ptr(var),
                                    _ptr(bf), _ptr(vd), _stream()), "mc_irradiance")
         return out
 
-    def sample_points(self, lo, hi, count, n_surface, seed, device="cuda"):
+    def targets(self, x, nrm, spp, bounces, seed, flags=1, out=None):
+        """Training targets: (E [n,3] float32, valid [n] uint8)."""
+        n = x.numel() // 3
+        if out is None:
+            out = (torch.empty((n, 3), dtype=torch.float32, device=x.device),
+                   torch.empty(n, dtype=torch.uint8, device=x.device))
+        E32, vd = out
+        _check(lib().mc_irradiance(self._h, _ptr(x), _ptr(nrm), n, int(spp), int(bounces),
+                                   int(flags), C.c_uint64(int(seed)), None, _ptr(E32), None,
+                                   None, _ptr(vd), _stream()), "mc_irradiance")
+        return out
+
+    def sample_points(self, lo, hi, count, n_surface, seed, device="cuda", out=None):
         """Training points: (x [count,3], n [count,3]) float32 on the device."""
         lo_a = (C.c_double * 3)(*[float(v) for v in lo])
         hi_a = (C.c_double * 3)(*[float(v) for v in hi])
-        x = torch.empty((count, 3), dtype=torch.float32, device=device)
-        n = torch.empty((count, 3), dtype=torch.float32, device=device)
+        if out is None:
+            out = (torch.empty((count, 3), dtype=torch.float32, device=device),
+                   torch.empty((count, 3), dtype=torch.float32, device=device))
+        x, n = out
         _check(lib().mc_sample_points(self._h, lo_a, hi_a, int(count), int(n_surface),
                                       C.c_uint64(int(seed)), _ptr(x), _ptr(n), _stream()),
                "mc_sample_points")
         return x, n
+
+class Graph:
+    """niv_graph_capture / niv_graph_launch: the frame's launches replayed
+    with the same buffers (whose contents may change)."""
+
+    def __init__(self, niv, frames, prec, fb, workspace):
+        self._keep = (niv, frames, workspace)
+        arr = (Frame * len(frames))(*frames)
+        g = C.c_void_p()
+        _check(lib().niv_graph_capture(niv._h, arr, len(frames), _prec(prec),
+                                       C.byref(fb) if fb is not None else None,
+                                       _ptr(workspace), workspace.numel() if workspace is not None else 0,
+                                       C.byref(g)), "niv_graph_capture")
+        self._g = g
+
+    def launch(self):
+        _check(lib().niv_graph_launch(self._g, _stream()), "niv_graph_launch")
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value and _lib is not None:
+            _lib.niv_graph_destroy(g)
+            self._g = None
 
 
 class Trainer:
