@@ -97,8 +97,9 @@ niv_status niv_prepare(niv_handle *h, const float *params, void *prepared,
  *   out_L        [count][3] float   albedo * E / pi (Eq. 2), or NULL
  *   out_flags    [count]    uint8   or NULL: bit 0 position outside the box
  *                (clamped), bit 1 non-finite input or zero normal (E set to
- *                0), bit 2 non-finite E.  Masked-off pixels get E = L = 0,
- *                flags 0.
+ *                0), bit 2 non-finite E, bit 4 finite E with a negative
+ *                channel (irradiance is non-negative, the linear output
+ *                layer is not).  Masked-off pixels get E = L = 0, flags 0.
  *   out_inputs   [count][din] float or NULL: the encoded input vector of each
  *                pixel as fed to the network (grid features, SH, frequency
  *                code; rounded to the operand precision), for inspection.
@@ -131,8 +132,8 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
  * workgroups walk the frames' pixel tiles in order. */
 
 /* Monte Carlo fallback for pixels the network should not answer: after the
- * query, pixels whose flags intersect `flag_mask` (bit 0 outside the box,
- * bit 2 non-finite E) or whose in_flags are set are appended to a list, and
+ * query, pixels whose flags intersect `flag_mask` (bits 0, 2 and 4 of
+ * out_flags) or whose in_flags are set are appended to a list, and
  * their E is replaced by mc_irradiance(spp, bounces, mc_flags) of the frame's
  * scene (L = albedo E / pi); their flags gain bit 3.  Random stream: point
  * index (frame << 28) | pixel. */

@@ -96,7 +96,7 @@ def lib():
                                      C.POINTER(C.c_uint64)]
         L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
         L.orc_uniform.restype = C.c_double
-        L.orc_mc_irradiance.argtypes = [C.c_void_p, C.c_int, fp, fp, C.c_int64, C.c_int,
+        L.orc_mc_irradiance.argtypes = [C.c_void_p, C.c_int, fp, fp, C.c_void_p, C.c_int64, C.c_int,
                                         C.c_int, C.c_int, C.c_uint64, dp, dp,
                                         C.POINTER(C.c_int32), u8p]
         L.orc_sample_points.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_int64,
@@ -278,8 +278,9 @@ def uniform(seed, a, b, stream, dim):
 
 
 # ---------------------------------------------------------------- Monte Carlo
-def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed):
-    """Eq. 1 indirect irradiance by Monte Carlo (Sec. 3.4 targets).
+def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None):
+    """Eq. 1 indirect irradiance by Monte Carlo (Sec. 3.4 targets).  The
+    random stream of point i is keyed by point_id[i] (default i).
     Returns (E [n,3], var [n,3], backfaces [n], valid [n])."""
     pr = np.ascontiguousarray(prims)
     x = _f32(x).reshape(-1, 3)
@@ -289,8 +290,12 @@ def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed):
     var = np.zeros((n, 3))
     bf = np.zeros(n, np.int32)
     vd = np.zeros(n, np.uint8)
+    ids = None
+    if point_id is not None:
+        ids = np.ascontiguousarray(point_id, dtype=np.uint64).reshape(-1)
+        assert ids.size == n
     lib().orc_mc_irradiance(pr.ctypes.data, len(pr), _P(x, C.c_float), _P(nrm, C.c_float),
-                            n, int(spp), int(bounces), int(flags), int(seed),
+                            None if ids is None else ids.ctypes.data, n, int(spp), int(bounces), int(flags), int(seed),
                             _P(E, C.c_double), _P(var, C.c_double),
                             _P(bf, C.c_int32), _P(vd, C.c_uint8))
     return E, var, bf, vd

@@ -246,6 +246,7 @@ static void orc_levels_init(const orc_config *c, orc_levels *lv)
 #define ORC_FLAG_OUTSIDE 1   /* position outside the box (clamped) */
 #define ORC_FLAG_BAD_INPUT 2 /* non-finite position/normal or zero normal */
 #define ORC_FLAG_BAD_OUTPUT 4 /* non-finite output */
+#define ORC_FLAG_NEG_OUTPUT 16 /* finite output with a negative channel */
 
 /* Input vector x0 = concat(grid features level 0..L-1, SH, freq(extra)). */
 static int orc_encode(const orc_config *c, const orc_levels *lv,
@@ -366,8 +367,13 @@ void orc_query(const orc_config *c, const double *params, int64_t count,
             flags |= orc_encode(c, &lv, params, p, n, ex, x0);
             if (out_x0) memcpy(out_x0 + q * in, x0, sizeof(double) * in);
             orc_mlp(c, W, x0, E, 0);
-            for (int o = 0; o < c->n_out; ++o)
+            int neg = 0;
+            for (int o = 0; o < c->n_out; ++o) {
                 if (!isfinite(E[o])) flags |= ORC_FLAG_BAD_OUTPUT;
+                neg |= E[o] < 0.0;
+            }
+            /* irradiance is non-negative; the linear output layer is not */
+            if (neg && !(flags & ORC_FLAG_BAD_OUTPUT)) flags |= ORC_FLAG_NEG_OUTPUT;
         }
         for (int o = 0; o < c->n_out; ++o) {
             out_E[q * c->n_out + o] = E[o];
@@ -757,14 +763,15 @@ static double orc_light_point(const orc_prim *pr, double u1, double u2, double q
  * and the path continues with a cosine-sampled direction and throughput
  * times albedo.  DIRECT_AT_ORIGIN replaces all of this by light sampling of
  * the direct irradiance at x itself (a test mode).
- * Random dimensions of sample s of point i: 0-1 first direction; bounce k
+ * The random stream of point i is keyed by point_id[i] (i when point_id is
+ * NULL).  Random dimensions of sample s: 0-1 first direction; bounce k
  * (1-based) uses 2 + (k-1)(2J+2) + 2j for light j and 2 + (k-1)(2J+2) + 2J
  * for the continuation, J = number of lights.  DIRECT_AT_ORIGIN uses 2j.
  * Outputs per point: mean E (3), variance of the mean (3), back-face count,
  * valid = (back-face count <= S/2) and some channel of E > 0. */
 void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
-                       const float *nrm, int64_t count, int spp, int bounces,
-                       int flags, uint64_t seed, double *out_E, double *out_var,
+                       const float *nrm, const uint64_t *point_id, int64_t count, int spp,
+                       int bounces, int flags, uint64_t seed, double *out_E, double *out_var,
                        int32_t *out_backfaces, uint8_t *out_valid)
 {
     int lights[64], J = 0;
@@ -793,6 +800,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
     int stride = 2 * J + 2;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < count; ++i) {
+        const uint64_t pid = point_id ? point_id[i] : (uint64_t)i;
         double sum[3] = {0, 0, 0}, sum2[3] = {0, 0, 0};
         int backs = 0;
         double px[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
@@ -807,8 +815,8 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                 for (int j = 0; j < J; ++j) {
                     const orc_prim *L = &prims[lights[j]];
                     double q[3], nq[3];
-                    double A = orc_light_point(L, orc_uniform(seed, i, s, 0, 2 * j),
-                                               orc_uniform(seed, i, s, 0, 2 * j + 1), q, nq);
+                    double A = orc_light_point(L, orc_uniform(seed, pid, s, 0, 2 * j),
+                                               orc_uniform(seed, pid, s, 0, 2 * j + 1), q, nq);
                     double w[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
                     double d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], dl = sqrt(d2);
                     for (int a = 0; a < 3; ++a) w[a] /= dl;
@@ -822,8 +830,8 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
             } else {
                 double o[3], d[3];
                 for (int a = 0; a < 3; ++a) o[a] = px[a] + eps * pn[a];
-                orc_cosine_dir(pn, orc_uniform(seed, i, s, 0, 0),
-                               orc_uniform(seed, i, s, 0, 1), d);
+                orc_cosine_dir(pn, orc_uniform(seed, pid, s, 0, 0),
+                               orc_uniform(seed, pid, s, 0, 1), d);
                 orc_hit h;
                 int ok = orc_trace(prims, n_prims, o, d, 0.0, &h);
                 if (ok && h.back) { backs++; ok = 0; }
@@ -845,8 +853,8 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                             for (int j = 0; j < J; ++j) {
                                 const orc_prim *L = &prims[lights[j]];
                                 double q[3], nq[3];
-                                double A = orc_light_point(L, orc_uniform(seed, i, s, 0, base + 2 * j),
-                                                           orc_uniform(seed, i, s, 0, base + 2 * j + 1), q, nq);
+                                double A = orc_light_point(L, orc_uniform(seed, pid, s, 0, base + 2 * j),
+                                                           orc_uniform(seed, pid, s, 0, base + 2 * j + 1), q, nq);
                                 double w[3] = {q[0] - oy[0], q[1] - oy[1], q[2] - oy[2]};
                                 double d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], dl = sqrt(d2);
                                 for (int a = 0; a < 3; ++a) w[a] /= dl;
@@ -865,8 +873,8 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                         if (!cont) break;
                         for (int c = 0; c < 3; ++c) beta[c] *= rho[c];
                         if (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0) break;
-                        orc_cosine_dir(ny, orc_uniform(seed, i, s, 0, base + 2 * J),
-                                       orc_uniform(seed, i, s, 0, base + 2 * J + 1), d);
+                        orc_cosine_dir(ny, orc_uniform(seed, pid, s, 0, base + 2 * J),
+                                       orc_uniform(seed, pid, s, 0, base + 2 * J + 1), d);
                         if (!orc_trace(prims, n_prims, oy, d, 0.0, &h) || h.back) break;
                         if (flags & ORC_MC_EMIT_ON_HIT) {
                             const orc_prim *pe = &prims[h.prim];

@@ -236,7 +236,7 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
     if (!fb || !workspace || !aligned(workspace, 256)) return NIV_ERR_INVALID_ARG;
     if (workspace_bytes < 256 + 4) return NIV_ERR_WORKSPACE;
     if (fb->spp < 1 || fb->bounces < 0 || fb->bounces > 16 || (fb->mc_flags & ~15) ||
-        ((fb->mc_flags & 1) && (fb->mc_flags & 2)) || (fb->flag_mask & ~7u))
+        ((fb->mc_flags & 1) && (fb->mc_flags & 2)) || (fb->flag_mask & ~21u))
         return NIV_ERR_INVALID_ARG;
     uint32_t *cnt = static_cast<uint32_t *>(workspace);
     uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(workspace) + 256);

@@ -483,6 +483,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             float E0 = work ? acc_out.x : 0.f, E1 = work ? acc_out.y : 0.f, E2 = work ? acc_out.z : 0.f;
             if (work && !(__builtin_isfinite(E0) && __builtin_isfinite(E1) && __builtin_isfinite(E2)))
                 flags |= 4u;
+            else if (work && (E0 < 0.f || E1 < 0.f || E2 < 0.f))
+                flags |= 16u;  // irradiance is non-negative; the linear output is not
             f_E[3 * q] = E0;
             f_E[3 * q + 1] = E1;
             f_E[3 * q + 2] = E2;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libniv.so")
 NIV_OK, NIV_ERR_INVALID_ARG, NIV_ERR_UNSUPPORTED, NIV_ERR_HIP, NIV_ERR_WORKSPACE, NIV_ERR_STATE = range(6)
 FP32, FP16, BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
-FLAG_OUTSIDE, FLAG_BAD_INPUT, FLAG_BAD_OUTPUT = 1, 2, 4
+FLAG_OUTSIDE, FLAG_BAD_INPUT, FLAG_BAD_OUTPUT, FLAG_FALLBACK, FLAG_NEG_OUTPUT = 1, 2, 4, 8, 16
 
 
 class NivError(RuntimeError):

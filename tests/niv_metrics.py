@@ -36,3 +36,26 @@ def max_rel_floored(a, b, frac=1e-3):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def assert_flags(fl, fl_ref, E_ref, near):
+    """Flags are integer outputs and must agree exactly, except the
+    negative-output bit (16), whose sign test may go either way where an
+    output channel lies within `near` of zero (`near` per output, from the
+    bar of the precision)."""
+    np.testing.assert_array_equal(fl & ~16, fl_ref & ~16)
+    diff = ((fl ^ fl_ref) & 16) != 0
+    if diff.any():
+        close = (np.abs(E_ref) <= near).any(axis=1)
+        bad = np.nonzero(diff & ~close)[0]
+        assert bad.size == 0, ("negative-output flag differs away from zero", bad[:10])
+
+
+def sign_margin(prec, E_ref, scale):
+    """How close to zero an output may be for its sign to be undecided:
+    1e-5 of the term scale for FP32; for FP16/BF16 2e-2 of the larger of the
+    term scale and the image's RMS output."""
+    if prec == "fp32":
+        return 1e-5 * np.maximum(np.abs(E_ref), scale)
+    rms = np.sqrt(np.mean(E_ref ** 2))
+    return 2e-2 * np.maximum(scale, rms)

@@ -14,7 +14,8 @@ import torch
 
 import oracle as O
 from niv_synth import get_workload, make_params, unit_cube_queries, make_room_gbuffer
-from niv_metrics import term_scale, max_rel_fp32, max_rel_floored, rel_l2
+from niv_metrics import (term_scale, max_rel_fp32, max_rel_floored, rel_l2, assert_flags,
+                         sign_margin)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,7 +83,7 @@ def test_unit_cube_parity(unit_cube, prec):
     E_ref, L_ref, fl_ref, sc = _oracle(oc, params, prec, pos, nrm, albedo=alb)
     err = _check(prec, E, E_ref, sc)
     _check(prec, L, L_ref, sc * alb / np.pi)
-    np.testing.assert_array_equal(fl, fl_ref)
+    assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
     print(f"  err {err:.3e}", flush=True)
 
 
@@ -112,7 +113,7 @@ def test_ragged_counts(unit_cube, n):
     E, _, fl = _run(m, params, pos[:n], nrm[:n], "fp32")
     E_ref, _, fl_ref, sc = _oracle(oc, params, "fp32", pos[:n], nrm[:n])
     _check("fp32", E, E_ref, sc)
-    np.testing.assert_array_equal(fl, fl_ref)
+    assert_flags(fl, fl_ref, E_ref, sign_margin("fp32", E_ref, sc))
 
 
 def test_empty_query_is_noop(unit_cube):
@@ -148,7 +149,7 @@ def test_edge_inputs_masks_and_flags(unit_cube, prec):
     alb = np.full((256, 3), 0.5, np.float32)
     E, L, fl = _run(m, params, pos, nrm, prec, albedo=alb, mask=mask)
     E_ref, L_ref, fl_ref, sc = _oracle(oc, params, prec, pos, nrm, albedo=alb, mask=mask)
-    np.testing.assert_array_equal(fl, fl_ref)
+    assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
     assert (E[mask == 0] == 0).all() and (L[mask == 0] == 0).all()
     assert (E[4] == 0).all() and (E[6] == 0).all()
     ok = mask.astype(bool) & ((fl_ref & 2) == 0)
@@ -204,7 +205,7 @@ def test_room_1080p_full_frame_parity(room, prec):
     ok = mask.astype(bool)
     err = _check(prec, E[ok], E_ref[ok], sc[ok])
     _check(prec, L[ok], L_ref[ok], (sc * alb / np.pi)[ok])
-    np.testing.assert_array_equal(fl, fl_ref)
+    assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
     assert (E[~ok] == 0).all()
     if prec != "fp32":
         # quantisation of the parameters themselves, reported not gated
