@@ -21,7 +21,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 MC_NEE, MC_EMIT_ON_HIT, MC_INCLUDE_DIRECT, MC_DIRECT_AT_ORIGIN = 1, 2, 4, 8
-FLAG_OUTSIDE, FLAG_BAD_INPUT, FLAG_BAD_OUTPUT = 1, 2, 4
+FLAG_OUTSIDE, FLAG_BAD_INPUT, FLAG_BAD_OUTPUT, FLAG_NEG_OUTPUT = 1, 2, 4, 16
 
 
 def build(force: bool = True) -> str:

@@ -182,8 +182,28 @@ def test_outside_box_is_clamped_and_flagged():
     pos = np.float32([[1.5, 0.5, 0.5], [1.0, 0.5, 0.5], [0.5, -0.1, 0.5]])
     nrm = np.float32([[0, 0, 1]] * 3)
     E, _, fl = O.query(c, params, pos, nrm)
-    assert fl.tolist() == [O.FLAG_OUTSIDE, 0, O.FLAG_OUTSIDE]
+    assert (fl & (0xff ^ O.FLAG_NEG_OUTPUT)).tolist() == [O.FLAG_OUTSIDE, 0, O.FLAG_OUTSIDE]
     np.testing.assert_array_equal(E[0], E[1])
+
+
+def test_negative_output_flag():
+    """Bit 4 marks a finite output with a negative channel, nothing else."""
+    c = O.config_from_workload(get_workload("unit_cube_16k"))
+    params = make_params(O.n_grid_values(c), O.mat_shapes(c), 5, -0.5, 0.5).astype(np.float64)
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0, 1, (500, 3)).astype(np.float32)
+    nrm = rng.standard_normal((500, 3)).astype(np.float32)
+    E, _, fl = O.query(c, params, pos, nrm)
+    neg = (E < 0).any(axis=1)
+    assert 0 < neg.sum() < 500
+    np.testing.assert_array_equal((fl & O.FLAG_NEG_OUTPUT) != 0, neg)
+    # flipping the sign of the output layer swaps which channels are negative
+    p2 = params.copy()
+    shapes = O.mat_shapes(c)
+    p2[-shapes[-1][0] * shapes[-1][1]:] *= -1
+    E2, _, fl2 = O.query(c, p2, pos, nrm)
+    np.testing.assert_array_equal(E2, -E)
+    np.testing.assert_array_equal((fl2 & O.FLAG_NEG_OUTPUT) != 0, (E > 0).any(axis=1))
 
 
 # ------------------------------------------------------------ SH and frequency encoding
@@ -268,7 +288,8 @@ def test_mlp_matches_numpy_matmul(wname):
     want = (mats[-1] @ h).T
     np.testing.assert_allclose(E, want, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(L, alb.astype(np.float64) * want / math.pi, rtol=1e-12, atol=1e-14)
-    assert (fl == 0).all()
+    assert ((fl & (0xff ^ O.FLAG_NEG_OUTPUT)) == 0).all()
+    np.testing.assert_array_equal((fl & O.FLAG_NEG_OUTPUT) != 0, (E < 0).any(axis=1))
     if c.n_extra:
         for q in range(4):
             np.testing.assert_allclose(x0[q, -16:], O.freq(8, float(extra[q, 0])), atol=1e-12)
