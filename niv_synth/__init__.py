@@ -12,13 +12,17 @@ from .params import make_params, xavier_bound
 from .scene import (PRIM_DTYPE, PRIM_BOX, PRIM_RECT, PRIM_DISK, make_room,
                     room_prims, enclosure_prims, disk_prim, rect_prim, box_prim,
                     scene_bounds)
-from .gbuffer import Camera, default_camera, cast_gbuffer, make_room_gbuffer
+from .gbuffer import (Camera, default_camera, cast_gbuffer, make_room_gbuffer,
+                      make_workload_gbuffer)
+from .mesh import icosphere, displaced_sphere
 from .points import unit_cube_queries, uniform_unit_normals
+from .batch import make_room_gbuffers
 
 __all__ = [
     "WORKLOADS", "Workload", "get_workload", "make_params", "xavier_bound",
     "PRIM_DTYPE", "PRIM_BOX", "PRIM_RECT", "PRIM_DISK", "make_room", "room_prims",
     "enclosure_prims", "disk_prim", "rect_prim", "box_prim", "scene_bounds",
     "Camera", "default_camera", "cast_gbuffer", "make_room_gbuffer",
-    "unit_cube_queries", "uniform_unit_normals",
+    "unit_cube_queries", "uniform_unit_normals", "make_room_gbuffers",
+    "make_workload_gbuffer", "icosphere", "displaced_sphere",
 ]

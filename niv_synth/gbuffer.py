@@ -27,7 +27,9 @@ def default_camera(width: int, height: int) -> Camera:
                   width=width, height=height)
 
 
-def primary_rays(cam: Camera):
+def camera_basis(cam: Camera):
+    """Origin, forward, right and up unit vectors and the half-extents of the
+    image plane at unit distance."""
     o = np.asarray(cam.pos, dtype=np.float64)
     fwd = np.asarray(cam.target, dtype=np.float64) - o
     fwd /= np.linalg.norm(fwd)
@@ -36,6 +38,11 @@ def primary_rays(cam: Camera):
     up = np.cross(right, fwd)
     tx = np.tan(np.radians(cam.hfov_deg) * 0.5)
     ty = tx * cam.height / cam.width
+    return o, fwd, right, up, tx, ty
+
+
+def primary_rays(cam: Camera):
+    o, fwd, right, up, tx, ty = camera_basis(cam)
     xs = (2.0 * (np.arange(cam.width) + 0.5) / cam.width - 1.0) * tx
     ys = (1.0 - 2.0 * (np.arange(cam.height) + 0.5) / cam.height) * ty
     d = (fwd[None, None, :] + xs[None, :, None] * right[None, None, :]
@@ -49,7 +56,7 @@ def _safe_inv(d):
     return 1.0 / d
 
 
-def _cast_chunk(prims, o, d, tris=None):
+def _cast_chunk(prims, o, d):
     n = d.shape[0]
     best_t = np.full(n, np.inf)
     best_n = np.zeros((n, 3))
@@ -116,62 +123,83 @@ def _cast_chunk(prims, o, d, tris=None):
             best_n = np.where(hit[:, None], nd[None, :], best_n)
             best_alb = np.where(hit[:, None], np.asarray(r["albedo"], float)[None, :], best_alb)
             best_id = np.where(hit, k, best_id)
-    if tris is not None:
-        best_t, best_n, best_alb, best_id, best_ax = _cast_tris(
-            tris, o, d, best_t, best_n, best_alb, best_id, best_ax, len(prims))
     return best_t, best_n, best_alb, best_id, best_ax, best_c
 
 
-def _cast_tris(tris, o, d, best_t, best_n, best_alb, best_id, best_ax, id_base):
-    """Moller-Trumbore over a triangle soup, vectorised over rays; only rays
-    that hit a mesh's bounding sphere are tested against its triangles."""
-    for mi, mesh in enumerate(tris):
-        v0, v1, v2 = mesh["v0"], mesh["v1"], mesh["v2"]
-        c, rad = mesh["center"], mesh["radius"]
-        oc = o - c
-        b = d @ oc
-        disc = b * b - (oc @ oc - rad * rad)
-        cand = np.nonzero(disc > 0.0)[0]
-        if cand.size == 0:
-            continue
-        dc = d[cand]
-        e1 = v1 - v0
-        e2 = v2 - v0
-        tri_best = best_t[cand].copy()
-        tri_n = np.zeros((cand.size, 3))
-        tri_hit = np.zeros(cand.size, dtype=bool)
+def _mesh_hits(cam: Camera, d, meshes, max_pairs=1 << 22):
+    """Nearest triangle hit per pixel for triangle soups: each triangle's
+    projected bounding box gives candidate pixels, and every candidate is
+    tested exactly against the pixel's primary ray (Moller-Trumbore).
+    Returns t [n] (inf = no hit), normal [n,3] facing the camera, albedo
+    [n,3], mesh index [n] (-1 = none)."""
+    o, fwd, right, up, tx, ty = camera_basis(cam)
+    W, H = cam.width, cam.height
+    n = W * H
+    best_t = np.full(n, np.inf)
+    best_n = np.zeros((n, 3))
+    best_alb = np.zeros((n, 3))
+    best_id = np.full(n, -1, np.int64)
+    for mi, mesh in enumerate(meshes):
+        v = [np.asarray(mesh[k], float) for k in ("v0", "v1", "v2")]
+        rel = [x - o[None, :] for x in v]
+        z = np.stack([r @ fwd for r in rel], 1)
+        front = (z > 1e-3).all(axis=1)
+        px = np.stack([((r @ right) / (zz * tx) + 1.0) * W / 2 - 0.5
+                       for r, zz in zip(rel, z.T)], 1)
+        py = np.stack([(1.0 - (r @ up) / (zz * ty)) * H / 2 - 0.5
+                       for r, zz in zip(rel, z.T)], 1)
+        i0 = np.clip(np.floor(px.min(1)), 0, W - 1).astype(np.int64)
+        i1 = np.clip(np.ceil(px.max(1)), 0, W - 1).astype(np.int64)
+        j0 = np.clip(np.floor(py.min(1)), 0, H - 1).astype(np.int64)
+        j1 = np.clip(np.ceil(py.max(1)), 0, H - 1).astype(np.int64)
+        bw, bh = i1 - i0 + 1, j1 - j0 + 1
+        cnt = np.where(front & (px.max(1) >= 0) & (px.min(1) <= W - 1) & (py.max(1) >= 0)
+                       & (py.min(1) <= H - 1), bw * bh, 0)
+        e1, e2 = v[1] - v[0], v[2] - v[0]
         fn = np.cross(e1, e2)
         fn /= np.linalg.norm(fn, axis=1, keepdims=True)
-        step = 512
-        for s0 in range(0, v0.shape[0], step):
-            E1, E2, V0, FN = e1[s0:s0 + step], e2[s0:s0 + step], v0[s0:s0 + step], fn[s0:s0 + step]
-            pv = np.cross(dc[:, None, :], E2[None, :, :])
-            det = np.einsum("tk,rtk->rt", E1, pv)
-            ok = np.abs(det) > 1e-12
-            inv_det = np.where(ok, 1.0 / np.where(ok, det, 1.0), 0.0)
-            tv = (o - V0)[None, :, :]
-            uu = np.einsum("rtk,rtk->rt", np.broadcast_to(tv, pv.shape), pv) * inv_det
-            qv = np.cross(np.broadcast_to(tv, pv.shape), E1[None, :, :])
-            vv = np.einsum("rk,rtk->rt", dc, qv) * inv_det
-            tt = np.einsum("tk,rtk->rt", E2, qv) * inv_det
-            valid = ok & (uu >= 0) & (vv >= 0) & (uu + vv <= 1) & (tt > 1e-6)
-            tt = np.where(valid, tt, np.inf)
-            j = np.argmin(tt, axis=1)
-            tj = tt[np.arange(cand.size), j]
-            better = tj < tri_best
-            if better.any():
-                tri_best = np.where(better, tj, tri_best)
-                nsel = FN[j]
-                nsel = np.where((np.sum(nsel * dc, axis=1) > 0)[:, None], -nsel, nsel)
-                tri_n = np.where(better[:, None], nsel, tri_n)
-                tri_hit |= better
-        idx = cand[tri_hit]
-        best_t[idx] = tri_best[tri_hit]
-        best_n[idx] = tri_n[tri_hit]
-        best_alb[idx] = np.asarray(mesh["albedo"], float)[None, :]
-        best_id[idx] = id_base + mi
-        best_ax[idx] = -1
-    return best_t, best_n, best_alb, best_id, best_ax
+        alb = np.asarray(mesh["albedo"], float)
+        tri = 0
+        while tri < len(cnt):
+            c = np.cumsum(cnt[tri:])
+            stop = tri + max(1, int(np.searchsorted(c, max_pairs, side="right")))
+            sel = np.arange(tri, stop)
+            tri = stop
+            cs = cnt[sel]
+            tot = int(cs.sum())
+            if tot == 0:
+                continue
+            ti = np.repeat(sel, cs)
+            k = np.arange(tot) - np.repeat(np.cumsum(cs) - cs, cs)
+            pix = (j0[ti] + k // bw[ti]) * W + (i0[ti] + k % bw[ti])
+            dr = d[pix]
+            pv = np.cross(dr, e2[ti])
+            det = np.sum(e1[ti] * pv, 1)
+            ok = np.abs(det) > 1e-14
+            inv = np.where(ok, 1.0 / np.where(ok, det, 1.0), 0.0)
+            tv = o[None, :] - v[0][ti]
+            uu = np.sum(tv * pv, 1) * inv
+            qv = np.cross(tv, e1[ti])
+            vv = np.sum(dr * qv, 1) * inv
+            tt = np.sum(e2[ti] * qv, 1) * inv
+            hit = ok & (uu >= 0) & (vv >= 0) & (uu + vv <= 1) & (tt > 1e-6)
+            if not hit.any():
+                continue
+            pix, tt, ti, dr = pix[hit], tt[hit], ti[hit], dr[hit]
+            order = np.lexsort((tt, pix))
+            pix, tt, ti, dr = pix[order], tt[order], ti[order], dr[order]
+            first = np.ones(len(pix), bool)
+            first[1:] = pix[1:] != pix[:-1]
+            pix, tt, ti, dr = pix[first], tt[first], ti[first], dr[first]
+            better = tt < best_t[pix]
+            pix, tt, ti, dr = pix[better], tt[better], ti[better], dr[better]
+            nn = fn[ti]
+            nn = np.where((np.sum(nn * dr, 1) > 0)[:, None], -nn, nn)
+            best_t[pix] = tt
+            best_n[pix] = nn
+            best_alb[pix] = alb[None, :]
+            best_id[pix] = mi
+    return best_t, best_n, best_alb, best_id
 
 
 def cast_gbuffer(prims, cam: Camera, tris=None, chunk: int = 1 << 18):
@@ -183,8 +211,18 @@ def cast_gbuffer(prims, cam: Camera, tris=None, chunk: int = 1 << 18):
     nrm = np.zeros((n, 3), np.float32)
     alb = np.zeros((n, 3), np.float32)
     pid = np.full(n, -1, np.int32)
+    if tris:
+        mt, mn, ma, mid = _mesh_hits(cam, d, tris)
     for s in range(0, n, chunk):
-        t, nn, aa, ii, ax, cc = _cast_chunk(prims, o, d[s:s + chunk], tris)
+        t, nn, aa, ii, ax, cc = _cast_chunk(prims, o, d[s:s + chunk])
+        if tris:
+            sl = slice(s, s + chunk)
+            m = mt[sl] < t
+            t = np.where(m, mt[sl], t)
+            nn = np.where(m[:, None], mn[sl], nn)
+            aa = np.where(m[:, None], ma[sl], aa)
+            ii = np.where(m, len(prims) + mid[sl], ii)
+            ax = np.where(m, -1, ax)
         hit = np.isfinite(t)
         p = o[None, :] + np.where(hit, t, 0.0)[:, None] * d[s:s + chunk]
         # put hits on axis-aligned faces exactly on their plane
@@ -227,3 +265,11 @@ def make_room_gbuffer(seed: int, width: int, height: int, n_boxes: int = 32,
     room = make_room(seed, n_boxes=n_boxes, n_lights=n_lights, opening_scale=scale)
     g = cast_gbuffer(room["prims_no_lights"], default_camera(width, height), tris=meshes)
     return room, g
+
+
+def make_workload_gbuffer(w, frame: int = 0):
+    """Room + G-buffer of a workload's frame, with its dynamic meshes."""
+    from .mesh import displaced_sphere
+    meshes = [displaced_sphere(seed, centre) for seed, centre in w.meshes] or None
+    W, H = w.frames[frame]
+    return make_room_gbuffer(w.scene_seeds[frame], W, H, meshes=meshes)

@@ -38,6 +38,7 @@ class Workload:
     point_seed: int = 0
     precision: str = "fp16"
     extra_values: Tuple[float, ...] = ()
+    meshes: Tuple[Tuple[int, Tuple[float, float, float]], ...] = ()  # (seed, centre)
     notes: str = ""
 
     def model_dict(self):
@@ -86,7 +87,8 @@ WORKLOADS = {
         per_level_scale=math.sqrt(2.0), sh_bands=4, n_extra=1, extra_bands=8,
         width=128, n_hidden=4, n_out=3, aabb_min=ROOM_LO, aabb_max=ROOM_HI,
         grid_init=(-0.5, 0.5), frames=((3840, 2160),), scene_seeds=(5001,),
-        param_seed=5002, precision="bf16", extra_values=(0.0, 0.37, 1.0)),
+        param_seed=5002, precision="bf16", extra_values=(0.0, 0.37, 1.0),
+        meshes=((5101, (3.6, 1.3, 5.0)), (5102, (6.6, 1.7, 6.5)))),
 }
 
 
