@@ -1,17 +1,37 @@
 """Benchmark of the Neural Irradiance Volume hot path on one MI355X.
 
-Workload: one 1920x1080 G-buffer of a 10x4x10 m room with 32 boxes (seeded,
-~4-5 % sky pixels masked), model of 16 hash-grid levels (T = 2^17, F = 2),
-16 SH of the normal, MLP 48-64-64-64-3.  A step is one fused query of the
-whole frame (G-buffer read, encoding, MLP, E and albedo * E / pi written),
-inputs resident in HBM.  The headline is the FP16-MFMA path; FP32 and BF16
-are timed on the same inputs and weights.
+Headline workload (room_1080p): one 1920x1080 G-buffer of a 10x4x10 m room
+with 32 boxes (seeded, ~5 % sky pixels masked), model of 16 hash-grid levels
+(T = 2^17, F = 2), 16 SH of the normal, MLP 48-64-64-64-3.  A step is one
+fused query of the whole frame (G-buffer read, encoding, MLP, E and
+albedo * E / pi written), inputs resident in HBM.  The headline is the
+FP16-MFMA path; FP32 and BF16 are timed on the same inputs and weights, each
+with its error against the FP64 oracle.
 
-Prints one JSON line on stdout; progress goes to stderr.
+Also measured, as extra fields of the same JSON line:
+  train       room_train: niv_train_step at B = 2^18 (FP16), the Monte Carlo
+              targets (256 spp, 3 bounces, NEE) and the sampler, and the whole
+              baking step (samples/s);
+  batched     batched_8_rooms: eight uneven G-buffers (16.3 M pixels), eight
+              models, one persistent launch replayed from a HIP graph, after
+              the autotuner; with and without the Monte Carlo fallback (64 spp);
+  field_4k    room_4k_6d: 3840x2160 G-buffer with two displaced icospheres,
+              scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16.
+
+Kernel times come from HIP events recorded on the stream the kernels are
+launched on (torch's current stream).  Prints one JSON line on stdout;
+progress goes to stderr.
+
+`--profile CASE` runs only that case's kernel a few times (for rocprofv3
+counter and trace runs): query_fp16, query_fp32, query_bf16, batched,
+field_4k, train_step, mc, copy (a 1 GiB device copy that calibrates the
+HBM byte counters).
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,6 +42,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
+# Vector ALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# (non-packed) operation per lane per clock.
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic vector work per query of a 16-level grid: ~640 integer
+# operations for corner indices and hashing, ~1000 FP32 operations for cell
+# coordinates, weights and trilinear blends.
+ALU_OPS_PER_QUERY = 1640
+# Compulsory HBM bytes per pixel: pos, nrm, albedo (3 x 12), mask 1, E and L
+# (2 x 12), flags 1.
+HBM_BYTES_PER_PX = 12 * 3 + 1 + 12 * 2 + 1
 
 
 def log(*a):
@@ -50,21 +80,365 @@ def term_scale(mats, x0):
     return (np.abs(mats[-1]) @ a).T
 
 
-def time_kernel(fn, steps, warmup):
+def time_steps(fn, steps, warmup):
+    """Per-step times (ms) from event pairs on the current stream, and the
+    whole timed region (ms per step)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
         fn()
-    stop.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return start.elapsed_time(stop) / steps, wall
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    total = ev[0].elapsed_time(ev[-1]) / steps
+    return total, per
+
+
+def stats(total, per):
+    return {"ms": total, "p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
+            "p90": float(np.percentile(per, 90))}
+
+
+def round_params(p, prec):
+    import torch
+    if prec == "fp16":
+        return p.astype(np.float16).astype(np.float64)
+    if prec == "bf16":
+        return torch.from_numpy(p).to(torch.bfloat16).to(torch.float64).numpy()
+    return p.astype(np.float64)
+
+
+def kernel_source_hash():
+    """Hash of the library sources and build flags: a counter summary taken
+    from another build does not describe this one."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2602_12949_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    with open(os.path.join(ROOT, "paper_2602_12949_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken from the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source hash: `([0-9a-f]+)`", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"\| " + re.escape(kernel_key) + r" \|[^\n]*\| ([0-9.eE+]+) \|\s*$", txt, re.M)
+    return float(m.group(1)) if m else None
+
+
+# ---------------------------------------------------------------- workloads
+def setup_1080p(dev):
+    import torch
+    from niv_synth import get_workload, make_params, make_room_gbuffer
+    from paper_2602_12949_amd import NIV
+    w = get_workload("room_1080p")
+    Wd, Ht = w.frames[0]
+    log(f"[bench] G-buffer {Wd}x{Ht} seed {w.scene_seeds[0]}")
+    _, g = make_room_gbuffer(w.scene_seeds[0], Wd, Ht)
+    m = NIV(w.model_dict())
+    params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = dict(pos=t(g["pos"]), nrm=t(g["nrm"]), alb=t(g["albedo"]), mask=t(g["mask"]),
+             params=t(params))
+    return w, g, m, params, d
+
+
+def bench_1080p(args, dev, precs):
+    import torch
+    w, g, m, params, d = setup_1080p(dev)
+    cfg = w.model_dict()
+    Wd, Ht = w.frames[0]
+    Q = Wd * Ht
+    n_valid = int(g["mask"].sum())
+    results, outputs = {}, {}
+    for prec in precs:
+        prepared = m.prepare(d["params"], prec)
+        frame, outs = m.frame(d["pos"], d["nrm"], prepared, albedo=d["alb"], mask=d["mask"])
+        total, per = time_steps(lambda: m.query_frames([frame], prec), args.steps, args.warmup)
+        graph = m.capture([frame], prec)
+        gtotal, gper = time_steps(graph.launch, args.steps, args.warmup)
+        torch.cuda.synchronize()
+        outputs[prec] = outs[0].reshape(-1, 3).cpu().numpy().astype(np.float64)
+        ms = min(total, gtotal)
+        results[prec] = {"ms_per_frame": ms, "launch": stats(total, per),
+                         "graph": stats(gtotal, gper),
+                         "queries_per_s": n_valid / (ms * 1e-3),
+                         "mlp_tflops": mlp_flops(cfg) * n_valid / (ms * 1e-3) / 1e12,
+                         "alu_tops": ALU_OPS_PER_QUERY * n_valid / (ms * 1e-3) / 1e12,
+                         "hbm_compulsory_GBs": HBM_BYTES_PER_PX * Q / (ms * 1e-3) / 1e9}
+        log(f"[bench] room_1080p {prec}: {ms:.4f} ms/frame (launch p50 {np.median(per):.4f}, "
+            f"graph p50 {np.median(gper):.4f}), {n_valid / (ms * 1e-3) / 1e9:.3f} G queries/s")
+        del graph
+    return w, g, params, results, outputs, n_valid, Q
+
+
+def errors_1080p(w, g, params, outputs):
+    import oracle as O
+    oc = O.config_from_workload(w)
+    pos, nrm, mask = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3), g["mask"].reshape(-1)
+    ok = mask.astype(bool)
+    E_master = None
+    errors = {}
+    for prec, E in outputs.items():
+        pr = round_params(params, prec)
+        ref, _, _, x0 = O.query(oc, pr, pos, nrm, mask=mask, want_x0=True)
+        if prec == "fp32":
+            E_master = ref
+        a, b = E[ok], ref[ok]
+        sc = term_scale(O.split_params(oc, pr)[1:], x0[ok])
+        del x0
+        floor = 1e-3 * np.abs(b).max()
+        errors[prec] = {
+            "max_rel_err": float(np.max(np.abs(a - b) / np.maximum(np.abs(b), sc))),
+            "max_rel_err_floored_1e-3": float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor))),
+            "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "vs": "FP64 oracle on the same rounded parameters, every valid pixel",
+        }
+        log(f"[bench] room_1080p {prec} error vs oracle: {errors[prec]}")
+    if E_master is None:
+        E_master, _, _ = O.query(oc, params.astype(np.float64), pos, nrm, mask=mask)
+    for prec, E in outputs.items():
+        if prec != "fp32":
+            errors[prec]["rel_l2_vs_fp32_master"] = float(
+                np.linalg.norm(E[ok] - E_master[ok]) / np.linalg.norm(E_master[ok]))
+    return errors
+
+
+def cpu_baseline_1080p(w, g, params):
+    import oracle as O
+    oc = O.config_from_workload(w)
+    pos, nrm, mask = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3), g["mask"].reshape(-1)
+    n_valid = int(mask.sum())
+    p64 = params.astype(np.float64)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    O.set_threads(cores)
+    log(f"[bench] CPU oracle: 3 full frames on {cores} threads, 1/16 frame on 1 thread")
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        O.query(oc, p64, pos, nrm, mask=mask)
+        runs.append(time.perf_counter() - t0)
+    med = float(np.median(runs))
+    O.set_threads(1)
+    k = len(pos) // 16
+    t0 = time.perf_counter()
+    O.query(oc, p64, pos[:k], nrm[:k], mask=mask[:k])
+    one = (time.perf_counter() - t0) * 16
+    O.set_threads(cores)
+    return {"value": med * 1e3, "unit": "ms/frame", "cores": cores, "kind": "oracle",
+            "sample": "three full 1920x1080 frames of room_1080p (FP64 forward, OpenMP over "
+                      "pixels), median; plus 1/16 of the frame on one thread, scaled",
+            "queries_per_s": n_valid / med, "one_thread_ms_per_frame": one * 1e3,
+            "runs_s": runs}
+
+
+def bench_train(args, dev):
+    import torch
+    from niv_synth import get_workload, make_params, make_room
+    from paper_2602_12949_amd import NIV, McScene, Trainer
+    from paper_2602_12949_amd.bake import lr_at
+    w = get_workload("room_train")
+    m = NIV(w.model_dict())
+    B = w.n_queries
+    params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+    p = torch.from_numpy(params).to(dev)
+    room = make_room(w.scene_seeds[0])
+    scene = McScene(room["prims"])
+    tr = Trainer(m, p, "fp16", max_batch=B)
+    lo, hi = w.aabb_min, w.aabb_max
+    n_surf = int(round(0.2 * B))
+    x, n = scene.sample_points(lo, hi, B, n_surf, seed=1, device=dev)
+    E = torch.empty((B, 3), dtype=torch.float32, device=dev)
+    valid = torch.empty(B, dtype=torch.uint8, device=dev)
+    scene.targets(x, n, 256, 3, seed=2, out=(E, valid))
+    steps = max(3, args.steps // 10)
+    tt, tp = time_steps(lambda: tr.step(x, n, E, 1e-3, valid=valid), steps * 4, 3)
+    st, sp = time_steps(lambda: scene.sample_points(lo, hi, B, n_surf, seed=3, out=(x, n)),
+                        steps, 2)
+    mt, mp = time_steps(lambda: scene.targets(x, n, 256, 3, seed=4, out=(E, valid)), 3, 1)
+    state = {"k": 0}
+
+    def whole():
+        state["k"] += 1
+        s = state["k"]
+        scene.sample_points(lo, hi, B, n_surf, seed=(7 << 20) + s, out=(x, n))
+        scene.targets(x, n, 256, 3, seed=(7 << 20) + s + (1 << 19), out=(E, valid))
+        tr.step(x, n, E, lr_at(s, 4000), valid=valid)
+
+    et, ep = time_steps(whole, 3, 1)
+    res = {
+        "workload": "room_train: B=2^18 points/step (80 % volume, 20 % surface), targets at "
+                    "256 spp, 3 bounces, NEE to 2 rect lights; model of room_1080p, FP16",
+        "batch": B,
+        "train_step": {**stats(tt, tp), "samples_per_s": B / (tt * 1e-3)},
+        "sampler": {**stats(st, sp), "points_per_s": B / (st * 1e-3)},
+        "mc_targets": {**stats(mt, mp), "points_per_s": B / (mt * 1e-3),
+                       "spp": 256, "bounces": 3},
+        "bake_step": {**stats(et, ep), "samples_per_s": B / (et * 1e-3)},
+        "valid_fraction": float(valid.float().mean().item()),
+    }
+    log(f"[bench] train: step {tt:.3f} ms ({B / (tt * 1e-3) / 1e6:.2f} M samples/s), "
+        f"MC {mt:.1f} ms ({B / (mt * 1e-3) / 1e6:.3f} M points/s), bake step {et:.1f} ms")
+    return res
+
+
+def bench_batched(args, dev):
+    import torch
+    from niv_synth import get_workload, make_params, make_room_gbuffers
+    from paper_2602_12949_amd import NIV, McScene, niv as N
+    w = get_workload("batched_8_rooms")
+    log(f"[bench] batched_8_rooms: building 8 G-buffers")
+    rooms = make_room_gbuffers(w.scene_seeds, w.frames)
+    m = NIV(w.model_dict())
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    prepared, frames, keep = [], [], []
+    rng = np.random.default_rng(4200)
+    n_px = n_valid = 0
+    for k, (room, g) in enumerate(rooms):
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed + k, *w.grid_init)
+        pm = m.prepare(t(params), "fp16")
+        mask = g["mask"].reshape(-1)
+        inf = np.zeros(len(mask), np.uint8)
+        vi = np.nonzero(mask)[0]
+        inf[rng.choice(vi, size=int(0.005 * len(vi)), replace=False)] = 1
+        sc = McScene(room["prims"])
+        d = dict(pos=t(g["pos"]), nrm=t(g["nrm"]), alb=t(g["albedo"]), mask=t(g["mask"]),
+                 inf=t(inf))
+        f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"],
+                          in_flags=d["inf"], scene=sc)
+        frames.append(f)
+        keep.append((pm, d, outs, sc))
+        n_px += len(mask)
+        n_valid += len(vi)
+    tune = m.autotune(frames, "fp16")
+    log(f"[bench] autotune: {tune}")
+    graph = m.capture(frames, "fp16")
+    qt, qp = time_steps(graph.launch, args.steps, args.warmup)
+    fb = m.fallback(flag_mask=N.FLAG_OUTSIDE | N.FLAG_BAD_OUTPUT, spp=64, bounces=3,
+                    mc_flags=N.MC_NEE, seed=11)
+    ws = m.fallback_workspace(1 << 20, device=dev)
+    gfb = m.capture(frames, "fp16", fb, ws)
+    ft, fp = time_steps(gfb.launch, max(5, args.steps // 10), 2)
+    torch.cuda.synchronize()
+    flagged = int(ws[:4].view(torch.int32).item())
+    taken = sum(int(((o[2] & 8) != 0).sum().item()) for _, _, o, _ in keep)
+    res = {
+        "workload": "batched_8_rooms: 8 G-buffers 1280x720 .. 2560x1440 (8 rooms, 8 models), "
+                    "one persistent launch from a HIP graph, FP16",
+        "pixels": n_px, "valid_pixels": n_valid,
+        "query": {**stats(qt, qp), "Mpix_per_s": n_px / (qt * 1e-3) / 1e6,
+                  "queries_per_s": n_valid / (qt * 1e-3)},
+        "with_fallback": {**stats(ft, fp), "flagged": flagged, "estimated": taken,
+                          "spp": 64, "bounces": 3,
+                          "triggers": "caller flags on 0.5 % of valid pixels, outside the "
+                                      "volume, non-finite E"},
+        "autotune": {"block": tune["block"], "blocks_per_cu": tune["blocks_per_cu"],
+                     "candidates": tune["candidates"]},
+        "alu_frac": ALU_OPS_PER_QUERY * n_valid / (qt * 1e-3) / 1e12 / ALU_PEAK_TOPS,
+    }
+    # sampled error of the query-only outputs against the oracle, frame by frame
+    import oracle as O
+    oc = O.config_from_workload(w)
+    graph.launch()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, (room, g) in enumerate(rooms):
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed + k, *w.grid_init)
+        pos, nrm, mask = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3), g["mask"].reshape(-1)
+        s = rng.choice(len(pos), 4096, replace=False)
+        s = s[mask[s] > 0]
+        ref, _, _ = O.query(oc, round_params(params, "fp16"), pos[s], nrm[s])
+        E = keep[k][2][0].reshape(-1, 3).cpu().numpy().astype(np.float64)[s]
+        worst = max(worst, float(np.linalg.norm(E - ref) / np.linalg.norm(ref)))
+    res["sampled_rel_l2_max_over_frames"] = worst
+    log(f"[bench] batched: {qt:.3f} ms/batch ({n_px / (qt * 1e-3) / 1e6:.0f} M px/s), "
+        f"with fallback {ft:.3f} ms ({flagged} flagged), sampled rel-L2 {worst:.2e}")
+    del graph, gfb
+    return res
+
+
+def bench_field_4k(args, dev):
+    import torch
+    from niv_synth import get_workload, make_params, make_workload_gbuffer
+    from paper_2602_12949_amd import NIV
+    w = get_workload("room_4k_6d")
+    log(f"[bench] room_4k_6d: building the 3840x2160 G-buffer with meshes")
+    room, g = make_workload_gbuffer(w)
+    m = NIV(w.model_dict())
+    cfg = w.model_dict()
+    params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pm = m.prepare(t(params), "bf16")
+    d = dict(pos=t(g["pos"]), nrm=t(g["nrm"]), alb=t(g["albedo"]), mask=t(g["mask"]))
+    mask = g["mask"].reshape(-1)
+    n_valid = int(mask.sum())
+    per_t = {}
+    import oracle as O
+    oc = O.config_from_workload(w)
+    rng = np.random.default_rng(5)
+    s = rng.choice(len(mask), 8192, replace=False)
+    s = s[mask[s] > 0]
+    pos, nrm = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3)
+    for tv in w.extra_values:
+        f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"], extra=(tv,))
+        graph = m.capture([f], "bf16")
+        tt, tp = time_steps(graph.launch, args.steps, args.warmup)
+        torch.cuda.synchronize()
+        E = outs[0].reshape(-1, 3).cpu().numpy().astype(np.float64)[s]
+        ex = np.full((len(s), 1), tv, np.float32)
+        ref, _, _ = O.query(oc, round_params(params, "bf16"), pos[s], nrm[s], extra=ex)
+        err = float(np.linalg.norm(E - ref) / np.linalg.norm(ref))
+        per_t[str(tv)] = {**stats(tt, tp), "sampled_rel_l2": err}
+        log(f"[bench] room_4k_6d t={tv}: {tt:.4f} ms/frame, sampled rel-L2 {err:.2e}")
+        del graph
+    ms = float(np.mean([v["ms"] for v in per_t.values()]))
+    fl = mlp_flops(cfg) * n_valid
+    return {
+        "workload": "room_4k_6d: 3840x2160 G-buffer, room + 2 displaced icospheres "
+                    "(20,480 triangles each), 16 levels T=2^19, MLP 64-128^4-3, BF16",
+        "pixels": len(mask), "valid_pixels": n_valid, "ms_per_frame": ms, "per_t": per_t,
+        "mlp_tflops": fl / (ms * 1e-3) / 1e12,
+        "mfma_frac": fl / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"],
+    }
+
+
+# ---------------------------------------------------------------- profiling cases
+def profile_case(case, steps):
+    import torch
+    dev = torch.device("cuda:0")
+    if case == "copy":
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[profile] copy: {steps} x 1 GiB device-to-device")
+        return
+    if case.startswith("query_"):
+        prec = case.split("_")[1]
+        w, g, m, params, d = setup_1080p(dev)
+        pm = m.prepare(d["params"], prec)
+        f, _ = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"])
+        for _ in range(steps):
+            m.query_frames([f], prec)
+        torch.cuda.synchronize()
+        log(f"[profile] {case}: {steps} launches")
+        return
+    raise SystemExit(f"unknown profile case {case}")
 
 
 def main():
@@ -74,102 +448,59 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precisions", default="fp16,fp32,bf16")
+    ap.add_argument("--only", default="query,train,batched,field_4k",
+                    help="comma list of parts to run")
+    ap.add_argument("--profile", default=None, help="run one kernel case for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              "(the query shards per pixel with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(the query shards per pixel with no exchange and is measured on one GPU)",
+              file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        profile_case(args.profile, args.steps)
+        return
 
     import torch
-    from niv_synth import get_workload, make_params, make_room_gbuffer
-    from paper_2602_12949_amd import NIV
-
-    w = get_workload("room_1080p")
-    cfg = w.model_dict()
-    Wd, Ht = w.frames[0]
-    log(f"[bench] building G-buffer {Wd}x{Ht} seed {w.scene_seeds[0]}")
-    _, g = make_room_gbuffer(w.scene_seeds[0], Wd, Ht)
-    m = NIV(cfg)
-    n_grid = m.n_grid_values
-    din = cfg["n_levels"] * 2 + 16
-    shapes = [(cfg["width"], din)] + [(cfg["width"], cfg["width"])] * (cfg["n_hidden"] - 1) + \
-        [(cfg["n_out"], cfg["width"])]
-    params = make_params(n_grid, shapes, w.param_seed, *w.grid_init)
     dev = torch.device("cuda:0")
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    pos, nrm, alb = t(g["pos"]), t(g["nrm"]), t(g["albedo"])
-    mask = t(g["mask"])
-    p_d = t(params)
-    Q = Wd * Ht
-    n_valid = int(g["mask"].sum())
-
-    results = {}
-    outputs = {}
-    for prec in args.precisions.split(","):
-        prepared = m.prepare(p_d, prec)
-        frame, outs = m.frame(pos, nrm, prepared, albedo=alb, mask=mask)
-        fn = lambda: m.query_frames([frame], prec)
-        ms, wall = time_kernel(fn, args.steps, args.warmup)
-        torch.cuda.synchronize()
-        outputs[prec] = outs[0].reshape(-1, 3).cpu().numpy().astype(np.float64)
-        results[prec] = {"ms_per_frame": ms, "queries_per_s": n_valid / (ms * 1e-3),
-                         "wall_s": wall}
-        log(f"[bench] {prec}: {ms:.4f} ms/frame, {n_valid / (ms * 1e-3) / 1e9:.3f} G valid queries/s")
-
-    head = "fp16" if "fp16" in results else list(results)[0]
+    parts = set(args.only.split(","))
+    precs = args.precisions.split(",")
+    w, g, params, results, outputs, n_valid, Q = bench_1080p(args, dev, precs)
+    head = "fp16" if "fp16" in results else precs[0]
     ms = results[head]["ms_per_frame"]
-    bytes_per_px = 12 * 3 + 1 + 12 * 2 + 1  # pos, nrm, albedo, mask, E, L, flags
-    flops = mlp_flops(cfg) * n_valid
-    roof = {
-        "bound": "mfma",
-        "achieved": flops / (ms * 1e-3) / 1e12,
-        "peak": MFMA_PEAK_TFLOPS[head],
-        "unit": "TFLOP/s",
-        "traffic": None,
-    }
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    hbm = bytes_per_px * Q / (ms * 1e-3) / 1e9
+    cfg = w.model_dict()
 
-    cpu = None
-    errors = {}
+    # rooflines of the query kernel; the tightest (highest fraction) is the bound
+    alu = ALU_OPS_PER_QUERY * n_valid / (ms * 1e-3) / 1e12
+    mfma = mlp_flops(cfg) * n_valid / (ms * 1e-3) / 1e12
+    hbm = HBM_BYTES_PER_PX * Q / (ms * 1e-3) / 1e9
+    bounds = {
+        "alu": {"achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                "per_query": ALU_OPS_PER_QUERY},
+        "mfma": {"achieved": mfma, "peak": MFMA_PEAK_TFLOPS[head], "unit": "TFLOP/s",
+                 "per_query": mlp_flops(cfg)},
+        "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "per_query": HBM_BYTES_PER_PX},
+    }
+    for b in bounds.values():
+        b["frac"] = b["achieved"] / b["peak"]
+    bound = max(bounds, key=lambda k: bounds[k]["frac"])
+    traffic = measured_traffic(f"k_query {head} room_1080p")
+    roof = {"bound": bound, "achieved": bounds[bound]["achieved"], "peak": bounds[bound]["peak"],
+            "unit": bounds[bound]["unit"], "frac": bounds[bound]["frac"], "traffic": traffic,
+            "kernel": f"k_query ({head}, room_1080p)", "all": bounds}
+
+    cpu, errors = None, {}
     if not args.no_cpu:
-        import oracle as O
-        oc = O.config_from_workload(w)
-        cores = os.cpu_count()
-        O.set_threads(cores)
-        log(f"[bench] CPU oracle: full frame, {cores} threads")
-        p64 = params.astype(np.float64)
-        t0 = time.perf_counter()
-        E_ref, _, _ = O.query(oc, p64, g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3),
-                              mask=g["mask"].reshape(-1))
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": cpu_s * 1e3, "unit": "ms/frame", "cores": cores, "kind": "oracle",
-               "sample": "one full 1920x1080 frame, FP64, OpenMP over pixels",
-               "queries_per_s": n_valid / cpu_s}
-        ok = g["mask"].reshape(-1).astype(bool)
-        for prec, E in outputs.items():
-            if prec == "fp16":
-                pr = params.astype(np.float16).astype(np.float64)
-            elif prec == "bf16":
-                pr = torch.from_numpy(params).to(torch.bfloat16).to(torch.float64).numpy()
-            else:
-                pr = p64
-            ref, _, _, x0 = O.query(oc, pr, g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3),
-                                    mask=g["mask"].reshape(-1), want_x0=True)
-            a, b = E[ok], ref[ok]
-            sc = term_scale(O.split_params(oc, pr)[1:], x0[ok])
-            del x0
-            floor = 1e-3 * np.abs(b).max()
-            errors[prec] = {
-                "max_rel_err": float(np.max(np.abs(a - b) / np.maximum(np.abs(b), sc))),
-                "max_rel_err_floored_1e-3": float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor))),
-                "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
-                "vs": "oracle on the same rounded parameters",
-            }
-            if prec != "fp32":
-                errors[prec]["rel_l2_vs_fp32_master"] = float(
-                    np.linalg.norm(a - E_ref[ok]) / np.linalg.norm(E_ref[ok]))
-            log(f"[bench] {prec} error vs oracle: {errors[prec]}")
+        cpu = cpu_baseline_1080p(w, g, params)
+        errors = errors_1080p(w, g, params, outputs)
+    extra = {}
+    if "train" in parts:
+        extra["train"] = bench_train(args, dev)
+    if "batched" in parts:
+        extra["batched"] = bench_batched(args, dev)
+    if "field_4k" in parts:
+        extra["field_4k"] = bench_field_4k(args, dev)
 
     line = {
         "metric": "1080p NIV query ms/frame, FP16-MFMA vs FP32 at stated err; train samples/s",
@@ -188,11 +519,13 @@ def main():
                                "16 levels T=2^17 F=2, SH-16, MLP 48-64-64-64-3",
                    "pixels": Q, "valid_pixels": n_valid},
         "queries_per_s": results[head]["queries_per_s"],
+        "fp32_ms_per_frame": results.get("fp32", {}).get("ms_per_frame"),
+        "train_samples_per_s": extra.get("train", {}).get("train_step", {}).get("samples_per_s"),
         "precisions": results,
         "errors_vs_oracle": errors,
-        "hbm_compulsory_GBs": hbm,
         "roofline": roof,
         "cpu_baseline": cpu,
+        **extra,
     }
     print(json.dumps(line), flush=True)
 

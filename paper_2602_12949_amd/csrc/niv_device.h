@@ -15,6 +15,7 @@ typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
@@ -37,13 +38,22 @@ template <> struct Prec<NIV_FP16> {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a),
                                                       __builtin_bit_cast(h8, b), c, 0, 0, 0);
     }
+    // A K = 16 product issued as the K = 32 instruction with the upper half
+    // of each lane's operands zero: lane (g, j) then pairs the same four
+    // products as the K = 16 layout, and the sum is unchanged.
     __device__ static f4 mma_half(u2 a, u2 b, f4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a),
-                                                     __builtin_bit_cast(h4, b), c, 0, 0, 0);
+        return mma((u4){a.x, a.y, 0u, 0u}, (u4){b.x, b.y, 0u, 0u}, c);
     }
     __device__ static uint32_t pack(float x, float y) {
         h2 v = __builtin_convertvector((f2){x, y}, h2);
         return __builtin_bit_cast(uint32_t, v);
+    }
+    // ReLU after rounding: a half with its sign bit set is a negative 16-bit
+    // integer, so a packed integer max with 0 zeroes exactly the negative
+    // halves (rounding preserves the sign, so this equals rounding the ReLU).
+    __device__ static uint32_t pack_relu(float x, float y) {
+        s2 v = __builtin_bit_cast(s2, __builtin_convertvector((f2){x, y}, h2));
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (s2){0, 0}));
     }
     __device__ static f2 unpack(uint32_t w) {
         return __builtin_convertvector(__builtin_bit_cast(h2, w), f2);
@@ -80,6 +90,11 @@ template <> struct Prec<NIV_BF16> {
 template <> struct Prec<NIV_FP32> {
     static constexpr int ES = 4;
     static constexpr int EPO = 1;
+    // ReLU as a signed integer max: negative floats are negative integers
+    __device__ static float relu(float x) {
+        const int32_t i = (int32_t)f2u(x);
+        return u2f((uint32_t)(i > 0 ? i : 0));
+    }
     __device__ static f4 mma1(float a, float b, f4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }

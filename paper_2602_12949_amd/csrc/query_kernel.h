@@ -314,10 +314,10 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     for (int t = 0; t < TB; ++t)
 #pragma unroll
                         for (int ob = 0; ob < S::NOB; ++ob) {
-                            bh[t][4 * ob] = fmaxf(acc[t][ob].x, 0.f);
-                            bh[t][4 * ob + 1] = fmaxf(acc[t][ob].y, 0.f);
-                            bh[t][4 * ob + 2] = fmaxf(acc[t][ob].z, 0.f);
-                            bh[t][4 * ob + 3] = fmaxf(acc[t][ob].w, 0.f);
+                            bh[t][4 * ob] = Prec<P>::relu(acc[t][ob].x);
+                            bh[t][4 * ob + 1] = Prec<P>::relu(acc[t][ob].y);
+                            bh[t][4 * ob + 2] = Prec<P>::relu(acc[t][ob].z);
+                            bh[t][4 * ob + 3] = Prec<P>::relu(acc[t][ob].w);
                         }
                     if constexpr (TRAIN) {
                         uint32_t *xs = reinterpret_cast<uint32_t *>(a.x_save + chunk * CHUNK_BYTES) +
@@ -367,11 +367,14 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     for (int t = 0; t < TB; ++t)
 #pragma unroll
                         for (int ob = 0; ob < S::NOB; ++ob) {
-                            const float r0 = fmaxf(acc[t][ob].x, 0.f), r1 = fmaxf(acc[t][ob].y, 0.f);
-                            const float r2 = fmaxf(acc[t][ob].z, 0.f), r3 = fmaxf(acc[t][ob].w, 0.f);
-                            bh[0][t][2 * ob] = Prec<P>::pack(r0, r1);
-                            bh[0][t][2 * ob + 1] = Prec<P>::pack(r2, r3);
-                            if constexpr (O::NS == 2) {
+                            if constexpr (O::NS == 1) {
+                                bh[0][t][2 * ob] = Prec<P>::pack_relu(acc[t][ob].x, acc[t][ob].y);
+                                bh[0][t][2 * ob + 1] = Prec<P>::pack_relu(acc[t][ob].z, acc[t][ob].w);
+                            } else {
+                                const float r0 = fmaxf(acc[t][ob].x, 0.f), r1 = fmaxf(acc[t][ob].y, 0.f);
+                                const float r2 = fmaxf(acc[t][ob].z, 0.f), r3 = fmaxf(acc[t][ob].w, 0.f);
+                                bh[0][t][2 * ob] = Prec<P>::pack(r0, r1);
+                                bh[0][t][2 * ob + 1] = Prec<P>::pack(r2, r3);
                                 bh[O::NS - 1][t][2 * ob] = Prec<P>::pack_lo(r0, r1, bh[0][t][2 * ob]);
                                 bh[O::NS - 1][t][2 * ob + 1] = Prec<P>::pack_lo(r2, r3, bh[0][t][2 * ob + 1]);
                             }

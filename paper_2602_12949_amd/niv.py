@@ -184,6 +184,13 @@ class NIV:
         _check(lib().niv_sizes(self._h, FP32, C.byref(n_p), C.byref(n_g), None), "niv_sizes")
         return n_g.value
 
+    def mat_shapes(self):
+        """(out, in) of every weight matrix, input layer first (row-major
+        blocks after the grid in the parameter vector)."""
+        c = self.cfg
+        W = c["width"]
+        return [(W, self.input_dim)] + [(W, W)] * (c["n_hidden"] - 1) + [(c["n_out"], W)]
+
     def level_info(self):
         import numpy as np
         L = self.cfg["n_levels"]
