@@ -167,6 +167,9 @@ def bench_1080p(args, dev, precs):
     for prec in precs:
         prepared = m.prepare(d["params"], prec)
         frame, outs = m.frame(d["pos"], d["nrm"], prepared, albedo=d["alb"], mask=d["mask"])
+        tune = m.autotune([frame], prec)
+        log(f"[bench] room_1080p {prec} autotune: block {tune['block']} x {tune['blocks_per_cu']}"
+            f" per CU, xcd order {tune['xcd_order']}: {tune['candidates']}")
         total, per = time_steps(lambda: m.query_frames([frame], prec), args.steps, args.warmup)
         graph = m.capture([frame], prec)
         gtotal, gper = time_steps(graph.launch, args.steps, args.warmup)
@@ -174,6 +177,7 @@ def bench_1080p(args, dev, precs):
         outputs[prec] = outs[0].reshape(-1, 3).cpu().numpy().astype(np.float64)
         ms = min(total, gtotal)
         results[prec] = {"ms_per_frame": ms, "launch": stats(total, per),
+                         "autotune": {k: tune[k] for k in ("block", "blocks_per_cu", "xcd_order")},
                          "graph": stats(gtotal, gper),
                          "queries_per_s": n_valid / (ms * 1e-3),
                          "mlp_tflops": mlp_flops(cfg) * n_valid / (ms * 1e-3) / 1e12,
@@ -346,7 +350,7 @@ def bench_batched(args, dev):
                           "triggers": "caller flags on 0.5 % of valid pixels, outside the "
                                       "volume, non-finite E"},
         "autotune": {"block": tune["block"], "blocks_per_cu": tune["blocks_per_cu"],
-                     "candidates": tune["candidates"]},
+                     "xcd_order": tune["xcd_order"], "candidates": tune["candidates"]},
         "alu_frac": ALU_OPS_PER_QUERY * n_valid / (qt * 1e-3) / 1e12 / ALU_PEAK_TOPS,
     }
     # sampled error of the query-only outputs against the oracle, frame by frame
@@ -416,7 +420,7 @@ def bench_field_4k(args, dev):
 
 
 # ---------------------------------------------------------------- profiling cases
-def profile_case(case, steps):
+def profile_case(case, steps, tune=None):
     import torch
     dev = torch.device("cuda:0")
     if case == "copy":
@@ -431,8 +435,13 @@ def profile_case(case, steps):
     if case.startswith("query_"):
         prec = case.split("_")[1]
         w, g, m, params, d = setup_1080p(dev)
+        if tune:
+            m.set_tune(prec, *tune)
         pm = m.prepare(d["params"], prec)
         f, _ = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"])
+        for _ in range(steps):   # warm-up: clocks and caches as in the timed loop of the bench
+            m.query_frames([f], prec)
+        torch.cuda.synchronize()
         for _ in range(steps):
             m.query_frames([f], prec)
         torch.cuda.synchronize()
@@ -451,6 +460,8 @@ def main():
     ap.add_argument("--only", default="query,train,batched,field_4k",
                     help="comma list of parts to run")
     ap.add_argument("--profile", default=None, help="run one kernel case for rocprofv3")
+    ap.add_argument("--tune", default=None,
+                    help="launch shape for --profile: block,blocks_per_cu,xcd_order")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -458,7 +469,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
-        profile_case(args.profile, args.steps)
+        tune = [int(v) for v in args.tune.split(",")] if args.tune else None
+        profile_case(args.profile, args.steps, tune)
         return
 
     import torch

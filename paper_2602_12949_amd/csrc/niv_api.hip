@@ -214,6 +214,7 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, n
         const int n = n_frames - f0 < kMaxFrames ? n_frames - f0 : kMaxFrames;
         QueryArgs a;
         fill_args(h, frames + f0, n, prec, a);
+        a.xcd_order = tu.xcd_order;
         if (launch_query(h->m, a, prec, tu, stream) != hipSuccess) return NIV_ERR_HIP;
     }
     return NIV_OK;
@@ -250,7 +251,9 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
     a.fb_count = cnt;
     a.fb_cap = cap;
     a.fb_mask = fb->flag_mask;
-    if (launch_query(h->m, a, prec, tune_of(h, prec), stream) != hipSuccess) return NIV_ERR_HIP;
+    const LaunchTune tu = tune_of(h, prec);
+    a.xcd_order = tu.xcd_order;
+    if (launch_query(h->m, a, prec, tu, stream) != hipSuccess) return NIV_ERR_HIP;
     FbArgs b;
     memset(&b, 0, sizeof(b));
     b.list = list;
@@ -282,6 +285,7 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
     if (n_frames < 1 || n_frames > kMaxFrames) return NIV_ERR_INVALID_ARG;
     static const int blocks[2] = {256, 512};
     static const int per_cu[3] = {0, 1, 2};
+    static const int orders[2] = {0, 1};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return NIV_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NIV_ERR_HIP; }
@@ -290,10 +294,12 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
     int k = 0;
     niv_status st = NIV_OK;
     for (int b = 0; b < 2 && st == NIV_OK; ++b)
-        for (int c = 0; c < 3 && st == NIV_OK; ++c, ++k) {
-            LaunchTune tu = {blocks[b], per_cu[c]};
+        for (int c = 0; c < 3 && st == NIV_OK; ++c)
+        for (int o = 0; o < 2 && st == NIV_OK; ++o, ++k) {
+            LaunchTune tu = {blocks[b], per_cu[c], orders[o]};
             QueryArgs a;
             fill_args(h, frames, n_frames, prec, a);
+            a.xcd_order = tu.xcd_order;
             float ms = 1e30f;
             for (int rep = 0; rep < 12 && st == NIV_OK; ++rep) {
                 if (hipEventRecord(e0, stream) != hipSuccess ||
@@ -306,9 +312,10 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
                 if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = NIV_ERR_HIP; break; }
                 if (rep >= 2 && t < ms) ms = t;  // best of 10 after 2 warm-up launches
             }
-            if (out && k < 8) {
+            if (out && k < 16) {
                 out->block[k] = tu.block;
                 out->blocks_per_cu[k] = tu.blocks_per_cu;
+                out->xcd_order[k] = tu.xcd_order;
                 out->ms[k] = ms;
             }
             if (ms < best_ms) { best_ms = ms; best = tu; }
@@ -322,8 +329,21 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
         out->n = k;
         out->chosen_block = best.block;
         out->chosen_blocks_per_cu = best.blocks_per_cu;
+        out->chosen_xcd_order = best.xcd_order;
         out->chosen_ms = best_ms;
     }
+    return NIV_OK;
+}
+
+niv_status niv_set_tune(niv_handle *h, niv_precision prec, int32_t block, int32_t blocks_per_cu,
+                        int32_t xcd_order)
+{
+    if (!h || (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16)) return NIV_ERR_INVALID_ARG;
+    if ((block != 256 && block != 512) || blocks_per_cu < 0 || blocks_per_cu > 64 ||
+        (xcd_order != 0 && xcd_order != 1))
+        return NIV_ERR_INVALID_ARG;
+    h->m.tune[prec] = LaunchTune{block, blocks_per_cu, xcd_order};
+    h->m.tuned[prec] = true;
     return NIV_OK;
 }
 

@@ -69,7 +69,7 @@ struct QueryArgs {
     float *dE;                // [count][3] d(loss)/dE without the 1/(3n) factor
     float *loss;              // device scalar, accumulates the Eq. 3 loss
     float loss_eps;           // 0.01 (Eq. 3)
-    int32_t pad1;
+    int32_t xcd_order;        // tile order, see LaunchTune
     FrameArgs f[kMaxFrames];
 };
 
@@ -81,7 +81,9 @@ enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kNumKinds = 3 };
 struct LaunchTune {
     int block;
     int blocks_per_cu;
+    int xcd_order;   // 1: each XCD walks a contiguous eighth of the tiles
 };
+constexpr int kXcds = 8;  // workgroups are dealt to the XCDs round robin
 
 // Operand-block layout of a prepared model (see the prepare kernel).
 struct OpLayout {

@@ -165,6 +165,7 @@ LaunchTune default_tune(int kind, niv_precision prec)
     // FP32 operands need twice the LDS per wave; smaller workgroups fit more of them
     t.block = (prec == NIV_FP32 && kind != kWide6D) ? 256 : 512;
     t.blocks_per_cu = 0;
+    t.xcd_order = 1;
     return t;
 }
 

@@ -52,7 +52,17 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
     uint32_t *stage = reinterpret_cast<uint32_t *>(smem + (WLDS ? O::W_BYTES : 0)) + wave * 64 * O::ROW_DW;
     int staged = -1;  // frame whose operand block is in LDS (block-uniform)
 
-    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    // Tile order.  Workgroup b runs on XCD b % 8; with xcd_order each XCD
+    // takes a contiguous eighth of the tiles (pixels close on screen touch
+    // the same grid cells and now share that XCD's L2), else tiles are
+    // strided over all workgroups.  Both are uniform over the workgroup.
+    const bool by_xcd = a.xcd_order && (gridDim.x % kXcds) == 0;
+    const int64_t per_xcd = (a.n_tiles + kXcds - 1) / kXcds;
+    const int64_t first = by_xcd ? (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds
+                                 : (int64_t)blockIdx.x;
+    const int64_t last = by_xcd ? (int64_t)(blockIdx.x % kXcds + 1) * per_xcd : a.n_tiles;
+    const int64_t step = by_xcd ? (int64_t)(gridDim.x / kXcds) : (int64_t)gridDim.x;
+    for (int64_t tile = first; tile < last && tile < a.n_tiles; tile += step) {
         int fi = 0;
         for (int k = 1; k < a.n_frames; ++k)
             if (tile >= ka->f[k].tile_begin) fi = k;

@@ -47,9 +47,10 @@ class Fallback(C.Structure):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("n", C.c_int32), ("block", C.c_int32 * 8), ("blocks_per_cu", C.c_int32 * 8),
-                ("ms", C.c_float * 8), ("chosen_block", C.c_int32),
-                ("chosen_blocks_per_cu", C.c_int32), ("chosen_ms", C.c_float)]
+    _fields_ = [("n", C.c_int32), ("block", C.c_int32 * 16), ("blocks_per_cu", C.c_int32 * 16),
+                ("xcd_order", C.c_int32 * 16), ("ms", C.c_float * 16), ("chosen_block", C.c_int32),
+                ("chosen_blocks_per_cu", C.c_int32), ("chosen_xcd_order", C.c_int32),
+                ("chosen_ms", C.c_float)]
 
 
 class Batch(C.Structure):
@@ -96,6 +97,7 @@ def lib():
                                          C.POINTER(Fallback), vp, C.c_int64, vp]
         L.niv_autotune.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp,
                                    C.POINTER(TuneResult)]
+        L.niv_set_tune.argtypes = [vp, C.c_int, C.c_int32, C.c_int32, C.c_int32]
         L.niv_graph_capture.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
                                         C.POINTER(Fallback), vp, C.c_int64, C.POINTER(vp)]
         L.niv_graph_launch.argtypes = [vp, vp]
@@ -274,9 +276,15 @@ class NIV:
         r = TuneResult()
         _check(lib().niv_autotune(self._h, arr, len(frames), _prec(prec), _stream(), C.byref(r)),
                "niv_autotune")
-        return {"candidates": [(r.block[k], r.blocks_per_cu[k], r.ms[k]) for k in range(r.n)],
+        return {"candidates": [(r.block[k], r.blocks_per_cu[k], r.xcd_order[k], r.ms[k])
+                               for k in range(r.n)],
                 "block": r.chosen_block, "blocks_per_cu": r.chosen_blocks_per_cu,
-                "ms": r.chosen_ms}
+                "xcd_order": r.chosen_xcd_order, "ms": r.chosen_ms}
+
+    def set_tune(self, prec, block, blocks_per_cu, xcd_order):
+        """Pins the launch shape of later queries at `prec` (niv_set_tune)."""
+        _check(lib().niv_set_tune(self._h, _prec(prec), int(block), int(blocks_per_cu),
+                                  int(xcd_order)), "niv_set_tune")
 
     def capture(self, frames, prec, fb=None, workspace=None):
         """A HIP graph of one frame's query (and fallback); see Graph."""

@@ -349,10 +349,11 @@ def test_autotune_keeps_results():
     m.query_frames(fr.frames, "fp16")
     before = fr.host()
     r = m.autotune(fr.frames, "fp16")
-    print(f"  candidates {r['candidates']}; chosen {r['block']}x{r['blocks_per_cu']}", flush=True)
-    assert len(r["candidates"]) == 6
-    assert (r["block"], r["blocks_per_cu"]) in [(b, c) for b, c, _ in r["candidates"]]
-    assert r["ms"] == min(ms for _, _, ms in r["candidates"])
+    print(f"  candidates {r['candidates']}; chosen {r['block']}x{r['blocks_per_cu']} "
+          f"order {r['xcd_order']}", flush=True)
+    assert len(r["candidates"]) == 12
+    assert (r["block"], r["blocks_per_cu"], r["xcd_order"]) in [c[:3] for c in r["candidates"]]
+    assert r["ms"] == min(c[3] for c in r["candidates"])
     for outs in fr.outs:
         for o in outs:
             o.zero_()
@@ -361,6 +362,19 @@ def test_autotune_keeps_results():
     for a3, b3 in zip(before, after):
         for a, b in zip(a3, b3):
             np.testing.assert_array_equal(a, b)
+    # every shape gives the same pixels
+    from paper_2602_12949_amd import niv as N
+    for blk, per_cu, order, _ in r["candidates"][::3]:
+        m.set_tune("fp16", blk, per_cu, order)
+        for outs in fr.outs:
+            for o in outs:
+                o.zero_()
+        m.query_frames(fr.frames, "fp16")
+        for a3, b3 in zip(before, fr.host()):
+            for a, b in zip(a3, b3):
+                np.testing.assert_array_equal(a, b)
+    with pytest.raises(N.NivError):
+        m.set_tune("fp16", 384, 0, 0)
 
 
 # ------------------------------------------------------------ full-size batch
