@@ -23,9 +23,9 @@ launched on (torch's current stream).  Prints one JSON line on stdout;
 progress goes to stderr.
 
 `--profile CASE` runs only that case's kernel a few times (for rocprofv3
-counter and trace runs): query_fp16, query_fp32, query_bf16, batched,
-field_4k, train_step, mc, copy (a 1 GiB device copy that calibrates the
-HBM byte counters).
+counter and trace runs): query_fp16, query_fp32, query_bf16, field_4k,
+train_step, mc, copy (a 1 GiB device copy that calibrates the HBM byte
+counters).
 """
 import argparse
 import hashlib
@@ -446,6 +446,48 @@ def profile_case(case, steps, tune=None):
             m.query_frames([f], prec)
         torch.cuda.synchronize()
         log(f"[profile] {case}: {steps} launches")
+        return
+    if case in ("train_step", "mc"):
+        from niv_synth import get_workload, make_params, make_room
+        from paper_2602_12949_amd import NIV, McScene, Trainer
+        w = get_workload("room_train")
+        m = NIV(w.model_dict())
+        B = w.n_queries
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+        scene = McScene(make_room(w.scene_seeds[0])["prims"])
+        x, n = scene.sample_points(w.aabb_min, w.aabb_max, B, int(round(0.2 * B)), seed=1,
+                                   device=dev)
+        E = torch.empty((B, 3), dtype=torch.float32, device=dev)
+        valid = torch.empty(B, dtype=torch.uint8, device=dev)
+        reps = steps if case == "train_step" else max(1, steps // 10)
+        for k in range(reps):
+            scene.targets(x, n, 256, 3, seed=2 + k, out=(E, valid))
+            if case == "mc" and k == 0:
+                torch.cuda.synchronize()
+        if case == "train_step":
+            tr = Trainer(m, torch.from_numpy(params).to(dev), "fp16", max_batch=B)
+            for _ in range(steps):
+                tr.step(x, n, E, 1e-3, valid=valid)
+        torch.cuda.synchronize()
+        log(f"[profile] {case}: done")
+        return
+    if case == "field_4k":
+        from niv_synth import get_workload, make_params, make_workload_gbuffer
+        from paper_2602_12949_amd import NIV
+        w = get_workload("room_4k_6d")
+        _, g = make_workload_gbuffer(w)
+        m = NIV(w.model_dict())
+        if tune:
+            m.set_tune("bf16", *tune)
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        pm = m.prepare(t(params), "bf16")
+        d = [t(g["pos"]), t(g["nrm"]), t(g["albedo"]), t(g["mask"])]
+        f, _ = m.frame(d[0], d[1], pm, albedo=d[2], mask=d[3], extra=(0.37,))
+        for _ in range(2 * steps):
+            m.query_frames([f], "bf16")
+        torch.cuda.synchronize()
+        log(f"[profile] {case}: done")
         return
     raise SystemExit(f"unknown profile case {case}")
 

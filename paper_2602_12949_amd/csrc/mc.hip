@@ -82,77 +82,100 @@ struct Hit {
     bool back;
 };
 
-// Closest hit with t > 0; ties go to the lowest primitive index.
+// Closest hit with t > 0; ties go to the lowest primitive index.  The
+// slab and plane distances use the ray's reciprocal direction: a box costs
+// six FMAs and a min/max tree, and only (t, primitive, back) is tracked in
+// the loop; the normal of the winning primitive is rebuilt afterwards.
+struct Ray {
+    float o[3], d[3], inv[3], oi[3];  // oi = o * inv: a slab distance is fma(x, inv, -oi)
+};
+
+__device__ inline Ray make_ray(const float o[3], const float d[3])
+{
+    Ray r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = o[a];
+        r.d[a] = d[a];
+        // a zero component gets a huge finite reciprocal: slab distances keep
+        // the sign of (x - o) instead of turning into inf - inf
+        r.inv[a] = d[a] != 0.0f ? 1.0f / d[a] : 1e30f;
+        r.oi[a] = o[a] * r.inv[a];
+    }
+    return r;
+}
+
+__device__ inline float slab(float x, const Ray &r, int a) { return __builtin_fmaf(x, r.inv[a], -r.oi[a]); }
+
 __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], const float d[3],
                              Hit &h)
 {
-    h.t = INFINITY;
-    h.prim = -1;
-    h.back = false;
+    const Ray r = make_ray(o, d);
+    float best = INFINITY;
+    int bp = -1;
+    bool bback = false;
     for (int k = 0; k < n_prims; ++k) {
         const int kind = prims[k].kind;
         if (kind == 0) {
-            float tn = -INFINITY, tf = INFINITY;
-            int an = -1, af = -1;
-            bool miss = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float lo = prims[k].p[a], hi = prims[k].q[a];
-                if (d[a] == 0.0f) {
-                    if (o[a] < lo || o[a] > hi) miss = true;
-                    continue;
-                }
-                float t1 = (lo - o[a]) / d[a], t2 = (hi - o[a]) / d[a];
-                float ta = fminf(t1, t2), tb = fmaxf(t1, t2);
-                if (ta > tn) { tn = ta; an = a; }
-                if (tb < tf) { tf = tb; af = a; }
-            }
-            if (miss || tn > tf) continue;
-            if (tn > 0.0f && an >= 0) {
-                if (tn < h.t) {
-                    h.t = tn; h.prim = k; h.back = false;
-                    h.n[0] = h.n[1] = h.n[2] = 0.0f;
-                    h.n[an] = d[an] > 0.0f ? -1.0f : 1.0f;
-                }
-            } else if (tf > 0.0f && af >= 0) {
-                if (tf < h.t) {
-                    h.t = tf; h.prim = k; h.back = true;
-                    h.n[0] = h.n[1] = h.n[2] = 0.0f;
-                    h.n[af] = d[af] > 0.0f ? 1.0f : -1.0f;
-                }
-            }
+            const float x1 = slab(prims[k].p[0], r, 0), x2 = slab(prims[k].q[0], r, 0);
+            const float y1 = slab(prims[k].p[1], r, 1), y2 = slab(prims[k].q[1], r, 1);
+            const float z1 = slab(prims[k].p[2], r, 2), z2 = slab(prims[k].q[2], r, 2);
+            const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
+            const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
+            if (!(tn <= tf)) continue;
+            const bool front = tn > 0.0f;
+            const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
+            if (t > 0.0f && t < best) { best = t; bp = k; bback = !front; }
         } else if (kind == 1) {
-            const int a = prims[k].axis, uu = (a + 1) % 3, vv = (a + 2) % 3;
-            if (d[a] == 0.0f) continue;
-            float t = (prims[k].p[a] - o[a]) / d[a];
-            if (!(t > 0.0f) || !(t < h.t)) continue;
-            float hu = o[uu] + t * d[uu], hv = o[vv] + t * d[vv];
+            const int a = prims[k].axis, uu = a == 2 ? 0 : a + 1, vv = a == 0 ? 2 : a - 1;
+            const float t = slab(prims[k].p[a], r, a);
+            if (!(t > 0.0f) || !(t < best)) continue;
+            const float hu = __builtin_fmaf(t, d[uu], o[uu]), hv = __builtin_fmaf(t, d[vv], o[vv]);
             if (fabsf(hu - prims[k].p[uu]) > prims[k].q[0] || fabsf(hv - prims[k].p[vv]) > prims[k].q[1])
                 continue;
-            h.t = t; h.prim = k;
-            h.n[0] = h.n[1] = h.n[2] = 0.0f;
-            h.n[a] = prims[k].sign;
-            h.back = d[a] * prims[k].sign > 0.0f;
+            best = t; bp = k;
+            bback = d[a] * prims[k].sign > 0.0f;
         } else {
             const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
-            float den = d[0] * nx + d[1] * ny + d[2] * nz;
+            const float den = d[0] * nx + d[1] * ny + d[2] * nz;
             if (den == 0.0f) continue;
-            float t = ((prims[k].p[0] - o[0]) * nx + (prims[k].p[1] - o[1]) * ny +
-                       (prims[k].p[2] - o[2]) * nz) / den;
-            if (!(t > 0.0f) || !(t < h.t)) continue;
+            const float t = ((prims[k].p[0] - o[0]) * nx + (prims[k].p[1] - o[1]) * ny +
+                             (prims[k].p[2] - o[2]) * nz) / den;
+            if (!(t > 0.0f) || !(t < best)) continue;
             float r2 = 0.0f;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                float e = o[a] + t * d[a] - prims[k].p[a];
-                r2 += e * e;
+                const float e = __builtin_fmaf(t, d[a], o[a]) - prims[k].p[a];
+                r2 = __builtin_fmaf(e, e, r2);
             }
             if (r2 > prims[k].radius * prims[k].radius) continue;
-            h.t = t; h.prim = k;
-            h.n[0] = nx; h.n[1] = ny; h.n[2] = nz;
-            h.back = den > 0.0f;
+            best = t; bp = k;
+            bback = den > 0.0f;
         }
     }
-    return h.prim >= 0;
+    h.t = best;
+    h.prim = bp;
+    h.back = bback;
+    h.n[0] = h.n[1] = h.n[2] = 0.0f;
+    if (bp < 0) return false;
+    const int kind = prims[bp].kind;
+    if (kind == 0) {
+        // the face whose slab distance is the hit distance: entry (front) or exit (back)
+        int ax = 0;
+        float sg = 1.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float t1 = slab(prims[bp].p[a], r, a), t2 = slab(prims[bp].q[a], r, a);
+            const float ta = bback ? fmaxf(t1, t2) : fminf(t1, t2);
+            if (ta == best) { ax = a; sg = (d[a] > 0.0f) != bback ? -1.0f : 1.0f; }
+        }
+        h.n[ax] = sg;
+    } else if (kind == 1) {
+        h.n[prims[bp].axis] = prims[bp].sign;
+    } else {
+        h.n[0] = prims[bp].q[0]; h.n[1] = prims[bp].q[1]; h.n[2] = prims[bp].q[2];
+    }
+    return true;
 }
 
 // Orthonormal basis around a unit vector (Duff et al., JCGT 2017).
@@ -172,7 +195,7 @@ __device__ inline void cosine_dir(const float n[3], float u1, float u2, float d[
     onb(n, t, b);
     float r = sqrtf(u1), phi = 6.28318530717958647692f * u2;
     float sp, cp;
-    sincosf(phi, &sp, &cp);
+    __sincosf(phi, &sp, &cp);
     float x = r * cp, y = r * sp, z = sqrtf(fmaxf(0.0f, 1.0f - u1));
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] = x * t[a] + y * b[a] + z * n[a];
@@ -226,9 +249,9 @@ __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy
     float q[3], nq[3];
     float A = light_point(prims, lk, u1, u2, q, nq);
     float w[3] = {q[0] - oy[0], q[1] - oy[1], q[2] - oy[2]};
-    float d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], dl = sqrtf(d2);
+    float d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], il = 1.0f / sqrtf(d2);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) w[a] /= dl;
+    for (int a = 0; a < 3; ++a) w[a] *= il;
     float cy = ny[0] * w[0] + ny[1] * w[1] + ny[2] * w[2];
     float cq = -(nq[0] * w[0] + nq[1] * w[1] + nq[2] * w[2]);
     if (cy <= 0.0f || cq <= 0.0f) return false;
