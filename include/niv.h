@@ -6,7 +6,7 @@
  * "Real-time Rendering with a Neural Irradiance Volume" (Eurographics 2026):
  * a multi-level hash-grid encoding of the position plus spherical-harmonic
  * encoding of the normal, fed to a ReLU MLP with a linear RGB output
- * (Sec. 3.1), queried per G-buffer pixel and shaded with albedo * E / pi
+ * (Sec. 4.1), queried per G-buffer pixel and shaded with albedo * E / pi
  * (Sec. 4.4, Eq. 2).
  *
  * Conventions for every call:
@@ -40,7 +40,7 @@ typedef enum {
 
 typedef enum { NIV_FP32 = 0, NIV_FP16 = 1, NIV_BF16 = 2 } niv_precision;
 
-/* Model shape (Sec. 3.1).  Level l has resolution floor(base_res *
+/* Model shape (Sec. 4.1).  Level l has resolution floor(base_res *
  * per_level_scale^l); it is stored densely ((N+1)^3 entries, x fastest) when
  * that fits in T = 2^log2_T entries, else hashed into T entries with the
  * primes 1, 2654435761, 805459861.  The input vector is the concatenation
@@ -189,7 +189,7 @@ niv_status niv_graph_launch(niv_graph *g, hipStream_t stream);
 void niv_graph_destroy(niv_graph *g);
 
 /* ------------------------------------------------------------------ */
-/* Training (Sec. 3.4)                                                  */
+/* Training (Sec. 4.5)                                                  */
 /* ------------------------------------------------------------------ */
 
 /* A batch of training samples (device arrays): x, nrm [count][3] float
@@ -290,14 +290,14 @@ void mc_scene_destroy(mc_scene *s);
  * Outputs (device): out_E [count][3] double mean and/or out_E32 [count][3]
  * the same rounded to float (either may be NULL, not both); out_var
  * [count][3] variance of the mean or NULL; out_backfaces [count] or NULL; out_valid [count] or NULL:
- * 1 iff back faces <= spp/2 and some channel of E > 0 (Sec. 3.4 culling and
+ * 1 iff back faces <= spp/2 and some channel of E > 0 (Sec. 4.5 culling and
  * null-irradiance rejection). */
 niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
                          int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
                          double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
                          uint8_t *out_valid, hipStream_t stream);
 
-/* Training points (Sec. 3.2 and 3.4): points [0, count - n_surface) uniform in
+/* Training points (Sec. 4.2 and 4.5): points [0, count - n_surface) uniform in
  * the box [lo, hi] (host arrays of 3) with a normal uniform on the sphere;
  * points [count - n_surface, count) uniform by area over the non-emitting
  * surfaces with the surface's front normal.  Philox stream 1, counter

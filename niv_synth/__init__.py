@@ -3,7 +3,7 @@
 This package only draws random numbers and builds input data: query points,
 model parameter values, rooms made of boxes and rectangles, and G-buffers made
 by casting primary rays into those rooms (primary visibility is outside the
-method and outside its timings, Sec. 5.1 and App. F).  It holds none of the
+method and outside its timings, Sec. 5.2 and App. F).  It holds none of the
 method's arithmetic: no encoding, no network, no irradiance estimation.  Both
 the CPU oracle and the GPU library consume what it produces.
 """

@@ -1,7 +1,7 @@
 """Synthetic G-buffers: primary rays from a pinhole camera cast into a scene.
 
 Primary visibility is input preparation, not part of the method (the paper
-excludes buffer generation from its timings, Sec. 5.1 and App. F).  The output
+excludes buffer generation from its timings, Sec. 5.2 and App. F).  The output
 is what a rasteriser would hand the irradiance query: per pixel a position, a
 surface normal, an albedo and a coverage mask (0 where the ray leaves the room
 through the opening, i.e. sky).

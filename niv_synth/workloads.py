@@ -1,8 +1,8 @@
 """The five synthetic workloads, named by what they are.
 
-Model hyper-parameters follow Sec. 3.1 (hash table size, latent size, level
+Model hyper-parameters follow Sec. 4.1 (hash table size, latent size, level
 scale and coarsest resolution) where a workload does not fix them; the network
-is a stack of ReLU layers with a linear RGB output (Sec. 3.1).
+is a stack of ReLU layers with a linear RGB output (Sec. 4.1).
 """
 from dataclasses import dataclass, field
 from typing import Optional, Tuple

@@ -121,7 +121,7 @@ def _f32(a, shape_last=None):
 
 # ---------------------------------------------------------------- model
 def level_table(cfg: Config):
-    """Sec. 3.1: resolutions, dense flags, sizes and offsets per level."""
+    """Sec. 4.1: resolutions, dense flags, sizes and offsets per level."""
     L = cfg.n_levels
     res = np.zeros(L, np.int64)
     dense = np.zeros(L, np.int32)
@@ -145,7 +145,7 @@ def n_grid_values(cfg: Config) -> int:
 
 
 def mat_shapes(cfg: Config):
-    """Weight shapes (out, in): W_0, hidden ..., W_H (Sec. 3.1)."""
+    """Weight shapes (out, in): W_0, hidden ..., W_H (Sec. 4.1)."""
     shapes = [(cfg.width, input_dim(cfg))]
     shapes += [(cfg.width, cfg.width)] * (cfg.n_hidden - 1)
     shapes.append((cfg.n_out, cfg.width))
@@ -252,7 +252,7 @@ def loss(cfg: Config, params, pos, nrm, target, extra=None, valid=None, eps=0.01
 
 
 def adam(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
-    """Kingma & Ba Adam, in place on float64 arrays (Sec. 3.4)."""
+    """Kingma & Ba Adam, in place on float64 arrays (Sec. 4.5)."""
     for a in (params, grads, m, v):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_adam(params.size, _P(params, C.c_double), _P(grads, C.c_double),
@@ -260,7 +260,7 @@ def adam(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def lr_at(step, s1, s_end, lr0=1e-2, lr1=1e-4):
-    """Sec. 3.4 schedule: lr0, then exponential decay to lr1."""
+    """Sec. 4.5 schedule: lr0, then exponential decay to lr1."""
     return float(lib().orc_lr(step, s1, s_end, lr0, lr1))
 
 
@@ -279,7 +279,7 @@ def uniform(seed, a, b, stream, dim):
 
 # ---------------------------------------------------------------- Monte Carlo
 def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None):
-    """Eq. 1 indirect irradiance by Monte Carlo (Sec. 3.4 targets).  The
+    """Eq. 1 indirect irradiance by Monte Carlo (Sec. 4.5 targets).  The
     random stream of point i is keyed by point_id[i] (default i).
     Returns (E [n,3], var [n,3], backfaces [n], valid [n])."""
     pr = np.ascontiguousarray(prims)
@@ -302,7 +302,7 @@ def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None):
 
 
 def sample_points(prims, lo, hi, count, n_surface, seed):
-    """Sec. 3.4 training points: volume points then surface points."""
+    """Sec. 4.5 training points: volume points then surface points."""
     pr = np.ascontiguousarray(prims)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)

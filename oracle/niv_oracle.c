@@ -10,12 +10,12 @@
  * Neural Irradiance Volume", Eurographics 2026):
  *   - irradiance E(x,n), Eq. 1; diffuse shading rho/pi * E, Eq. 2 (Sec. 3);
  *   - the model: multi-level hash-grid encoding of x plus a ReLU MLP with a
- *     linear output (Sec. 3.1); per-frame scene variables frequency-encoded
+ *     linear output (Sec. 4.1); per-frame scene variables frequency-encoded
  *     as extra inputs (Sec. 6);
  *   - training: relative L2 loss with a stop-gradient denominator, Eq. 3;
- *     Adam with an exponentially decaying learning rate (Sec. 3.4);
+ *     Adam with an exponentially decaying learning rate (Sec. 4.5);
  *   - targets: Monte Carlo estimates of the indirect part of Eq. 1 with
- *     back-face culling and null-irradiance rejection (Sec. 3.4, App. I).
+ *     back-face culling and null-irradiance rejection (Sec. 4.5, App. H).
  * Readings of points the paper leaves open are listed next to the code that
  * takes them.
  *
@@ -50,7 +50,7 @@ typedef struct {
     double aabb_min[3], aabb_max[3];
 } orc_config;
 
-/* Level table (Sec. 3.1, learned encodings).  Reading: the resolution of
+/* Level table (Sec. 4.1, learned encodings).  Reading: the resolution of
  * level l is floor(N_min * b^l), taken with a tiny relative guard so that a
  * product that is mathematically an integer is not floored to the integer
  * below; a level is stored densely with (N+1)^3 entries when that fits in T,
@@ -215,7 +215,7 @@ void orc_sh(int bands, const double n_unit[3], double *out)
     }
 }
 
-/* Frequency encoding of a scalar (Sec. 3.1 and Sec. 6, cited positional
+/* Frequency encoding of a scalar (Sec. 4.1 and Sec. 6, cited positional
  * encoding): [sin(2^k pi t), cos(2^k pi t)] for k < bands, interleaved. */
 void orc_freq(int bands, double t, double *out)
 {
@@ -297,7 +297,7 @@ static void orc_weight_ptrs(const orc_config *c, const double *params,
     W[c->n_hidden] = w;
 }
 
-/* Forward through the MLP (Sec. 3.1): x_{k+1} = max(0, W_k x_k) for the
+/* Forward through the MLP (Sec. 4.1): x_{k+1} = max(0, W_k x_k) for the
  * hidden layers, E = W_H x_H.  If `acts` is given it receives x_0 .. x_H
  * (post-activation) concatenated. */
 static void orc_mlp(const orc_config *c, const double *const *W, const double *x0,
@@ -552,7 +552,7 @@ void orc_adam(int64_t n, double *params, const double *grads, double *m, double 
     }
 }
 
-/* Learning rate schedule (Sec. 3.4): lr0 until step s1, then exponential
+/* Learning rate schedule (Sec. 4.5): lr0 until step s1, then exponential
  * decay reaching lr1 at step s_end (reading: decay ends at the last step). */
 double orc_lr(int64_t step, int64_t s1, int64_t s_end, double lr0, double lr1)
 {
@@ -757,7 +757,7 @@ static double orc_light_point(const orc_prim *pr, double u1, double u2, double q
  * reaching x.  Per sample: a cosine-distributed direction about n (so the
  * estimator is pi times the radiance found along it); at the first hit y_1,
  * emission is direct and skipped (unless INCLUDE_DIRECT); a hit from behind
- * is counted and scores 0 (culling, Sec. 3.4); then for k = 1..B the
+ * is counted and scores 0 (culling, Sec. 4.5); then for k = 1..B the
  * radiance reflected at y_k is gathered by next-event estimation to every
  * light (NEE) or by emission found by the continuation ray (EMIT_ON_HIT),
  * and the path continues with a cosine-sampled direction and throughput
@@ -901,7 +901,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
     }
 }
 
-/* Training points (Sec. 3.4, App. I): the first count - n_surface points
+/* Training points (Sec. 4.5, App. H): the first count - n_surface points
  * are uniform in the box [lo, hi] with a direction uniform on the sphere;
  * the last n_surface points are uniform by area over the non-emitting
  * surfaces (rectangles and box faces) with n = the surface's front normal.

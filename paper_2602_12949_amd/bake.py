@@ -1,11 +1,11 @@
-"""Baking a Neural Irradiance Volume on the GPU (Sec. 3.4).
+"""Baking a Neural Irradiance Volume on the GPU (Sec. 4.5).
 
 Each step draws training points (80 % uniform in the volume with a uniform
-direction, 20 % on surfaces with the surface normal, Sec. 3.2), estimates
+direction, 20 % on surfaces with the surface normal, Sec. 4.2), estimates
 their indirect irradiance with the Monte Carlo estimator (culling points
 whose first hits are mostly back faces and points with null irradiance),
 and takes one Adam step on the Eq. 3 loss; the learning rate is held, then
-decays exponentially (Sec. 3.4).  This module only sequences library calls;
+decays exponentially (Sec. 4.5).  This module only sequences library calls;
 every step runs in the library's kernels.
 """
 import math

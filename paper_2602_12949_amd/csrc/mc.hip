@@ -1,5 +1,5 @@
 // Monte Carlo estimate of indirect irradiance (Eq. 1) and the training-point
-// sampler (Sec. 3.4, App. I), for gfx950.
+// sampler (Sec. 4.5, App. H), for gfx950.
 //
 // One wave per query point: the lanes take samples s = lane, lane+64, ...,
 // trace in FP32, sum each sample's value in FP64, and the wave reduces the

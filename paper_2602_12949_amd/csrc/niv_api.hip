@@ -11,7 +11,7 @@ namespace {
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-// Level table (Sec. 3.1): resolution floor(N_min * b^l) (with a 2^-40
+// Level table (Sec. 4.1): resolution floor(N_min * b^l) (with a 2^-40
 // relative guard so an exact integer product is not floored down), dense
 // (N+1)^3 storage when it fits in T entries, else T hashed entries.
 void build_levels(Model &m)

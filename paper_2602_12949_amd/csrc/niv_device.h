@@ -1,6 +1,6 @@
 // Device-side pieces shared by the query and training kernels of libniv:
 // vector types, precision traits, model shapes, the operand layout of a
-// prepared model and the per-level encoding (Sec. 3.1).
+// prepared model and the per-level encoding (Sec. 4.1).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -231,7 +231,7 @@ __device__ inline f2 load_latent(const uint8_t *grid, uint32_t entry)
 }
 
 // Cell, corner indices (within the whole grid) and trilinear weights of one
-// level (Sec. 3.1).  Corner c = cx + 2cy + 4cz.
+// level (Sec. 4.1).  Corner c = cx + 2cy + 4cz.
 template <class LV>
 __device__ inline void level_corners(const LV &lv, const double p[3], uint32_t hmask,
                                      uint32_t idx[8], float w[8])
@@ -338,7 +338,7 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
     return acc;
 }
 
-// Trilinear blend of one level (Sec. 3.1).  Returns the F = 2 features.
+// Trilinear blend of one level (Sec. 4.1).  Returns the F = 2 features.
 template <int P, class LV>
 __device__ inline f2 encode_level(const LV &lv, const double p[3], uint32_t hmask,
                                   const uint8_t *grid)

@@ -4,7 +4,7 @@
 // and shades it with albedo * E / pi (Eq. 2):
 //   1. each lane loads one pixel (coalesced) and builds its input vector:
 //      per level the cell, the 8 corner indices (dense or spatially hashed),
-//      8 gathers and a trilinear blend in FP32 (Sec. 3.1); 16 real SH of the
+//      8 gathers and a trilinear blend in FP32 (Sec. 4.1); 16 real SH of the
 //      normal; the frequency code of the frame's scene variables (Sec. 6);
 //   2. the wave's 64 input vectors go through a per-wave LDS block into the
 //      operand layout of the matrix cores;

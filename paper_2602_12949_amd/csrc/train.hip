@@ -1,4 +1,4 @@
-// On-GPU training of the Neural Irradiance Volume (Sec. 3.4): Eq. 3 loss,
+// On-GPU training of the Neural Irradiance Volume (Sec. 4.5): Eq. 3 loss,
 // backpropagation through the MLP on the matrix cores, scatter of the
 // encoding gradient into the hash grid, and Adam.
 //

@@ -1,4 +1,4 @@
-"""End-to-end baking on the GPU (Sec. 3.4): points from the sampler, targets
+"""End-to-end baking on the GPU (Sec. 4.5): points from the sampler, targets
 from the Monte Carlo estimator, Adam steps on Eq. 3, then the trained
 network is judged against a high-sample Monte Carlo reference on held-out
 points, and compared with Monte Carlo at equal query time."""
