@@ -79,11 +79,20 @@ template <> struct Prec<NIV_BF16> {
         // a bf16 is the upper half of the float with the same bits
         return (f2){__builtin_bit_cast(float, w << 16), __builtin_bit_cast(float, w & 0xffff0000u)};
     }
-    // x = hi + lo with hi = bf16(x), lo = bf16(x - hi): the pair carries 16
-    // significant bits, so BF16 operands lose little to rounding.
-    __device__ static uint32_t pack_lo(float x, float y, uint32_t hi) {
-        f2 h = unpack(hi);
-        return pack(x - h.x, y - h.y);
+    // x = hi + lo: hi is x cut to its upper 16 bits (a BF16 by truncation),
+    // lo = x - hi (exact in FP32) rounded to BF16; the pair carries at least
+    // 16 significant bits, so BF16 operands lose little to rounding.  Two
+    // values per call: one byte permute for the two his, one conversion for
+    // the two los.
+    __device__ static void split(float x, float y, uint32_t &hi, uint32_t &lo) {
+        const uint32_t xb = f2u(x), yb = f2u(y);
+        hi = __builtin_amdgcn_perm(yb, xb, 0x07060302u);
+        lo = pack(x - u2f(xb & 0xffff0000u), y - u2f(yb & 0xffff0000u));
+    }
+    // the same after a ReLU, done as a signed integer max on the FP32 bits
+    __device__ static void split_relu(float x, float y, uint32_t &hi, uint32_t &lo) {
+        const int32_t xi = (int32_t)f2u(x), yi = (int32_t)f2u(y);
+        split(u2f((uint32_t)(xi > 0 ? xi : 0)), u2f((uint32_t)(yi > 0 ? yi : 0)), hi, lo);
     }
 };
 
@@ -101,18 +110,33 @@ template <> struct Prec<NIV_FP32> {
 };
 
 // ---------------------------------------------------------------- shapes
-template <int L_, int NEX_, int W_, int H_> struct Shape {
+// SL_: lane-sliced encoding.  Each lane encodes exactly the layer-0 operand
+// elements it feeds to the matrix cores (for the four pixels it serves, one
+// per 16-pixel tile), so no per-wave staging block in LDS is needed and the
+// whole LDS can hold the weights.
+template <int L_, int NEX_, int W_, int H_, bool SL_ = false> struct Shape {
     static constexpr int L = L_, NEX = NEX_, W = W_, H = H_;
+    static constexpr bool SL = SL_;
     static constexpr int DIN = 2 * L + 16 + 16 * NEX;  // F = 2, 16 SH, 16 per variable
     static constexpr int KLG = DIN / 4;                // input slots per lane group
     static constexpr int NOB = W / 16;                 // 16-row output blocks
     static_assert(DIN % 16 == 0, "input width must be a multiple of 16");
+    static_assert(!SL || (L == 16 && DIN == 64), "lane slices need 16 levels and 64 inputs");
     static_assert(L % 4 == 0 && W % 32 == 0, "shape");
 };
 
 using ShapeUnitCube = Shape<8, 0, 64, 2>;
 using ShapeRoom = Shape<16, 0, 64, 3>;
-using ShapeWide6D = Shape<16, 1, 128, 4>;
+using ShapeWide6D = Shape<16, 1, 128, 4, true>;
+
+// Lane-sliced layer-0 input order.  Virtual element v (0..15) of lane group
+// g: v < 8 is feature v % 2 of level 4 (v / 2) + g; then SH coefficients
+// 4g..4g+3 and frequency-code entries 4g..4g+3.  (16 levels, 16 SH, one
+// scene variable: 64 inputs.)
+__host__ __device__ constexpr int slice_col(int v, int g)
+{
+    return v < 8 ? 2 * (4 * (v >> 1) + g) + (v & 1) : (v < 12 ? 32 + 4 * g + (v - 8) : 48 + 4 * g + (v - 12));
+}
 
 // Byte layout of the operand block of a prepared model.
 template <int P, class S> struct Ops {
@@ -156,7 +180,7 @@ __device__ int64_t operand_source(int op, int lane, int e, int64_t n_grid, int n
     if (op < n0) {  // layer 0: [ob][chunk]
         int ob = op / (O::L0_FULL + O::L0_HALF), c = op % (O::L0_FULL + O::L0_HALF);
         int slot = O::F32 ? c : (c < O::L0_FULL ? c * 8 + e : O::L0_FULL * 8 + e);
-        int row = 16 * ob + i, col = S::KLG * g + slot;
+        int row = 16 * ob + i, col = S::SL ? slice_col(slot, g) : S::KLG * g + slot;
         return w0 + (int64_t)row * S::DIN + col;
     }
     op -= n0;
@@ -322,6 +346,91 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
         v[2] = ld(x0 ^ t10, o); v[3] = ld(x1 ^ t10, o);
         v[4] = ld(x0 ^ t01, o); v[5] = ld(x1 ^ t01, o);
         v[6] = ld(x0 ^ t11, o); v[7] = ld(x1 ^ t11, o);
+    }
+    const float wx1 = fr[0], wx0 = 1.0f - fr[0];
+    const float wy1 = fr[1], wy0 = 1.0f - fr[1];
+    const float wz1 = fr[2], wz0 = 1.0f - fr[2];
+    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+    const float w[8] = {wx0 * w00, wx1 * w00, wx0 * w10, wx1 * w10,
+                        wx0 * w01, wx1 * w01, wx0 * w11, wx1 * w11};
+    f2 acc = {0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
+        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
+    }
+    return acc;
+}
+
+// The same blend for a level that differs between lanes (lane-sliced
+// encoding): the level's constants are per-lane values, its first entry is
+// added to the per-lane buffer offset.
+struct LevelRegs {   // the per-lane part of a level's constants
+    double k[3], o[3];
+    int32_t nm1, dense;
+    uint32_t off, s1, s2;
+};
+
+__device__ inline LevelRegs load_level(const LevelConst *lp)
+{
+    LevelRegs r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.k[a] = lp->k[a];
+        r.o[a] = lp->o[a];
+    }
+    r.nm1 = lp->nm1;
+    r.dense = lp->dense;
+    r.off = lp->off;
+    r.s1 = lp->s1;
+    r.s2 = lp->s2;
+    return r;
+}
+
+template <int P>
+__device__ inline f2 encode_level_vec(const LevelRegs &lv, const double p[3], uint32_t hmask,
+                                      __amdgpu_buffer_rsrc_t rsrc)
+{
+    constexpr int SH = (P == NIV_FP32) ? 3 : 2;
+    constexpr uint32_t EB = 1u << SH;
+    int32_t ci[3];
+    float fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+        int32_t c = (int32_t)s;
+        c = c < lv.nm1 ? c : lv.nm1;
+        ci[a] = c;
+        fr[a] = (float)(s - (double)c);
+    }
+    auto ld = [&](uint32_t voff) -> f2 {
+        if constexpr (P == NIV_FP32) {
+            u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, 0, 0);
+            return (f2){u2f(w.x), u2f(w.y)};
+        } else {
+            return Prec<P>::unpack(__builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, 0, 0));
+        }
+    };
+    const uint32_t o = lv.off << SH;
+    f2 v[8];
+    if (lv.dense) {
+        const uint32_t b = (((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH) + o;
+        const uint32_t dy = lv.s1 << SH, dz = lv.s2 << SH;
+        v[0] = ld(b); v[1] = ld(b + EB);
+        v[2] = ld(b + dy); v[3] = ld(b + dy + EB);
+        v[4] = ld(b + dz); v[5] = ld(b + dz + EB);
+        v[6] = ld(b + dz + dy); v[7] = ld(b + dz + dy + EB);
+    } else {
+        const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH, m = hmask << SH;
+        const uint32_t x0 = (uint32_t)ci[0] << SH, x1 = x0 + EB;
+        const uint32_t y0 = (uint32_t)ci[1] * p1, y1 = y0 + p1;
+        const uint32_t z0 = (uint32_t)ci[2] * p2, z1 = z0 + p2;
+        const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
+        const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
+        v[0] = ld((x0 ^ t00) + o); v[1] = ld((x1 ^ t00) + o);
+        v[2] = ld((x0 ^ t10) + o); v[3] = ld((x1 ^ t10) + o);
+        v[4] = ld((x0 ^ t01) + o); v[5] = ld((x1 ^ t01) + o);
+        v[6] = ld((x0 ^ t11) + o); v[7] = ld((x1 ^ t11) + o);
     }
     const float wx1 = fr[0], wx0 = 1.0f - fr[0];
     const float wy1 = fr[1], wy0 = 1.0f - fr[1];

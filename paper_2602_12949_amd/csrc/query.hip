@@ -119,7 +119,7 @@ static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
     using O = Ops<P, S>;
     constexpr int kWavesPerBlock = BLOCK / 64;
     auto kern = k_query<P, S, WLDS, TB, false, BLOCK>;
-    const size_t lds = (WLDS ? O::W_BYTES : 0) + (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4;
+    const size_t lds = (WLDS ? O::W_BYTES : 0) + (S::SL ? 0 : (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4);
     static int max_blocks = -1;  // resident workgroups per CU for this instantiation
     static int n_cu = 0;
     if (max_blocks < 0) {
@@ -181,10 +181,10 @@ hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const 
         if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeRoom, true, 4>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeRoom, true, 4>(a, tu, st);
         return query_b<NIV_BF16, ShapeRoom, true, 4>(a, tu, st);
-    default:
-        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6D, false, 2>(a, tu, st);
-        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeWide6D, false, 2>(a, tu, st);
-        return query_b<NIV_BF16, ShapeWide6D, false, 2>(a, tu, st);
+    default:  // lane-sliced encoding: the LDS holds the whole weight block
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6D, true, 2>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeWide6D, true, 2>(a, tu, st);
+        return query_b<NIV_BF16, ShapeWide6D, true, 2>(a, tu, st);
     }
 }
 

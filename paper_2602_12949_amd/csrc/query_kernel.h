@@ -100,9 +100,137 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         const uint8_t *f_mask = ka->f[fi].mask;
         const int64_t q = chunk * 64 + lane;
         const bool live = q < count;
+        float *f_inputs = ka->f[fi].out_inputs;
+        bool on = false, work = false;
+        uint32_t flags = 0u;
+        // lane-sliced layer-0 operands of the TB tiles in flight: [part][tile][dword]
+        constexpr int SL_DW = (P == NIV_FP32) ? 16 : 8;
+        [[maybe_unused]] uint32_t sl[O::NS][TB][SL_DW];
+        [[maybe_unused]] uint32_t tfl[4];
+        [[maybe_unused]] bool ton[4], twk[4];
+        // ---- 1'. lane-sliced encoding: lane (g, j) serves pixel 16t + j of
+        // every tile t; it encodes grid levels 4s + g (s = 0..3) and SH /
+        // frequency-code entries 4g..4g+3 of that pixel, i.e. exactly its own
+        // layer-0 operand elements.  Runs per group of TB tiles, just before
+        // their matrix products, so only TB tiles of operands are live.
+        auto encode_tiles = [&](int tb0) {
+            double pd[TB][3];
+#pragma unroll
+            for (int tt = 0; tt < TB; ++tt) {
+                const int t = tb0 + tt;
+                const int64_t qt = chunk * 64 + 16 * t + j;
+                bool o = false;
+                float x = 0.f, y = 0.f, z = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+                if (qt < count) {
+                    o = f_mask ? (f_mask[qt] != 0) : true;
+                    if (o) {
+                        x = f_pos[3 * qt]; y = f_pos[3 * qt + 1]; z = f_pos[3 * qt + 2];
+                        mx = f_nrm[3 * qt]; my = f_nrm[3 * qt + 1]; mz = f_nrm[3 * qt + 2];
+                    }
+                }
+                bool bd = !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z) &&
+                            __builtin_isfinite(mx) && __builtin_isfinite(my) && __builtin_isfinite(mz));
+#pragma unroll
+                for (int e = 0; e < S::NEX; ++e) bd |= !__builtin_isfinite(ka->f[fi].extra[e]);
+                const float nm = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
+                bd |= !(nm > 0.0f);
+                const float ns = (nm > 0.0f) ? 1.0f / nm : 0.0f;
+                mx *= ns; my *= ns; mz *= ns;
+                const float n2 = mx * mx + my * my + mz * mz;
+                const bool wk = o && !bd;
+                uint32_t fl = (o && bd) ? 2u : 0u;
+                double pp[3] = {x, y, z};
+                bool out = false;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    out |= (pp[c] < a.lo[c]) | (pp[c] > a.hi[c]);
+                    pd[tt][c] = pp[c] < a.lo[c] ? a.lo[c] : (pp[c] > a.hi[c] ? a.hi[c] : pp[c]);
+                }
+                if (wk && out) fl |= 1u;
+                tfl[t] = fl; ton[t] = o; twk[t] = wk;
+                const float rn = wk ? __builtin_amdgcn_rsqf(n2) : 0.0f;
+                float sh[16];
+                sh16(mx * rn, my * rn, mz * rn, sh);
+                float se[4], fe[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    se[e] = g == 0 ? sh[e] : g == 1 ? sh[4 + e] : g == 2 ? sh[8 + e] : sh[12 + e];
+                    fe[e] = g == 0 ? gam[e] : g == 1 ? gam[4 + e] : g == 2 ? gam[8 + e] : gam[12 + e];
+                }
+                if constexpr (P == NIV_FP32) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        sl[0][tt][8 + e] = f2u(se[e]);
+                        sl[0][tt][12 + e] = f2u(fe[e]);
+                    }
+                } else {
+                    if constexpr (O::NS == 2) {
+                        Prec<P>::split(se[0], se[1], sl[0][tt][4], sl[O::NS - 1][tt][4]);
+                        Prec<P>::split(se[2], se[3], sl[0][tt][5], sl[O::NS - 1][tt][5]);
+                        Prec<P>::split(fe[0], fe[1], sl[0][tt][6], sl[O::NS - 1][tt][6]);
+                        Prec<P>::split(fe[2], fe[3], sl[0][tt][7], sl[O::NS - 1][tt][7]);
+                    } else {
+                        sl[0][tt][4] = Prec<P>::pack(se[0], se[1]);
+                        sl[0][tt][5] = Prec<P>::pack(se[2], se[3]);
+                        sl[0][tt][6] = Prec<P>::pack(fe[0], fe[1]);
+                        sl[0][tt][7] = Prec<P>::pack(fe[2], fe[3]);
+                    }
+                }
+            }
+            // grid levels 4s + g: the level's constants are per-lane loads
+            const LevelConst *lt = reinterpret_cast<const LevelConst *>(fmodel);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                __builtin_amdgcn_sched_barrier(0);  // one slot of gathers in flight at a time
+                const LevelRegs lc = load_level(lt + 4 * s2 + g);
+#pragma unroll
+                for (int tt = 0; tt < TB; ++tt) {
+                    const f2 f = encode_level_vec<P>(lc, pd[tt], a.hash_mask, grid_rsrc);
+                    if constexpr (P == NIV_FP32) {
+                        sl[0][tt][2 * s2] = f2u(f.x);
+                        sl[0][tt][2 * s2 + 1] = f2u(f.y);
+                    } else {
+                        if constexpr (O::NS == 2) Prec<P>::split(f.x, f.y, sl[0][tt][s2], sl[O::NS - 1][tt][s2]);
+                        else sl[0][tt][s2] = Prec<P>::pack(f.x, f.y);
+                    }
+                }
+            }
+            // no bias anywhere: a pixel without valid inputs feeds zeros (E = 0)
+#pragma unroll
+            for (int tt = 0; tt < TB; ++tt)
+#pragma unroll
+                for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
+                    for (int d = 0; d < SL_DW; ++d)
+                        if (!twk[tb0 + tt]) sl[sp][tt][d] = 0u;
+            if (f_inputs) {
+#pragma unroll
+                for (int tt = 0; tt < TB; ++tt) {
+                    const int64_t qt = chunk * 64 + 16 * (tb0 + tt) + j;
+                    if (qt >= count) continue;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        float val;
+                        if constexpr (P == NIV_FP32) {
+                            val = u2f(sl[0][tt][v]);
+                        } else {
+                            f2 h = Prec<P>::unpack(sl[0][tt][v >> 1]);
+                            val = (v & 1) ? h.y : h.x;
+                            if constexpr (O::NS == 2) {
+                                f2 l = Prec<P>::unpack(sl[1][tt][v >> 1]);
+                                val += (v & 1) ? l.y : l.x;
+                            }
+                        }
+                        f_inputs[qt * S::DIN + slice_col(v, g)] = val;
+                    }
+                }
+            }
+        };
+        if constexpr (S::SL) {
+            static_assert(!TRAIN, "training uses the staged encoding");
+        } else {
         // ---- 1. load and encode this lane's pixel
         float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
-        bool on = false;
         if (live) {
             on = f_mask ? (f_mask[q] != 0) : true;
             if constexpr (TRAIN) on = a.valid ? (a.valid[q] != 0) : true;
@@ -138,8 +266,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         const float ns = (nm > 0.0f) ? 1.0f / nm : 0.0f;
         nx *= ns; ny *= ns; nz *= ns;
         const float n2 = nx * nx + ny * ny + nz * nz;
-        const bool work = on && !bad;
-        uint32_t flags = (on && bad) ? 2u : 0u;
+        work = on && !bad;
+        flags = (on && bad) ? 2u : 0u;
         double p[3] = {px, py, pz};
         bool outside = false;
 #pragma unroll
@@ -162,8 +290,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
                     f2 f = encode_level_buf<P>(lvs[l], p, a.hash_mask, grid_rsrc);
-                    row[l] = Prec<P>::pack(f.x, f.y);
-                    if constexpr (O::NS == 2) row[O::PART_DW + l] = Prec<P>::pack_lo(f.x, f.y, row[l]);
+                    if constexpr (O::NS == 2) Prec<P>::split(f.x, f.y, row[l], row[O::PART_DW + l]);
+                    else row[l] = Prec<P>::pack(f.x, f.y);
                 }
             }
             const float rn = __builtin_amdgcn_rsqf(n2);
@@ -179,16 +307,18 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             } else {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    row[base + k] = Prec<P>::pack(sh[2 * k], sh[2 * k + 1]);
                     if constexpr (O::NS == 2)
-                        row[O::PART_DW + base + k] = Prec<P>::pack_lo(sh[2 * k], sh[2 * k + 1], row[base + k]);
+                        Prec<P>::split(sh[2 * k], sh[2 * k + 1], row[base + k], row[O::PART_DW + base + k]);
+                    else
+                        row[base + k] = Prec<P>::pack(sh[2 * k], sh[2 * k + 1]);
                 }
 #pragma unroll
                 for (int k = 0; k < 8 * S::NEX; ++k) {
-                    row[base + 8 + k] = Prec<P>::pack(gam[2 * k], gam[2 * k + 1]);
                     if constexpr (O::NS == 2)
-                        row[O::PART_DW + base + 8 + k] =
-                            Prec<P>::pack_lo(gam[2 * k], gam[2 * k + 1], row[base + 8 + k]);
+                        Prec<P>::split(gam[2 * k], gam[2 * k + 1], row[base + 8 + k],
+                                       row[O::PART_DW + base + 8 + k]);
+                    else
+                        row[base + 8 + k] = Prec<P>::pack(gam[2 * k], gam[2 * k + 1]);
                 }
             }
         } else {
@@ -196,7 +326,6 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
 #pragma unroll
             for (int k = 0; k < O::NS * O::PART_DW; ++k) row[k] = 0u;
         }
-        float *f_inputs = ka->f[fi].out_inputs;
         if (f_inputs && live) {
             float *dst = f_inputs + q * S::DIN;
             if constexpr (P == NIV_FP32) {
@@ -230,6 +359,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 }
             }
         }
+        }  // staged encoding
         // LDS accesses of one wave complete in order; the fence keeps the
         // compiler from moving the operand reads above the row writes.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -242,12 +372,18 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         for (int t = 0; t < 4; ++t) acc_o[t] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t0 = 0; t0 < 4; t0 += TB) {
+            if constexpr (S::SL) encode_tiles(t0);
             f4 acc[TB][S::NOB];
             // layer 0
             if constexpr (P == NIV_FP32) {
                 float b0[TB][S::KLG];
 #pragma unroll
                 for (int t = 0; t < TB; ++t) {
+                    if constexpr (S::SL) {
+#pragma unroll
+                        for (int k = 0; k < S::KLG; ++k) b0[t][k] = u2f(sl[0][t][k]);
+                        continue;
+                    }
                     const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + O::LANE_DW * g;
 #pragma unroll
                     for (int k = 0; k < S::KLG; k += 4) {
@@ -260,6 +396,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 }
 #pragma unroll
                 for (int ob = 0; ob < S::NOB; ++ob) {
+                    // wide layers: keep the weight loads of one output block together
+                    if constexpr (S::W > 64) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -275,6 +413,11 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 for (int sp = 0; sp < O::NS; ++sp)
 #pragma unroll
                 for (int t = 0; t < TB; ++t) {
+                    if constexpr (S::SL) {
+#pragma unroll
+                        for (int k = 0; k < O::LANE_DW; ++k) b0[sp][t][k] = sl[sp][t][k];
+                        continue;
+                    }
                     const uint32_t *r = stage + (16 * (t0 + t) + j) * O::ROW_DW + sp * O::PART_DW +
                                         O::LANE_DW * g;
 #pragma unroll
@@ -286,6 +429,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 }
 #pragma unroll
                 for (int ob = 0; ob < S::NOB; ++ob) {
+                    // wide layers: keep the weight loads of one output block together
+                    if constexpr (S::W > 64) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -361,6 +506,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     } else {
 #pragma unroll
                         for (int ob = 0; ob < S::NOB; ++ob) {
+                            // wide layers: keep the weight loads of one output block together
+                            if constexpr (S::W > 64) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                             for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -381,12 +528,10 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                                 bh[0][t][2 * ob] = Prec<P>::pack_relu(acc[t][ob].x, acc[t][ob].y);
                                 bh[0][t][2 * ob + 1] = Prec<P>::pack_relu(acc[t][ob].z, acc[t][ob].w);
                             } else {
-                                const float r0 = fmaxf(acc[t][ob].x, 0.f), r1 = fmaxf(acc[t][ob].y, 0.f);
-                                const float r2 = fmaxf(acc[t][ob].z, 0.f), r3 = fmaxf(acc[t][ob].w, 0.f);
-                                bh[0][t][2 * ob] = Prec<P>::pack(r0, r1);
-                                bh[0][t][2 * ob + 1] = Prec<P>::pack(r2, r3);
-                                bh[O::NS - 1][t][2 * ob] = Prec<P>::pack_lo(r0, r1, bh[0][t][2 * ob]);
-                                bh[O::NS - 1][t][2 * ob + 1] = Prec<P>::pack_lo(r2, r3, bh[0][t][2 * ob + 1]);
+                                Prec<P>::split_relu(acc[t][ob].x, acc[t][ob].y, bh[0][t][2 * ob],
+                                                    bh[O::NS - 1][t][2 * ob]);
+                                Prec<P>::split_relu(acc[t][ob].z, acc[t][ob].w, bh[0][t][2 * ob + 1],
+                                                    bh[O::NS - 1][t][2 * ob + 1]);
                             }
                         }
                     if constexpr (TRAIN) {
@@ -427,6 +572,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     } else {
 #pragma unroll
                         for (int ob = 0; ob < S::NOB; ++ob) {
+                            // wide layers: keep the weight loads of one output block together
+                            if constexpr (S::W > 64) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                             for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -445,6 +592,12 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     }
                 }
             }
+        }
+        if constexpr (S::SL) {
+            // this lane's own pixel 16g + j is the one it served in tile g
+            on = g == 0 ? ton[0] : g == 1 ? ton[1] : g == 2 ? ton[2] : ton[3];
+            work = g == 0 ? twk[0] : g == 1 ? twk[1] : g == 2 ? twk[2] : twk[3];
+            flags = g == 0 ? tfl[0] : g == 1 ? tfl[1] : g == 2 ? tfl[2] : tfl[3];
         }
         // ---- 4. lane j (g = 0) holds the RGB of pixel 16t + j in acc_o[t]:
         // lane (g, j) takes channel c of its pixel 16g + j from lane j.
