@@ -119,7 +119,8 @@ static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
     using O = Ops<P, S>;
     constexpr int kWavesPerBlock = BLOCK / 64;
     auto kern = k_query<P, S, WLDS, TB, false, BLOCK>;
-    const size_t lds = (WLDS ? O::W_BYTES : 0) + (S::SL ? 0 : (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4);
+    const size_t lds = (WLDS ? O::W_BYTES : 0) +
+                       (S::SL ? (size_t)kLevelBytes : (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4);
     static int max_blocks = -1;  // resident workgroups per CU for this instantiation
     static int n_cu = 0;
     if (max_blocks < 0) {

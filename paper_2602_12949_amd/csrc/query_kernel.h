@@ -37,6 +37,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
     constexpr int kWavesPerBlock = BLOCK / 64;
     using O = Ops<P, S>;
     static_assert(!TRAIN || (TB == 4 && P != NIV_BF16), "training: four tiles, FP32 or FP16");
+    static_assert(!S::SL || WLDS, "lane slices read the level table from LDS");
     // training saves: per 64-sample chunk, X_0 (DIN rows) then X_1..X_H (W rows), each [row][64]
     constexpr int64_t CHUNK_BYTES = (int64_t)(S::DIN + S::H * S::W) * 64 * O::ES;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -73,6 +74,11 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 const u4 *src = reinterpret_cast<const u4 *>(fmodel + kLevelBytes);
                 u4 *dst = reinterpret_cast<u4 *>(smem);
                 for (int k = threadIdx.x; k < O::W_BYTES / 16; k += BLOCK) dst[k] = src[k];
+                if constexpr (S::SL) {  // level table behind the weights (per-lane level reads)
+                    const u4 *lsrc = reinterpret_cast<const u4 *>(fmodel);
+                    u4 *ldst = reinterpret_cast<u4 *>(smem + O::W_BYTES);
+                    for (int k = threadIdx.x; k < kLevelBytes / 16; k += BLOCK) ldst[k] = lsrc[k];
+                }
                 __syncthreads();
                 staged = fi;
             }
@@ -113,21 +119,35 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         // frequency-code entries 4g..4g+3 of that pixel, i.e. exactly its own
         // layer-0 operand elements.  Runs per group of TB tiles, just before
         // their matrix products, so only TB tiles of operands are live.
+        // each lane loads its own pixel (coalesced); the lanes serving it in
+        // the sliced layout fetch it with a cross-lane permute
+        [[maybe_unused]] uint32_t own[7];
+        if constexpr (S::SL) {
+            bool o = false;
+            float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (live) {
+                o = f_mask ? (f_mask[q] != 0) : true;
+                if (o) {
+                    v[0] = f_pos[3 * q]; v[1] = f_pos[3 * q + 1]; v[2] = f_pos[3 * q + 2];
+                    v[3] = f_nrm[3 * q]; v[4] = f_nrm[3 * q + 1]; v[5] = f_nrm[3 * q + 2];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) own[c] = f2u(v[c]);
+            own[6] = o ? 1u : 0u;
+        }
         auto encode_tiles = [&](int tb0) {
             double pd[TB][3];
 #pragma unroll
             for (int tt = 0; tt < TB; ++tt) {
                 const int t = tb0 + tt;
-                const int64_t qt = chunk * 64 + 16 * t + j;
-                bool o = false;
-                float x = 0.f, y = 0.f, z = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
-                if (qt < count) {
-                    o = f_mask ? (f_mask[qt] != 0) : true;
-                    if (o) {
-                        x = f_pos[3 * qt]; y = f_pos[3 * qt + 1]; z = f_pos[3 * qt + 2];
-                        mx = f_nrm[3 * qt]; my = f_nrm[3 * qt + 1]; mz = f_nrm[3 * qt + 2];
-                    }
-                }
+                const int src = (16 * t + j) << 2;   // byte address of the pixel's own lane
+                uint32_t r[7];
+#pragma unroll
+                for (int c = 0; c < 7; ++c) r[c] = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)own[c]);
+                const bool o = r[6] != 0u;
+                float x = u2f(r[0]), y = u2f(r[1]), z = u2f(r[2]);
+                float mx = u2f(r[3]), my = u2f(r[4]), mz = u2f(r[5]);
                 bool bd = !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z) &&
                             __builtin_isfinite(mx) && __builtin_isfinite(my) && __builtin_isfinite(mz));
 #pragma unroll
@@ -177,8 +197,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     }
                 }
             }
-            // grid levels 4s + g: the level's constants are per-lane loads
-            const LevelConst *lt = reinterpret_cast<const LevelConst *>(fmodel);
+            // grid levels 4s + g: the level's constants are per-lane LDS reads
+            const LevelConst *lt = reinterpret_cast<const LevelConst *>(smem + O::W_BYTES);
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) {
                 __builtin_amdgcn_sched_barrier(0);  // one slot of gathers in flight at a time
