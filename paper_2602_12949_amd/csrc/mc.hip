@@ -107,6 +107,21 @@ __device__ inline Ray make_ray(const float o[3], const float d[3])
 
 __device__ inline float slab(float x, const Ray &r, int a) { return __builtin_fmaf(x, r.inv[a], -r.oi[a]); }
 
+// Rectangle k perpendicular to axis A (a uniform value, so the caller
+// branches once per primitive and every index below is a constant).
+template <int A>
+__device__ inline void rect_hit(ConstPrims prims, int k, const Ray &r, float &best, int &bp, bool &bback)
+{
+    constexpr int U = A == 2 ? 0 : A + 1, V = A == 0 ? 2 : A - 1;
+    const float t = slab(prims[k].p[A], r, A);
+    if (!(t > 0.0f) || !(t < best)) return;
+    const float hu = __builtin_fmaf(t, r.d[U], r.o[U]), hv = __builtin_fmaf(t, r.d[V], r.o[V]);
+    if (fabsf(hu - prims[k].p[U]) > prims[k].q[0] || fabsf(hv - prims[k].p[V]) > prims[k].q[1]) return;
+    best = t;
+    bp = k;
+    bback = r.d[A] * prims[k].sign > 0.0f;
+}
+
 __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], const float d[3],
                              Hit &h)
 {
@@ -127,25 +142,21 @@ __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], co
             const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
             if (t > 0.0f && t < best) { best = t; bp = k; bback = !front; }
         } else if (kind == 1) {
-            const int a = prims[k].axis, uu = a == 2 ? 0 : a + 1, vv = a == 0 ? 2 : a - 1;
-            const float t = slab(prims[k].p[a], r, a);
-            if (!(t > 0.0f) || !(t < best)) continue;
-            const float hu = __builtin_fmaf(t, d[uu], o[uu]), hv = __builtin_fmaf(t, d[vv], o[vv]);
-            if (fabsf(hu - prims[k].p[uu]) > prims[k].q[0] || fabsf(hv - prims[k].p[vv]) > prims[k].q[1])
-                continue;
-            best = t; bp = k;
-            bback = d[a] * prims[k].sign > 0.0f;
+            const int a = prims[k].axis;
+            if (a == 0) rect_hit<0>(prims, k, r, best, bp, bback);
+            else if (a == 1) rect_hit<1>(prims, k, r, best, bp, bback);
+            else rect_hit<2>(prims, k, r, best, bp, bback);
         } else {
             const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
-            const float den = d[0] * nx + d[1] * ny + d[2] * nz;
+            const float den = r.d[0] * nx + r.d[1] * ny + r.d[2] * nz;
             if (den == 0.0f) continue;
-            const float t = ((prims[k].p[0] - o[0]) * nx + (prims[k].p[1] - o[1]) * ny +
-                             (prims[k].p[2] - o[2]) * nz) / den;
+            const float t = ((prims[k].p[0] - r.o[0]) * nx + (prims[k].p[1] - r.o[1]) * ny +
+                             (prims[k].p[2] - r.o[2]) * nz) / den;
             if (!(t > 0.0f) || !(t < best)) continue;
             float r2 = 0.0f;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float e = __builtin_fmaf(t, d[a], o[a]) - prims[k].p[a];
+            for (int c = 0; c < 3; ++c) {
+                const float e = __builtin_fmaf(t, r.d[c], r.o[c]) - prims[k].p[c];
                 r2 = __builtin_fmaf(e, e, r2);
             }
             if (r2 > prims[k].radius * prims[k].radius) continue;
@@ -158,20 +169,29 @@ __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], co
     h.back = bback;
     h.n[0] = h.n[1] = h.n[2] = 0.0f;
     if (bp < 0) return false;
+    // the winning primitive differs between lanes: per-lane loads, and the
+    // normal is assembled with selects (no indexing of a register array)
     const int kind = prims[bp].kind;
     if (kind == 0) {
         // the face whose slab distance is the hit distance: entry (front) or exit (back)
-        int ax = 0;
-        float sg = 1.0f;
+        float n3[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float t1 = slab(prims[bp].p[a], r, a), t2 = slab(prims[bp].q[a], r, a);
-            const float ta = bback ? fmaxf(t1, t2) : fminf(t1, t2);
-            if (ta == best) { ax = a; sg = (d[a] > 0.0f) != bback ? -1.0f : 1.0f; }
+        for (int c = 0; c < 3; ++c) {
+            const float t1 = slab(prims[bp].p[c], r, c), t2 = slab(prims[bp].q[c], r, c);
+            const float tc = bback ? fmaxf(t1, t2) : fminf(t1, t2);
+            n3[c] = tc == best ? ((r.d[c] > 0.0f) != bback ? -1.0f : 1.0f) : 0.0f;
         }
-        h.n[ax] = sg;
+        // a hit exactly on an edge matches two faces: keep the last, as a scan would
+        if (n3[2] != 0.0f) { n3[0] = 0.0f; n3[1] = 0.0f; }
+        else if (n3[1] != 0.0f) n3[0] = 0.0f;
+        h.n[0] = n3[0]; h.n[1] = n3[1]; h.n[2] = n3[2];
+        if (n3[0] == 0.0f && n3[1] == 0.0f && n3[2] == 0.0f) h.n[0] = (r.d[0] > 0.0f) != bback ? -1.0f : 1.0f;
     } else if (kind == 1) {
-        h.n[prims[bp].axis] = prims[bp].sign;
+        const int ax = prims[bp].axis;
+        const float sg = prims[bp].sign;
+        h.n[0] = ax == 0 ? sg : 0.0f;
+        h.n[1] = ax == 1 ? sg : 0.0f;
+        h.n[2] = ax == 2 ? sg : 0.0f;
     } else {
         h.n[0] = prims[bp].q[0]; h.n[1] = prims[bp].q[1]; h.n[2] = prims[bp].q[2];
     }
