@@ -221,12 +221,15 @@ typedef struct {
     int64_t step;
 } niv_adam;
 
-/* Scratch bytes for batches of up to max_batch samples (FP32 or FP16
- * training; BF16 is NIV_ERR_UNSUPPORTED). */
+/* Scratch bytes for batches of up to max_batch samples, 1 <= max_batch <=
+ * 2^24 (FP32 or FP16 training; BF16 is NIV_ERR_UNSUPPORTED).  About 0.2 KB
+ * per sample for the saved activations plus 12 B per (sample, level,
+ * corner) for the binned grid scatter (0.5 GB at 2^18 samples and 16
+ * levels). */
 niv_status niv_train_sizes(const niv_handle *h, niv_precision prec, int64_t max_batch,
                            int64_t *workspace_bytes);
 
-/* Loss and gradient of one batch (Eq. 3): loss = mean over samples and RGB
+/* Loss and gradient of one batch (Eq. 3), 1 <= count <= 2^24: loss = mean over samples and RGB
  * channels of (E - y)^2 / (E^2 + 0.01), the denominator held constant; the
  * gradient of every parameter is written to st->grads (overwritten), the
  * loss to st->loss.  The forward pass uses st->model at `prec` (matrix
