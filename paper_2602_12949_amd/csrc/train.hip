@@ -406,8 +406,9 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
 constexpr int kBinShift = 12;                 // 4096 entries (32 KB of FP32 pairs) per bin
 constexpr int kBinEntries = 1 << kBinShift;
 constexpr int kMaxBins = 2048;
-constexpr int kScatterBlocks = 256;           // workgroups of the count and write passes
-constexpr int kAccumRecords = 65536;          // records one accumulating workgroup takes
+constexpr int kScatterBlocks = 1024;          // workgroups of the count and write passes
+constexpr int kAccumRecords = 98304;          // records one accumulating workgroup takes (1.5x a
+                                              // hashed level's bin at 2^18 samples: those stay whole)
 
 struct ScatterArgs {
     const float *x;            // [n][3] sample positions
@@ -417,6 +418,7 @@ struct ScatterArgs {
     uint32_t *counts;          // [bins][kScatterBlocks] per workgroup, then their offsets
     uint32_t *bin_start;       // [bins + 1]
     uint32_t *work_start;      // [bins + 1] first accumulating workgroup of each bin
+    uint32_t *vmax;            // bits of the largest |contribution| of the step (>= 0 floats order as integers)
     uint32_t *keys;            // [records] entry index
     float2 *vals;              // [records] contributions of the two features
     float *grads;              // grid part of the gradient: [entries][2]
@@ -442,6 +444,7 @@ __global__ __launch_bounds__(256) void k_grid_bins(const ScatterArgs a)
     const int64_t n_chunks = (a.n + 63) / 64;
     const int64_t items = n_chunks * a.n_levels;
     ConstLevels lvs = (ConstLevels)a.model;
+    [[maybe_unused]] float vmax = 0.0f;
     const int NF = 2 * a.n_levels;
     for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < items; it += (int64_t)gridDim.x * 4) {
         const int64_t chunk = it / a.n_levels;
@@ -462,15 +465,34 @@ __global__ __launch_bounds__(256) void k_grid_bins(const ScatterArgs a)
             g0 = a.dx0[q * NF + 2 * l] * a.loss_scale;
             g1 = a.dx0[q * NF + 2 * l + 1] * a.loss_scale;
         }
+        // corners in the bin of corner 0 (all of them on coarse levels) take
+        // one counter update together; the others one each
+        const uint32_t b0 = idx[0] >> kBinShift;
+        uint32_t n0 = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) n0 += (idx[c] >> kBinShift) == b0 ? 1u : 0u;
+        uint32_t pos0 = atomicAdd(&cnt[b0], n0);
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const uint32_t b = idx[c] >> kBinShift;
-            const uint32_t pos = atomicAdd(&cnt[b], 1u);
+            uint32_t pos;
+            if (b == b0) pos = pos0++;
+            else pos = atomicAdd(&cnt[b], 1u);
             if constexpr (WRITE) {
+                const float v0 = w[c] * g0, v1 = w[c] * g1;
                 a.keys[pos] = idx[c];
-                a.vals[pos] = make_float2(w[c] * g0, w[c] * g1);
+                a.vals[pos] = make_float2(v0, v1);
+                vmax = fmaxf(vmax, fmaxf(fabsf(v0), fabsf(v1)));
             }
         }
+    }
+    if constexpr (WRITE) {   // the step's largest |contribution|, for the fixed-point sums
+        __shared__ uint32_t smax;
+        if (threadIdx.x == 0) smax = 0u;
+        __syncthreads();
+        if (vmax == vmax) atomicMax(&smax, f2u(vmax));   // NaN contributions are left out
+        __syncthreads();
+        if (threadIdx.x == 0 && smax) atomicMax(a.vmax, smax);
     }
     if constexpr (!WRITE) {
         __syncthreads();
@@ -551,12 +573,17 @@ __global__ __launch_bounds__(1024) void k_grid_scan_totals(const ScatterArgs a)
 
 // Accumulation: the records of bin b are split over work_start[b+1] -
 // work_start[b] workgroups of at most kAccumRecords records.  Each sums its
-// share in LDS; a bin taken by one workgroup is stored as is (every entry,
-// zeros included), the partial sums of a shared bin are added with atomics
-// to the zero-filled gradient (few: hot bins are the coarse dense levels).
+// share in LDS in 64-bit fixed point (LDS integer atomics run far faster than
+// LDS float atomics here, and integer sums do not depend on the order): with
+// M the step's largest |contribution| < 2^e, a value v becomes round(v 2^s),
+// s = 62 - 17 - e, so kAccumRecords < 2^17 terms cannot overflow and each
+// term is resolved to 2^-45 M.  A bin taken by one workgroup is stored as is
+// (every entry, zeros included); the partial sums of a shared bin are added
+// with atomics to the zero-filled gradient (few: hot bins are the coarse
+// dense levels).
 __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
 {
-    __shared__ float acc[2 * kBinEntries];
+    __shared__ unsigned long long acc[2 * kBinEntries];
     __shared__ int s_bin;
     const uint32_t w = blockIdx.x;
     if (w >= a.work_start[a.n_bins]) return;   // uniform over the workgroup
@@ -568,7 +595,7 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
         }
         s_bin = lo;
     }
-    for (int k = threadIdx.x; k < 2 * kBinEntries; k += 1024) acc[k] = 0.f;
+    for (int k = threadIdx.x; k < 2 * kBinEntries; k += 1024) acc[k] = 0ull;
     __syncthreads();
     const int b = s_bin;
     const uint32_t parts = a.work_start[b + 1] - a.work_start[b];
@@ -577,19 +604,41 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     const uint32_t r0 = b0 + part * (uint32_t)kAccumRecords;
     const uint32_t r1 = parts == 1 ? b1 : (r0 + kAccumRecords < b1 ? r0 + kAccumRecords : b1);
     const uint32_t base = (uint32_t)b << kBinShift;
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += 1024) {
+    int e;
+    (void)frexpf(u2f(*a.vmax), &e);            // M < 2^e (M = 0 gives e = 0: all terms are zero)
+    const int sh = 62 - 17 - e;
+    const double up = ldexp(1.0, sh), down = ldexp(1.0, -sh);
+    auto fx = [&](float v) { return (unsigned long long)(long long)__builtin_rint((double)v * up); };
+    uint32_t r = r0 + threadIdx.x;
+    // eight records per thread in flight before the LDS adds
+    for (; r + 7 * 1024 < r1; r += 8 * 1024) {
+        uint32_t i[8];
+        float2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            i[k] = a.keys[r + k * 1024] - base;
+            v[k] = a.vals[r + k * 1024];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            atomicAdd(&acc[2 * i[k]], fx(v[k].x));
+            atomicAdd(&acc[2 * i[k] + 1], fx(v[k].y));
+        }
+    }
+    for (; r < r1; r += 1024) {
         const uint32_t i = a.keys[r] - base;
         const float2 v = a.vals[r];
-        atomicAdd(&acc[2 * i], v.x);
-        atomicAdd(&acc[2 * i + 1], v.y);
+        atomicAdd(&acc[2 * i], fx(v.x));
+        atomicAdd(&acc[2 * i + 1], fx(v.y));
     }
     __syncthreads();
     const int64_t e0 = (int64_t)b << kBinShift;
     for (int k = threadIdx.x; k < 2 * kBinEntries; k += 1024) {
-        const int64_t e = e0 + (k >> 1);
-        if (e >= a.n_entries) continue;
-        if (parts == 1) a.grads[2 * e + (k & 1)] = acc[k];
-        else if (acc[k] != 0.f) atomicAdd(&a.grads[2 * e + (k & 1)], acc[k]);
+        const int64_t en = e0 + (k >> 1);
+        if (en >= a.n_entries) continue;
+        const float g = (float)((double)(long long)acc[k] * down);
+        if (parts == 1) a.grads[2 * en + (k & 1)] = g;
+        else if (g != 0.f) atomicAdd(&a.grads[2 * en + (k & 1)], g);
     }
 }
 
@@ -615,7 +664,7 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, floa
 // ---------------------------------------------------------------- host side
 struct TrainLayout {
     int64_t bwd_off, x_off, mask_off, dE_off, dx0_off, sflag_off, counts_off, start_off, work_off,
-        keys_off, vals_off, total;
+        vmax_off, keys_off, vals_off, total;
 };
 
 template <int P, class S> TrainLayout train_layout_t(int64_t n)
@@ -632,7 +681,8 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n)
     L.counts_off = L.sflag_off + align256(n);
     L.start_off = L.counts_off + align256((int64_t)kMaxBins * kScatterBlocks * 4);
     L.work_off = L.start_off + align256((kMaxBins + 1) * 4);
-    L.keys_off = L.work_off + align256((kMaxBins + 1) * 4);
+    L.vmax_off = L.work_off + align256((kMaxBins + 1) * 4);
+    L.keys_off = L.vmax_off + 256;
     const int64_t records = n * S::L * 8;
     L.vals_off = L.keys_off + align256(records * 4);
     L.total = L.vals_off + align256(records * 8);
@@ -754,6 +804,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.counts = reinterpret_cast<uint32_t *>(ws + L.counts_off);
     sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
     sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
+    sa.vmax = reinterpret_cast<uint32_t *>(ws + L.vmax_off);
     sa.keys = reinterpret_cast<uint32_t *>(ws + L.keys_off);
     sa.vals = reinterpret_cast<float2 *>(ws + L.vals_off);
     sa.grads = st.grads;
@@ -768,6 +819,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     hipLaunchKernelGGL((k_grid_bins<false>), dim3(kScatterBlocks), dim3(256), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
+    if ((e = launch_zero_u32(sa.vmax, 1, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_grid_bins<true>), dim3(kScatterBlocks), dim3(256), 0, stream, sa);
     // an upper bound of the accumulating workgroups: one per bin plus one per
     // kAccumRecords records; the excess ones return at once
