@@ -294,6 +294,17 @@ def bench_train(args, dev):
         "bake_step": {**stats(et, ep), "samples_per_s": B / (et * 1e-3)},
         "valid_fraction": float(valid.float().mean().item()),
     }
+    if not args.no_cpu:
+        # the estimator's oracle on a bounded sample: 64 points x 4096 spp
+        import oracle as O
+        xs, ns = x[:64].cpu().numpy(), n[:64].cpu().numpy()
+        t0 = time.perf_counter()
+        O.mc_irradiance(room["prims"], xs, ns, 4096, 3, O.MC_NEE, 5)
+        cs = time.perf_counter() - t0
+        res["mc_cpu_oracle"] = {"points_per_s_at_256spp": 64 * 16 / cs, "s": cs,
+                                "sample": "64 points x 4096 spp, 3 bounces, NEE, FP64 on the "
+                                          "host threads (points/s scaled to 256 spp)"}
+        log(f"[bench] MC oracle: 64 x 4096 spp in {cs:.2f} s")
     log(f"[bench] train: step {tt:.3f} ms ({B / (tt * 1e-3) / 1e6:.2f} M samples/s), "
         f"MC {mt:.1f} ms ({B / (mt * 1e-3) / 1e6:.3f} M points/s), bake step {et:.1f} ms")
     return res
