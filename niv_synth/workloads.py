@@ -39,6 +39,7 @@ class Workload:
     precision: str = "fp16"
     extra_values: Tuple[float, ...] = ()
     meshes: Tuple[Tuple[int, Tuple[float, float, float]], ...] = ()  # (seed, centre)
+    pos_bands: int = 0   # positional code of x (models without grid levels)
     notes: str = ""
 
     def model_dict(self):
@@ -47,7 +48,8 @@ class Workload:
                     per_level_scale=self.per_level_scale, sh_bands=self.sh_bands,
                     n_extra=self.n_extra, extra_bands=self.extra_bands,
                     width=self.width, n_hidden=self.n_hidden, n_out=self.n_out,
-                    aabb_min=self.aabb_min, aabb_max=self.aabb_max)
+                    aabb_min=self.aabb_min, aabb_max=self.aabb_max,
+                    pos_bands=self.pos_bands)
 
 
 WORKLOADS = {
@@ -90,6 +92,17 @@ WORKLOADS = {
         param_seed=5002, precision="bf16", extra_values=(0.0, 0.37, 1.0),
         meshes=((5101, (3.6, 1.3, 5.0)), (5102, (6.6, 1.7, 6.5)))),
 }
+
+# The room G-buffer under the grid-free models of Table 1: no grid levels, an
+# eight-band positional code of x, a four-layer network of width 16, 32 or 64
+# (Sec. 4.1).
+for _w in (16, 32, 64):
+    WORKLOADS[f"room_1080p_pe{_w}"] = Workload(
+        name=f"room_1080p_pe{_w}", n_levels=0, log2_T=17, n_features=2, base_res=16.0,
+        per_level_scale=math.sqrt(2.0), sh_bands=4, n_extra=0, extra_bands=0,
+        width=_w, n_hidden=3, n_out=3, aabb_min=ROOM_LO, aabb_max=ROOM_HI,
+        grid_init=(0.0, 0.0), frames=((1920, 1080),), scene_seeds=(2001,),
+        param_seed=2002 + _w, precision="fp16", pos_bands=8)
 
 
 def get_workload(name: str) -> Workload:

@@ -40,7 +40,8 @@ class Config(C.Structure):
                 ("base_res", C.c_double), ("per_level_scale", C.c_double),
                 ("sh_bands", C.c_int), ("n_extra", C.c_int), ("extra_bands", C.c_int),
                 ("width", C.c_int), ("n_hidden", C.c_int), ("n_out", C.c_int),
-                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3)]
+                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3),
+                ("pos_bands", C.c_int)]
 
 
 def make_config(**kw) -> Config:

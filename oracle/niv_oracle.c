@@ -48,6 +48,7 @@ typedef struct {
     int n_hidden;          /* number of hidden layers */
     int n_out;             /* outputs (3 = RGB) */
     double aabb_min[3], aabb_max[3];
+    int pos_bands;         /* positional code of x: 0 = none, else bands */
 } orc_config;
 
 /* Level table (Sec. 4.1, learned encodings).  Reading: the resolution of
@@ -75,9 +76,16 @@ int64_t orc_level_table(const orc_config *c, int64_t *res, int *dense,
     return total;
 }
 
+/* Width of the positional code of x: u itself plus a sine and a cosine
+ * per axis and band. */
+int orc_pos_dim(const orc_config *c)
+{
+    return c->pos_bands > 0 ? 3 + 6 * c->pos_bands : 0;
+}
+
 int orc_input_dim(const orc_config *c)
 {
-    return c->n_levels * c->n_features + c->sh_bands * c->sh_bands
+    return c->n_levels * c->n_features + orc_pos_dim(c) + c->sh_bands * c->sh_bands
            + c->n_extra * 2 * c->extra_bands;
 }
 
@@ -248,7 +256,35 @@ static void orc_levels_init(const orc_config *c, orc_levels *lv)
 #define ORC_FLAG_BAD_OUTPUT 4 /* non-finite output */
 #define ORC_FLAG_NEG_OUTPUT 16 /* finite output with a negative channel */
 
-/* Input vector x0 = concat(grid features level 0..L-1, SH, freq(extra)). */
+/* Positional code of x for the models without grid levels (Sec. 4.1: the
+ * smaller networks of Table 1 feed the position through the cited frequency
+ * encoding, eight bands).  Readings: the position is first mapped onto the
+ * unit cube by the box, u = (p - a_min) / (a_max - a_min), clamped as for the
+ * grid; the code is u itself followed, band by band (k = 0 .. bands-1), by
+ * sin(2^k pi u_x), sin(2^k pi u_y), sin(2^k pi u_z), then the three cosines.
+ * Returns 1 if p was outside the box. */
+int orc_pos_code(const orc_config *c, const double p[3], double *out)
+{
+    int outside = 0;
+    double u[3];
+    for (int a = 0; a < 3; ++a) {
+        double lo = c->aabb_min[a], hi = c->aabb_max[a], pc = p[a];
+        if (pc < lo) { pc = lo; outside = 1; }
+        if (pc > hi) { pc = hi; outside = 1; }
+        u[a] = (pc - lo) / (hi - lo);
+        out[a] = u[a];
+    }
+    for (int k = 0; k < c->pos_bands; ++k)
+        for (int a = 0; a < 3; ++a) {
+            double ang = ldexp(ORC_PI, k) * u[a];
+            out[3 + 6 * k + a] = sin(ang);
+            out[3 + 6 * k + 3 + a] = cos(ang);
+        }
+    return outside;
+}
+
+/* Input vector x0 = concat(grid features level 0..L-1, positional code,
+ * SH, freq(extra)). */
 static int orc_encode(const orc_config *c, const orc_levels *lv,
                       const double *grid, const double p[3], const double n[3],
                       const double *extra, double *x0)
@@ -269,6 +305,10 @@ static int orc_encode(const orc_config *c, const orc_levels *lv,
         }
     }
     int k = c->n_levels * F;
+    if (c->pos_bands > 0) {
+        flags |= orc_pos_code(c, p, x0 + k) ? ORC_FLAG_OUTSIDE : 0;
+        k += orc_pos_dim(c);
+    }
     if (c->sh_bands > 0) {
         double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         double u[3] = {n[0] / len, n[1] / len, n[2] / len};

@@ -418,3 +418,107 @@ def test_lr_schedule_endpoints():
     assert O.lr_at(3000, 1000, 5000) == pytest.approx(1e-3, rel=1e-12)
     assert O.lr_at(5000, 1000, 5000) == pytest.approx(1e-4, rel=1e-12)
     assert O.lr_at(9000, 1000, 5000) == pytest.approx(1e-4, rel=1e-12)
+
+
+# ------------------------------------------------------------ positional code (grid-free models)
+def _pe_cfg(width=16, **kw):
+    base = dict(n_levels=0, log2_T=17, n_features=2, base_res=16.0,
+                per_level_scale=math.sqrt(2.0), sh_bands=4, n_extra=0, extra_bands=0,
+                width=width, n_hidden=3, n_out=3, aabb_min=(0.0, 0.0, 0.0),
+                aabb_max=(10.0, 4.0, 10.0), pos_bands=8)
+    base.update(kw)
+    return O.make_config(**base)
+
+
+def test_table1_memory_grid_free_rows():
+    """Half-precision parameter bytes of the grid-free networks reproduce the
+    first three memory entries of Table 1, which pins the input width (67)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_memory_pe.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for width, mb, digits in rows:
+        c = _pe_cfg(int(width))
+        assert O.input_dim(c) == 67
+        assert O.n_grid_values(c) == 0
+        nbytes = 2 * O.n_params(c)
+        assert round(nbytes / 1e6, int(digits)) == pytest.approx(float(mb)), (width, nbytes)
+    # the alternatives named in the fixture do not fit the width-64 row
+    for din in (64, 51):
+        nbytes = 2 * (64 * din + 2 * 64 * 64 + 3 * 64)
+        assert round(nbytes / 1e6, 2) != 0.03
+
+
+def test_positional_code_closed_form():
+    """At u = 1/2 and u = 1/4 on every axis, sin and cos of 2^k pi u take
+    exact values; the code is [u, per band three sines then three cosines]
+    followed by the SH of the normal."""
+    c = _pe_cfg()
+    lo, hi = np.array([0.0, 0.0, 0.0]), np.array([10.0, 4.0, 10.0])
+    params = np.zeros(O.n_params(c))
+    for frac in (0.5, 0.25):
+        pos = (lo + frac * (hi - lo)).astype(np.float32)[None]
+        nrm = np.array([[0.0, 0.0, 1.0]], np.float32)
+        _, _, fl, x0 = O.query(c, params, pos, nrm, want_x0=True)
+        assert fl[0] == 0
+        x0 = x0[0]
+        np.testing.assert_allclose(x0[:3], frac, rtol=0, atol=1e-15)
+        for k in range(8):
+            # angle 2^k pi frac: multiples of pi/2 for frac = 1/2, pi/4 for 1/4
+            q = (2 ** k) * frac * 2          # angle in units of pi/2
+            if frac == 0.5:
+                s = [0.0, 1.0, 0.0, -1.0][int(q) % 4]
+                co = [1.0, 0.0, -1.0, 0.0][int(q) % 4]
+            else:
+                if k == 0:
+                    s = co = math.sqrt(0.5)   # pi/4
+                else:
+                    s = [0.0, 1.0, 0.0, -1.0][int(q) % 4]
+                    co = [1.0, 0.0, -1.0, 0.0][int(q) % 4]
+            np.testing.assert_allclose(x0[3 + 6 * k: 6 + 6 * k], s, atol=1e-12)
+            np.testing.assert_allclose(x0[6 + 6 * k: 9 + 6 * k], co, atol=1e-12)
+        # SH of +z: Y00, Y1-1 = 0, Y10 = sqrt(3/(4 pi)), ...
+        np.testing.assert_allclose(x0[51], 0.5 / math.sqrt(math.pi), atol=1e-15)
+        np.testing.assert_allclose(x0[53], math.sqrt(3.0 / (4 * math.pi)), atol=1e-15)
+
+
+def test_positional_code_outside_box_clamps_and_flags():
+    c = _pe_cfg()
+    params = np.zeros(O.n_params(c))
+    pos = np.array([[-1.0, 2.0, 11.0], [5.0, 2.0, 5.0]], np.float32)
+    nrm = np.array([[0.0, 1.0, 0.0]] * 2, np.float32)
+    _, _, fl, x0 = O.query(c, params, pos, nrm, want_x0=True)
+    assert fl.tolist() == [1, 0]
+    np.testing.assert_allclose(x0[0, :3], [0.0, 0.5, 1.0], atol=1e-15)
+    np.testing.assert_allclose(x0[1, :3], [0.5, 0.5, 0.5], atol=1e-15)
+
+
+def test_positional_code_pairs_on_unit_circle():
+    """Every (sin, cos) pair lies on the unit circle, and band k + 1 follows
+    band k by the double-angle formulas."""
+    c = _pe_cfg()
+    rng = np.random.default_rng(11)
+    pos = (rng.random((64, 3)) * [10.0, 4.0, 10.0]).astype(np.float32)
+    nrm = rng.normal(size=(64, 3)).astype(np.float32)
+    _, _, _, x0 = O.query(c, np.zeros(O.n_params(c)), pos, nrm, want_x0=True)
+    s = np.stack([x0[:, 3 + 6 * k: 6 + 6 * k] for k in range(8)], 1)
+    co = np.stack([x0[:, 6 + 6 * k: 9 + 6 * k] for k in range(8)], 1)
+    np.testing.assert_allclose(s ** 2 + co ** 2, 1.0, atol=1e-14)
+    np.testing.assert_allclose(s[:, 1:], 2 * s[:, :-1] * co[:, :-1], atol=1e-12)
+    np.testing.assert_allclose(co[:, 1:], 1 - 2 * s[:, :-1] ** 2, atol=1e-12)
+    # band 0 recovers u: u = atan2(sin, cos) / pi on [0, 1]
+    np.testing.assert_allclose(np.arctan2(s[:, 0], co[:, 0]) / np.pi, x0[:, :3], atol=1e-12)
+
+
+def test_grid_free_mlp_matches_numpy():
+    """The grid-free network is the plain matrix chain on the code."""
+    c = _pe_cfg(32)
+    rng = np.random.default_rng(12)
+    params = make_params(0, O.mat_shapes(c), 5, 0.0, 0.0).astype(np.float64)
+    pos = (rng.random((50, 3)) * [10.0, 4.0, 10.0]).astype(np.float32)
+    nrm = rng.normal(size=(50, 3)).astype(np.float32)
+    E, _, _, x0 = O.query(c, params, pos, nrm, want_x0=True)
+    mats = O.split_params(c, params)[1:]
+    h = x0
+    for W in mats[:-1]:
+        h = np.maximum(h @ W.T, 0.0)
+    np.testing.assert_allclose(E, h @ mats[-1].T, rtol=1e-12, atol=1e-14)
