@@ -16,7 +16,10 @@ Also measured, as extra fields of the same JSON line:
               models, one persistent launch replayed from a HIP graph, after
               the autotuner; with and without the Monte Carlo fallback (64 spp);
   field_4k    room_4k_6d: 3840x2160 G-buffer with two displaced icospheres,
-              scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16.
+              scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16;
+  table1      room_1080p_pe16/32/64: the same 1080p G-buffer under the
+              grid-free models of Table 1 (eight-band positional code of x,
+              three hidden layers of width 16, 32 or 64), FP16.
 
 Kernel times come from HIP events recorded on the stream the kernels are
 launched on (torch's current stream).  Prints one JSON line on stdout;
@@ -24,8 +27,8 @@ progress goes to stderr.
 
 `--profile CASE` runs only that case's kernel a few times (for rocprofv3
 counter and trace runs): query_fp16, query_fp32, query_bf16, field_4k,
-train_step, mc, copy (a 1 GiB device copy that calibrates the HBM byte
-counters).
+train_step, mc, pe16, pe32, pe64, copy (a 1 GiB device copy that calibrates
+the HBM byte counters).
 """
 import argparse
 import hashlib
@@ -59,8 +62,9 @@ def log(*a):
 
 
 def mlp_flops(cfg):
-    din = cfg["n_levels"] * cfg["n_features"] + cfg["sh_bands"] ** 2 + \
-        cfg["n_extra"] * 2 * cfg["extra_bands"]
+    pb = cfg.get("pos_bands", 0)
+    din = cfg["n_levels"] * cfg["n_features"] + (3 + 6 * pb if pb > 0 else 0) + \
+        cfg["sh_bands"] ** 2 + cfg["n_extra"] * 2 * cfg["extra_bands"]
     W = cfg["width"]
     macs = W * din + (cfg["n_hidden"] - 1) * W * W + cfg["n_out"] * W
     return 2 * macs
@@ -430,6 +434,51 @@ def bench_field_4k(args, dev):
     }
 
 
+def bench_table1(args, dev):
+    """The grid-free rows of Table 1 on the room_1080p G-buffer, FP16."""
+    import torch
+    import oracle as O
+    from niv_synth import get_workload, make_params, make_room_gbuffer
+    from paper_2602_12949_amd import NIV
+    w0 = get_workload("room_1080p_pe16")
+    Wd, Ht = w0.frames[0]
+    _, g = make_room_gbuffer(w0.scene_seeds[0], Wd, Ht)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = dict(pos=t(g["pos"]), nrm=t(g["nrm"]), alb=t(g["albedo"]), mask=t(g["mask"]))
+    mask = g["mask"].reshape(-1)
+    n_valid = int(mask.sum())
+    rng = np.random.default_rng(6)
+    s = rng.choice(len(mask), 8192, replace=False)
+    s = s[mask[s] > 0]
+    pos, nrm = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3)
+    rows = {}
+    for width in (16, 32, 64):
+        w = get_workload(f"room_1080p_pe{width}")
+        m = NIV(w.model_dict())
+        params = make_params(0, m.mat_shapes(), w.param_seed, *w.grid_init)
+        pm = m.prepare(t(params), "fp16")
+        f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"])
+        tune = m.autotune([f], "fp16")
+        graph = m.capture([f], "fp16")
+        tt, tp = time_steps(graph.launch, args.steps, args.warmup)
+        torch.cuda.synchronize()
+        E = outs[0].reshape(-1, 3).cpu().numpy().astype(np.float64)[s]
+        oc = O.config_from_workload(w)
+        ref, _, _ = O.query(oc, round_params(params, "fp16"), pos[s], nrm[s])
+        err = float(np.linalg.norm(E - ref) / np.linalg.norm(ref))
+        fl = mlp_flops(w.model_dict()) * n_valid
+        rows[f"pe{width}"] = {
+            **stats(tt, tp), "ms_per_frame": tt, "queries_per_s": n_valid / (tt * 1e-3),
+            "params_MB_fp16": 2 * m.n_params / 1e6, "sampled_rel_l2": err,
+            "mlp_tflops": fl / (tt * 1e-3) / 1e12,
+            "autotune": {k: tune[k] for k in ("block", "blocks_per_cu", "xcd_order")}}
+        log(f"[bench] room_1080p_pe{width} fp16: {tt:.4f} ms/frame, sampled rel-L2 {err:.2e}")
+        del graph
+    return {"workload": "room_1080p G-buffer, grid-free models: u + 8-band positional code of x, "
+                        "SH-16, MLP 67-W-W-W-3 (W = 16, 32, 64), FP16",
+            "valid_pixels": n_valid, "rows": rows}
+
+
 # ---------------------------------------------------------------- profiling cases
 def profile_case(case, steps, tune=None):
     import torch
@@ -482,6 +531,23 @@ def profile_case(case, steps, tune=None):
         torch.cuda.synchronize()
         log(f"[profile] {case}: done")
         return
+    if case.startswith("pe") and case[2:].isdigit():
+        from niv_synth import get_workload, make_params, make_room_gbuffer
+        from paper_2602_12949_amd import NIV
+        w = get_workload(f"room_1080p_{case}")
+        _, g = make_room_gbuffer(w.scene_seeds[0], *w.frames[0])
+        m = NIV(w.model_dict())
+        if tune:
+            m.set_tune("fp16", *tune)
+        params = make_params(0, m.mat_shapes(), w.param_seed, *w.grid_init)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        pm = m.prepare(t(params), "fp16")
+        f, _ = m.frame(t(g["pos"]), t(g["nrm"]), pm, albedo=t(g["albedo"]), mask=t(g["mask"]))
+        for _ in range(2 * steps):
+            m.query_frames([f], "fp16")
+        torch.cuda.synchronize()
+        log(f"[profile] {case}: done")
+        return
     if case == "field_4k":
         from niv_synth import get_workload, make_params, make_workload_gbuffer
         from paper_2602_12949_amd import NIV
@@ -510,7 +576,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precisions", default="fp16,fp32,bf16")
-    ap.add_argument("--only", default="query,train,batched,field_4k",
+    ap.add_argument("--only", default="query,train,batched,field_4k,table1",
                     help="comma list of parts to run")
     ap.add_argument("--profile", default=None, help="run one kernel case for rocprofv3")
     ap.add_argument("--tune", default=None,
@@ -566,6 +632,8 @@ def main():
         extra["batched"] = bench_batched(args, dev)
     if "field_4k" in parts:
         extra["field_4k"] = bench_field_4k(args, dev)
+    if "table1" in parts:
+        extra["table1"] = bench_table1(args, dev)
 
     line = {
         "metric": "1080p NIV query ms/frame, FP16-MFMA vs FP32 at stated err; train samples/s",

@@ -44,13 +44,18 @@ typedef enum { NIV_FP32 = 0, NIV_FP16 = 1, NIV_BF16 = 2 } niv_precision;
  * per_level_scale^l); it is stored densely ((N+1)^3 entries, x fastest) when
  * that fits in T = 2^log2_T entries, else hashed into T entries with the
  * primes 1, 2654435761, 805459861.  The input vector is the concatenation
- * of the n_levels * n_features grid features (level-major), sh_bands^2 real
- * spherical harmonics of the unit normal, and for each scene variable the
- * 2*extra_bands values sin(2^k pi t), cos(2^k pi t) (Sec. 6).  Hidden layers
- * are width wide with ReLU, no biases; the output layer is linear.
- * Supported by the kernels: n_features = 2, n_levels a multiple of 4 (<= 32),
- * sh_bands = 4, width 64 or 128, 1 <= n_hidden <= 8, n_out = 3, and an input
- * width that is a multiple of 16. */
+ * of the n_levels * n_features grid features (level-major), the positional
+ * code of x when pos_bands > 0 (the grid-free models of Table 1: u = the
+ * position mapped onto the unit cube by the box, then per band k <
+ * pos_bands sin(2^k pi u_x..z) and cos(2^k pi u_x..z), 3 + 6 pos_bands
+ * values), sh_bands^2 real spherical harmonics of the unit normal, and for
+ * each scene variable the 2*extra_bands values sin(2^k pi t), cos(2^k pi t)
+ * (Sec. 6).  Hidden layers are width wide with ReLU, no biases; the output
+ * layer is linear.
+ * Supported by the kernels: n_features = 2, sh_bands = 4, n_out = 3, and
+ * either a grid (n_levels 8 or 16, pos_bands 0: width 64 with 2 or 3 hidden
+ * layers, or width 128 with 4 hidden layers and one scene variable) or no
+ * grid (n_levels 0, pos_bands 8, width 16, 32 or 64, 3 hidden layers). */
 typedef struct {
     int32_t n_levels, log2_T, n_features;
     double  base_res, per_level_scale;
@@ -58,6 +63,7 @@ typedef struct {
     int32_t n_extra, extra_bands;
     int32_t width, n_hidden, n_out;
     double  aabb_min[3], aabb_max[3];   /* box mapped onto every level */
+    int32_t pos_bands;                  /* 0, or bands of the positional code */
 } niv_config;
 
 typedef struct niv_handle niv_handle;

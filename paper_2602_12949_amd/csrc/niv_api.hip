@@ -44,14 +44,16 @@ void build_levels(Model &m)
     }
     m.n_entries = total;
     m.n_grid_values = total * c.n_features;
-    m.din = c.n_levels * c.n_features + c.sh_bands * c.sh_bands + c.n_extra * 2 * c.extra_bands;
+    m.din = c.n_levels * c.n_features + (c.pos_bands > 0 ? 3 + 6 * c.pos_bands : 0) +
+            c.sh_bands * c.sh_bands + c.n_extra * 2 * c.extra_bands;
     m.n_params = m.n_grid_values + (int64_t)c.width * m.din +
                  (int64_t)(c.n_hidden - 1) * c.width * c.width + (int64_t)c.n_out * c.width;
 }
 
 niv_status check_config(const niv_config *c)
 {
-    if (c->n_levels < 1 || c->n_levels > kMaxLevels || c->log2_T < 1 || c->log2_T > 24 ||
+    if (c->n_levels < 0 || c->n_levels > kMaxLevels || c->pos_bands < 0 || c->pos_bands > 16 ||
+        (c->n_levels == 0 && c->pos_bands == 0) || c->log2_T < 1 || c->log2_T > 24 ||
         c->n_features < 1 || c->n_features > 8 || !(c->base_res >= 1.0) ||
         !(c->per_level_scale >= 1.0) || c->sh_bands < 0 || c->sh_bands > 8 || c->n_extra < 0 ||
         c->n_extra > 4 || c->extra_bands < 0 || c->extra_bands > 16 || c->width < 1 ||
@@ -61,8 +63,10 @@ niv_status check_config(const niv_config *c)
         if (!(c->aabb_max[a] > c->aabb_min[a]) || !isfinite(c->aabb_min[a]) ||
             !isfinite(c->aabb_max[a]))
             return NIV_ERR_INVALID_ARG;
-    double top = c->base_res * pow(c->per_level_scale, (double)(c->n_levels - 1));
-    if (!(top < 2147483647.0 / 2)) return NIV_ERR_INVALID_ARG;
+    if (c->n_levels > 0) {
+        double top = c->base_res * pow(c->per_level_scale, (double)(c->n_levels - 1));
+        if (!(top < 2147483647.0 / 2)) return NIV_ERR_INVALID_ARG;
+    }
     return NIV_OK;
 }
 
@@ -76,6 +80,11 @@ int kernel_kind(const Model &m)
     for (int l = 0; l < c.n_levels; ++l)
         if (!m.dense[l] && m.res[l] + 1 > (int64_t(1) << c.log2_T)) return -1;
     if (m.n_entries > (int64_t)0xFFFFFFFF / 2) return -1;
+    if (c.n_levels == 0) {  // grid-free models of Table 1
+        if (c.pos_bands != 8 || c.n_extra != 0 || c.n_hidden != 3) return -1;
+        return c.width == 16 ? kPE16 : c.width == 32 ? kPE32 : c.width == 64 ? kPE64 : -1;
+    }
+    if (c.pos_bands != 0) return -1;
     if (c.n_levels == 8 && c.n_extra == 0 && c.width == 64 && c.n_hidden == 2) return kUnitCube;
     if (c.n_levels == 16 && c.n_extra == 0 && c.width == 64 && c.n_hidden == 3) return kRoom;
     if (c.n_levels == 16 && c.n_extra == 1 && c.width == 128 && c.n_hidden == 4) return kWide6D;
@@ -180,6 +189,8 @@ static void fill_args(const niv_handle *h, const niv_frame *frames, int n, niv_p
     for (int c = 0; c < 3; ++c) {
         a.lo[c] = h->m.cfg.aabb_min[c];
         a.hi[c] = h->m.cfg.aabb_max[c];
+        a.pe_k[c] = 1.0 / (a.hi[c] - a.lo[c]);
+        a.pe_o[c] = -(a.lo[c] * a.pe_k[c]);
     }
     for (int f = 0; f < n; ++f) {
         const niv_frame &fr = frames[f];

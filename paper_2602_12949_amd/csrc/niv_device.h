@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "niv_internal.h"
 
@@ -67,9 +68,10 @@ template <> struct Prec<NIV_BF16> {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
                                                        __builtin_bit_cast(bf8, b), c, 0, 0, 0);
     }
+    // as for FP16: the K = 16 BF16 instruction gave wrong accumulators for
+    // the last tile of a wave on this target, the zero-padded K = 32 one not
     __device__ static f4 mma_half(u2 a, u2 b, f4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a),
-                                                         __builtin_bit_cast(s4, b), c, 0, 0, 0);
+        return mma((u4){a.x, a.y, 0u, 0u}, (u4){b.x, b.y, 0u, 0u}, c);
     }
     __device__ static uint32_t pack(float x, float y) {
         bf2 v = __builtin_convertvector((f2){x, y}, bf2);
@@ -114,20 +116,48 @@ template <> struct Prec<NIV_FP32> {
 // elements it feeds to the matrix cores (for the four pixels it serves, one
 // per 16-pixel tile), so no per-wave staging block in LDS is needed and the
 // whole LDS can hold the weights.
-template <int L_, int NEX_, int W_, int H_, bool SL_ = false> struct Shape {
-    static constexpr int L = L_, NEX = NEX_, W = W_, H = H_;
+// PB_: bands of the positional code of x (grid-free models, L_ = 0).
+//
+// Layer-0 columns.  The parameters of W_0 follow the input vector of the
+// model: [grid 2L][u 3, bands 6 PB][SH 16][scene variables 16 NEX].  The
+// kernels order the columns as [grid 2L][bands 6 PB][u 3][0][SH 16][scene
+// variables][0 ...] so that 16-bit pairs never straddle two parts, padded
+// with zero columns to a multiple of 16; in_col maps a kernel column to its
+// parameter column (or -1 for a zero column).
+template <int L_, int NEX_, int W_, int H_, bool SL_ = false, int PB_ = 0> struct Shape {
+    static constexpr int L = L_, NEX = NEX_, W = W_, H = H_, PB = PB_;
     static constexpr bool SL = SL_;
-    static constexpr int DIN = 2 * L + 16 + 16 * NEX;  // F = 2, 16 SH, 16 per variable
+    static constexpr int PEW_IN = PB > 0 ? 3 + 6 * PB : 0;       // positional code
+    static constexpr int PEW = PB > 0 ? PEW_IN + 1 : 0;           // with its zero column
+    static constexpr int DIN_IN = 2 * L + PEW_IN + 16 + 16 * NEX; // F = 2, 16 SH, 16 per variable
+    static constexpr int DIN = (2 * L + PEW + 16 + 16 * NEX + 15) / 16 * 16;
     static constexpr int KLG = DIN / 4;                // input slots per lane group
     static constexpr int NOB = W / 16;                 // 16-row output blocks
-    static_assert(DIN % 16 == 0, "input width must be a multiple of 16");
-    static_assert(!SL || (L == 16 && DIN == 64), "lane slices need 16 levels and 64 inputs");
-    static_assert(L % 4 == 0 && W % 32 == 0, "shape");
+    static_assert(!SL || (L == 16 && DIN == 64 && PB == 0), "lane slices need 16 levels and 64 inputs");
+    static_assert(L % 4 == 0 && W % 16 == 0 && W >= 16, "shape");
+    static_assert(PB == 0 || L == 0, "positional code only without grid levels");
+    __host__ __device__ static constexpr int in_col(int kc)
+    {
+        if (kc < 2 * L) return kc;
+        int r = kc - 2 * L;
+        if (PB > 0) {
+            if (r < 6 * PB) return 2 * L + 3 + r;          // bands
+            if (r < 6 * PB + 3) return 2 * L + (r - 6 * PB);  // u
+            if (r == 6 * PB + 3) return -1;
+            r -= PEW;
+        }
+        return r < 16 + 16 * NEX ? 2 * L + PEW_IN + r : -1;
+    }
 };
 
 using ShapeUnitCube = Shape<8, 0, 64, 2>;
 using ShapeRoom = Shape<16, 0, 64, 3>;
 using ShapeWide6D = Shape<16, 1, 128, 4, true>;
+// FP32 weights of the wide network (232 KB) do not fit in LDS: that
+// precision stages the inputs and reads the weights from memory.
+template <int P> using ShapeWide6DFor =
+    typename std::conditional<P == NIV_FP32, Shape<16, 1, 128, 4>, ShapeWide6D>::type;
+template <int W> using ShapePE = Shape<0, 0, W, 3, false, 8>;
 
 // Lane-sliced layer-0 input order.  Virtual element v (0..15) of lane group
 // g: v < 8 is feature v % 2 of level 4 (v / 2) + g; then SH coefficients
@@ -138,7 +168,9 @@ __host__ __device__ constexpr int slice_col(int v, int g)
     return v < 8 ? 2 * (4 * (v >> 1) + g) + (v & 1) : (v < 12 ? 32 + 4 * g + (v - 8) : 48 + 4 * g + (v - 12));
 }
 
-// Byte layout of the operand block of a prepared model.
+// Byte layout of the operand block of a prepared model.  16-bit layers
+// whose contraction depth is not a multiple of 32 end with one half-depth
+// (K = 16) operand per output block.
 template <int P, class S> struct Ops {
     static constexpr bool F32 = (P == NIV_FP32);
     static constexpr int ES = F32 ? 4 : 2;
@@ -149,9 +181,12 @@ template <int P, class S> struct Ops {
     static constexpr int L0_HALF = F32 ? 0 : (S::KLG % 8) / 4;
     static constexpr int L0_OB = L0_FULL * OPB + L0_HALF * OPS;    // bytes per output block
     static constexpr int L0_BYTES = S::NOB * L0_OB;
-    static constexpr int HOPS = F32 ? S::W / 4 : S::W / 32;         // operands per block row
-    static constexpr int HID_BYTES = S::NOB * HOPS * OPB;
-    static constexpr int OUT_BYTES = HOPS * OPB;                    // rows 0..2 = W_H
+    static constexpr int HF = F32 ? S::W / 4 : S::W / 32;           // full operands per block row
+    static constexpr int HH = F32 ? 0 : (S::W % 32) / 16;           // half-depth operands per row
+    static constexpr int HOPS = HF + HH;
+    static constexpr int HROW = HF * OPB + HH * OPS;                // bytes per block row
+    static constexpr int HID_BYTES = S::NOB * HROW;
+    static constexpr int OUT_BYTES = HROW;                          // rows 0..2 = W_H
     static constexpr int W_BYTES = L0_BYTES + (S::H - 1) * HID_BYTES + OUT_BYTES;
     static constexpr int N_OPS = S::NOB * (L0_FULL + L0_HALF) + (S::H - 1) * S::NOB * HOPS + HOPS;
     // BF16 operands are split into hi + lo parts (two products each)
@@ -166,14 +201,14 @@ __host__ __device__ constexpr int64_t align256(int64_t x) { return (x + 255) & ~
 
 // ---------------------------------------------------------------- prepare
 // Source parameter index of element `e` of lane `lane` of operand `op`, or -1
-// for a zero.  Parameters: [grid][W_0 (W x DIN)][W_1..W_{H-1} (W x W)][W_H (3 x W)].
+// for a zero.  Parameters: [grid][W_0 (W x DIN_IN)][W_1..W_{H-1} (W x W)][W_H (3 x W)].
 template <int P, class S>
 __device__ int64_t operand_source(int op, int lane, int e, int64_t n_grid, int n_out)
 {
     using O = Ops<P, S>;
     const int i = lane & 15, g = lane >> 4;
     const int64_t w0 = n_grid;
-    const int64_t wh = w0 + (int64_t)S::W * S::DIN;
+    const int64_t wh = w0 + (int64_t)S::W * S::DIN_IN;
     const int64_t wo = wh + (int64_t)(S::H - 1) * S::W * S::W;
     const int n0 = S::NOB * (O::L0_FULL + O::L0_HALF);
     const int nh = (S::H - 1) * S::NOB * O::HOPS;
@@ -181,10 +216,14 @@ __device__ int64_t operand_source(int op, int lane, int e, int64_t n_grid, int n
         int ob = op / (O::L0_FULL + O::L0_HALF), c = op % (O::L0_FULL + O::L0_HALF);
         int slot = O::F32 ? c : (c < O::L0_FULL ? c * 8 + e : O::L0_FULL * 8 + e);
         int row = 16 * ob + i, col = S::SL ? slice_col(slot, g) : S::KLG * g + slot;
-        return w0 + (int64_t)row * S::DIN + col;
+        const int pc = S::in_col(col);
+        if (pc < 0) return -1;
+        return w0 + (int64_t)row * S::DIN_IN + pc;
     }
     op -= n0;
     int col;
+    // contraction column of element e of lane group g in operand kb of a
+    // block row (a half-depth operand covers 16 columns, 4 per lane group)
     auto hidden_col = [&](int kb) {
         return O::F32 ? 16 * (kb / 4) + 4 * g + (kb % 4)
                       : 16 * (2 * kb + e / 4) + 4 * g + (e % 4);
@@ -216,8 +255,10 @@ __device__ void operand_place(int op, int64_t *off, int *n_elem)
         *n_elem = (c < O::L0_FULL) ? O::EPO : 4;
         return;
     }
-    *off = O::L0_BYTES + (int64_t)(op - n0) * O::OPB;
-    *n_elem = O::EPO;
+    op -= n0;  // hidden rows, then the output row: HOPS operands per block row
+    const int row = op / O::HOPS, kb = op % O::HOPS;
+    *off = O::L0_BYTES + (int64_t)row * O::HROW + (int64_t)kb * O::OPB;
+    *n_elem = kb < O::HF ? O::EPO : 4;
 }
 
 // ---------------------------------------------------------------- encoding
@@ -242,6 +283,66 @@ __device__ inline void sh16(float x, float y, float z, float *o)
     o[13] = -0.4570457994644658f * x * (5.0f * zz - 1.0f);
     o[14] = 1.445305721320277f * z * (xx - yy);
     o[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// sin(pi r) and cos(pi r) for |r| <= 1/2 from their Taylor series about 0,
+// to degree 11 and 12; on that range the first omitted terms are below
+// 5.7e-8 and 6.4e-9.  Coefficients (-1)^k pi^n / n! are formed at compile
+// time in double precision.
+constexpr double taylor_pi(int n)
+{
+    double v = 1.0;
+    for (int k = 1; k <= n; ++k) v *= 3.14159265358979323846 / k;
+    return (n / 2) % 2 ? -v : v;
+}
+__device__ inline void sincospi_half(float r, float &s, float &c)
+{
+    const float x2 = r * r;
+    float ps = (float)taylor_pi(11);
+    ps = __builtin_fmaf(ps, x2, (float)taylor_pi(9));
+    ps = __builtin_fmaf(ps, x2, (float)taylor_pi(7));
+    ps = __builtin_fmaf(ps, x2, (float)taylor_pi(5));
+    ps = __builtin_fmaf(ps, x2, (float)taylor_pi(3));
+    ps = __builtin_fmaf(ps, x2, (float)taylor_pi(1));
+    s = ps * r;
+    float pc = (float)taylor_pi(12);
+    pc = __builtin_fmaf(pc, x2, (float)taylor_pi(10));
+    pc = __builtin_fmaf(pc, x2, (float)taylor_pi(8));
+    pc = __builtin_fmaf(pc, x2, (float)taylor_pi(6));
+    pc = __builtin_fmaf(pc, x2, (float)taylor_pi(4));
+    pc = __builtin_fmaf(pc, x2, (float)taylor_pi(2));
+    c = __builtin_fmaf(pc, x2, 1.0f);
+}
+
+// Positional code of one coordinate u in [0, 1] given as u = uh + ul (two
+// floats): sin and cos of 2^b pi u for b < PB.  2^b u = th + tl exactly;
+// n = rint(th) and th - n are exact (Sterbenz), so r = (th - n) + tl is the
+// reduced argument with one rounding, and sin(pi (n + r)) = (-1)^n sin(pi r)
+// (the same for cos).  DOUBLING (for 16-bit operands): only every fourth
+// band is evaluated so; the three after it follow from the double-angle
+// formulas sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a, which at most
+// multiply the error of the evaluated band by 8 (about 1.3e-6, far below
+// the rounding of a 16-bit operand).
+template <int PB, bool DOUBLING>
+__device__ inline void pos_code_axis(float uh, float ul, float *sv, float *cv)
+{
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+        if (DOUBLING && (b % 4) != 0) {
+            const float s0 = sv[b - 1], c0 = cv[b - 1];
+            sv[b] = 2.0f * (s0 * c0);
+            cv[b] = __builtin_fmaf(-2.0f * s0, s0, 1.0f);
+            continue;
+        }
+        const float th = uh * (float)(1 << b), tl = ul * (float)(1 << b);
+        const float n = __builtin_rintf(th);
+        const float r = (th - n) + tl;
+        float sr, cr;
+        sincospi_half(r, sr, cr);
+        const uint32_t flip = (uint32_t)(int32_t)n << 31;
+        sv[b] = u2f(f2u(sr) ^ flip);
+        cv[b] = u2f(f2u(cr) ^ flip);
+    }
 }
 
 template <int P>

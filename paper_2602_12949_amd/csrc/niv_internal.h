@@ -56,6 +56,7 @@ struct QueryArgs {
     uint32_t grid_bytes;      // size of the grid latents (bounds of the buffer loads)
     uint32_t fb_mask;         // flag bits that send a pixel to the Monte Carlo fallback
     double lo[3], hi[3];      // box the positions are clamped to
+    double pe_k[3], pe_o[3];  // u = fma(p, pe_k, pe_o) on the unit cube (positional code)
     uint32_t *fb_list;        // fallback list: (frame << 28) | pixel, or null
     uint32_t *fb_count;       // entries appended (may exceed fb_cap)
     uint32_t fb_cap;
@@ -74,7 +75,7 @@ struct QueryArgs {
 };
 
 // Shapes the fused kernels are instantiated for.
-enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kNumKinds = 3 };
+enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kPE16 = 3, kPE32 = 4, kPE64 = 5, kNumKinds = 6 };
 
 // Launch shape of the fused query: workgroup size and resident workgroups
 // per CU (0 = as many as fit); chosen by niv_autotune, else defaults.

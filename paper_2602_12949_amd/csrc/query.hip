@@ -68,7 +68,10 @@ OpLayout op_layout(int kind, niv_precision prec)
     switch (kind) {                                                     \
     case kUnitCube: return layout_of<P, ShapeUnitCube>();               \
     case kRoom: return layout_of<P, ShapeRoom>();                       \
-    default: return layout_of<P, ShapeWide6D>();                        \
+    case kPE16: return layout_of<P, ShapePE<16>>();                     \
+    case kPE32: return layout_of<P, ShapePE<32>>();                     \
+    case kPE64: return layout_of<P, ShapePE<64>>();                     \
+    default: return layout_of<P, ShapeWide6DFor<P>>();                  \
     }
     if (prec == NIV_FP32) { NIV_LAYOUT(NIV_FP32) }
     if (prec == NIV_FP16) { NIV_LAYOUT(NIV_FP16) }
@@ -91,6 +94,7 @@ static hipError_t prepare_t(const Model &m, const float *params, void *prepared,
                        params, out + kLevelBytes, m.n_grid_values, m.cfg.n_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (m.n_grid_values == 0) return hipSuccess;
     int64_t blocks = (m.n_grid_values + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((k_prepare_grid<P>), dim3((unsigned)blocks), dim3(256), 0, st, params,
@@ -105,7 +109,10 @@ hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
     switch (m.kind) {                                                                    \
     case kUnitCube: return prepare_t<P, ShapeUnitCube>(m, params, prepared, st);        \
     case kRoom: return prepare_t<P, ShapeRoom>(m, params, prepared, st);                \
-    default: return prepare_t<P, ShapeWide6D>(m, params, prepared, st);                 \
+    case kPE16: return prepare_t<P, ShapePE<16>>(m, params, prepared, st);              \
+    case kPE32: return prepare_t<P, ShapePE<32>>(m, params, prepared, st);              \
+    case kPE64: return prepare_t<P, ShapePE<64>>(m, params, prepared, st);              \
+    default: return prepare_t<P, ShapeWide6DFor<P>>(m, params, prepared, st);           \
     }
     if (prec == NIV_FP32) { NIV_PREP(NIV_FP32) }
     if (prec == NIV_FP16) { NIV_PREP(NIV_FP16) }
@@ -113,14 +120,23 @@ hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
 #undef NIV_PREP
 }
 
+// LDS of one workgroup: the operand block (WLDS) and the per-wave staging
+// rows, or the level table for the lane-sliced encoding.
+template <int P, class S, bool WLDS, int BLOCK> constexpr size_t query_lds()
+{
+    using O = Ops<P, S>;
+    return (WLDS ? (size_t)O::W_BYTES : 0) +
+           (S::SL ? (size_t)kLevelBytes : (size_t)(BLOCK / 64) * 64 * O::ROW_DW * 4);
+}
+constexpr size_t kLdsPerCu = 160 * 1024;
+
 template <int P, class S, bool WLDS, int TB, int BLOCK>
 static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
 {
-    using O = Ops<P, S>;
     constexpr int kWavesPerBlock = BLOCK / 64;
     auto kern = k_query<P, S, WLDS, TB, false, BLOCK>;
-    const size_t lds = (WLDS ? O::W_BYTES : 0) +
-                       (S::SL ? (size_t)kLevelBytes : (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4);
+    constexpr size_t lds = query_lds<P, S, WLDS, BLOCK>();
+    static_assert(lds <= kLdsPerCu, "workgroup LDS");
     static int max_blocks = -1;  // resident workgroups per CU for this instantiation
     static int n_cu = 0;
     if (max_blocks < 0) {
@@ -156,8 +172,13 @@ static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
 template <int P, class S, bool WLDS, int TB>
 static hipError_t query_b(QueryArgs &a, const LaunchTune &tu, hipStream_t st)
 {
-    if (tu.block == 256) return query_t<P, S, WLDS, TB, 256>(a, tu.blocks_per_cu, st);
-    return query_t<P, S, WLDS, TB, 512>(a, tu.blocks_per_cu, st);
+    // shapes whose 512-thread workgroup would not fit in LDS run 256 threads
+    if constexpr (query_lds<P, S, WLDS, 512>() > kLdsPerCu) {
+        return query_t<P, S, WLDS, TB, 256>(a, tu.blocks_per_cu, st);
+    } else {
+        if (tu.block == 256) return query_t<P, S, WLDS, TB, 256>(a, tu.blocks_per_cu, st);
+        return query_t<P, S, WLDS, TB, 512>(a, tu.blocks_per_cu, st);
+    }
 }
 
 LaunchTune default_tune(int kind, niv_precision prec)
@@ -182,8 +203,20 @@ hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const 
         if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeRoom, true, 4>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeRoom, true, 4>(a, tu, st);
         return query_b<NIV_BF16, ShapeRoom, true, 4>(a, tu, st);
+    case kPE16:
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapePE<16>, true, 4>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapePE<16>, true, 4>(a, tu, st);
+        return query_b<NIV_BF16, ShapePE<16>, true, 4>(a, tu, st);
+    case kPE32:
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapePE<32>, true, 4>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapePE<32>, true, 4>(a, tu, st);
+        return query_b<NIV_BF16, ShapePE<32>, true, 4>(a, tu, st);
+    case kPE64:
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapePE<64>, true, 4>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapePE<64>, true, 4>(a, tu, st);
+        return query_b<NIV_BF16, ShapePE<64>, true, 4>(a, tu, st);
     default:  // lane-sliced encoding: the LDS holds the whole weight block
-        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6D, true, 2>(a, tu, st);
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6DFor<NIV_FP32>, false, 2>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeWide6D, true, 2>(a, tu, st);
         return query_b<NIV_BF16, ShapeWide6D, true, 2>(a, tu, st);
     }

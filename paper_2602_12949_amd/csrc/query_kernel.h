@@ -38,6 +38,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
     using O = Ops<P, S>;
     static_assert(!TRAIN || (TB == 4 && P != NIV_BF16), "training: four tiles, FP32 or FP16");
     static_assert(!S::SL || WLDS, "lane slices read the level table from LDS");
+    static_assert(!TRAIN || S::DIN == S::DIN_IN, "training: kernel columns are the parameter columns");
     // training saves: per 64-sample chunk, X_0 (DIN rows) then X_1..X_H (W rows), each [row][64]
     constexpr int64_t CHUNK_BYTES = (int64_t)(S::DIN + S::H * S::W) * 64 * O::ES;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                                 val += (v & 1) ? l.y : l.x;
                             }
                         }
-                        f_inputs[qt * S::DIN + slice_col(v, g)] = val;
+                        f_inputs[qt * S::DIN_IN + slice_col(v, g)] = val;
                     }
                 }
             }
@@ -314,16 +315,56 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     else row[l] = Prec<P>::pack(f.x, f.y);
                 }
             }
+            if constexpr (S::PB > 0) {
+                // positional code of the grid-free models (Sec. 4.1): u on the
+                // unit cube in FP64, split into two floats, then sin and cos
+                // of 2^k pi u with an exact argument reduction (16-bit
+                // operands: bands between evaluated ones by angle doubling)
+                float pe[S::PEW];
+                double ud[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ud[c] = __builtin_fma(p[c], a.pe_k[c], a.pe_o[c]);
+                    const float uh = (float)ud[c];
+                    const float ul = (float)(ud[c] - (double)uh);
+                    float sv[S::PB], cv[S::PB];
+                    pos_code_axis<S::PB, P != NIV_FP32>(uh, ul, sv, cv);
+#pragma unroll
+                    for (int b = 0; b < S::PB; ++b) {
+                        pe[6 * b + c] = sv[b];
+                        pe[6 * b + 3 + c] = cv[b];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pe[6 * S::PB + c] = (float)ud[c];
+                pe[6 * S::PB + 3] = 0.0f;
+                if constexpr (P == NIV_FP32) {
+#pragma unroll
+                    for (int k = 0; k < S::PEW; ++k) row[2 * S::L + k] = f2u(pe[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < S::PEW / 2; ++k) {
+                        if constexpr (O::NS == 2)
+                            Prec<P>::split(pe[2 * k], pe[2 * k + 1], row[S::L + k], row[O::PART_DW + S::L + k]);
+                        else
+                            row[S::L + k] = Prec<P>::pack(pe[2 * k], pe[2 * k + 1]);
+                    }
+                }
+            }
             const float rn = __builtin_amdgcn_rsqf(n2);
             float sh[16];
             sh16(nx * rn, ny * rn, nz * rn, sh);
-            constexpr int base = (P == NIV_FP32) ? 2 * S::L : S::L;
+            constexpr int base = (P == NIV_FP32) ? 2 * S::L + S::PEW : S::L + S::PEW / 2;
+            // zero columns that pad the input to a multiple of 16
+            constexpr int used = 2 * S::L + S::PEW + 16 + 16 * S::NEX;
             if constexpr (P == NIV_FP32) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) row[base + k] = f2u(sh[k]);
 #pragma unroll
                 for (int k = 0; k < 16 * S::NEX; ++k)
                     row[base + 16 + k] = f2u(gam[k]);
+#pragma unroll
+                for (int k = used; k < S::DIN; ++k) row[k] = 0u;
             } else {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
@@ -340,6 +381,10 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     else
                         row[base + 8 + k] = Prec<P>::pack(gam[2 * k], gam[2 * k + 1]);
                 }
+#pragma unroll
+                for (int k = used / 2; k < S::DIN / 2; ++k)
+#pragma unroll
+                    for (int sp = 0; sp < O::NS; ++sp) row[sp * O::PART_DW + k] = 0u;
             }
         } else {
             // no bias anywhere: an all-zero input gives E = 0
@@ -347,10 +392,12 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             for (int k = 0; k < O::NS * O::PART_DW; ++k) row[k] = 0u;
         }
         if (f_inputs && live) {
-            float *dst = f_inputs + q * S::DIN;
+            // in the order of the parameters of W_0
+            float *dst = f_inputs + q * S::DIN_IN;
             if constexpr (P == NIV_FP32) {
 #pragma unroll
-                for (int k = 0; k < S::DIN; ++k) dst[k] = u2f(row[k]);
+                for (int k = 0; k < S::DIN; ++k)
+                    if (S::in_col(k) >= 0) dst[S::in_col(k)] = u2f(row[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < S::DIN / 2; ++k) {
@@ -360,8 +407,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                         v.x += w.x;
                         v.y += w.y;
                     }
-                    dst[2 * k] = v.x;
-                    dst[2 * k + 1] = v.y;
+                    if (S::in_col(2 * k) >= 0) dst[S::in_col(2 * k)] = v.x;
+                    if (S::in_col(2 * k + 1) >= 0) dst[S::in_col(2 * k + 1)] = v.y;
                 }
             }
         }
@@ -532,7 +579,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                             for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                             for (int c = 0; c < O::HOPS; ++c) {
-                                float av = reinterpret_cast<const float *>(lw + (ob * O::HOPS + c) * O::OPB)[lane];
+                                float av = reinterpret_cast<const float *>(lw + ob * O::HROW + c * O::OPB)[lane];
 #pragma unroll
                                 for (int t = 0; t < TB; ++t) acc[t][ob] = Prec<P>::mma1(av, bh[t][c], acc[t][ob]);
                             }
@@ -576,11 +623,12 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                         for (int d = 0; d < S::W / 32; ++d)
                             a.mask_save[((chunk * S::H + (layer - 1)) * (S::W / 32) + d) * 64 + lane] = mk[d];
                     }
+                    // a block row of operands: HF full-depth, then HH half-depth
                     if (last) {
 #pragma unroll
-                        for (int t = 0; t < TB; ++t)
+                        for (int t = 0; t < TB; ++t) {
 #pragma unroll
-                            for (int kb = 0; kb < O::HOPS; ++kb) {
+                            for (int kb = 0; kb < O::HF; ++kb) {
                                 u4 av = reinterpret_cast<const u4 *>(lw + kb * O::OPB)[lane];
 #pragma unroll
                                 for (int sp = 0; sp < O::NS; ++sp) {
@@ -589,6 +637,15 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                                     acc_o[t0 + t] = Prec<P>::mma(av, bv, acc_o[t0 + t]);
                                 }
                             }
+                            if constexpr (O::HH) {
+                                u2 av = reinterpret_cast<const u2 *>(lw + O::HF * O::OPB)[lane];
+#pragma unroll
+                                for (int sp = 0; sp < O::NS; ++sp) {
+                                    u2 bv = {bh[sp][t][4 * O::HF], bh[sp][t][4 * O::HF + 1]};
+                                    acc_o[t0 + t] = Prec<P>::mma_half(av, bv, acc_o[t0 + t]);
+                                }
+                            }
+                        }
                     } else {
 #pragma unroll
                         for (int ob = 0; ob < S::NOB; ++ob) {
@@ -597,8 +654,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
 #pragma unroll
                             for (int t = 0; t < TB; ++t) acc[t][ob] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                            for (int kb = 0; kb < O::HOPS; ++kb) {
-                                u4 av = reinterpret_cast<const u4 *>(lw + (ob * O::HOPS + kb) * O::OPB)[lane];
+                            for (int kb = 0; kb < O::HF; ++kb) {
+                                u4 av = reinterpret_cast<const u4 *>(lw + ob * O::HROW + kb * O::OPB)[lane];
 #pragma unroll
                                 for (int sp = 0; sp < O::NS; ++sp)
 #pragma unroll
@@ -606,6 +663,16 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                                     u4 bv = {bh[sp][t][4 * kb], bh[sp][t][4 * kb + 1], bh[sp][t][4 * kb + 2],
                                              bh[sp][t][4 * kb + 3]};
                                     acc[t][ob] = Prec<P>::mma(av, bv, acc[t][ob]);
+                                }
+                            }
+                            if constexpr (O::HH) {
+                                u2 av = reinterpret_cast<const u2 *>(lw + ob * O::HROW + O::HF * O::OPB)[lane];
+#pragma unroll
+                                for (int sp = 0; sp < O::NS; ++sp)
+#pragma unroll
+                                for (int t = 0; t < TB; ++t) {
+                                    u2 bv = {bh[sp][t][4 * O::HF], bh[sp][t][4 * O::HF + 1]};
+                                    acc[t][ob] = Prec<P>::mma_half(av, bv, acc[t][ob]);
                                 }
                             }
                         }

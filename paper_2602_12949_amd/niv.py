@@ -30,7 +30,8 @@ class Config(C.Structure):
                 ("base_res", C.c_double), ("per_level_scale", C.c_double),
                 ("sh_bands", C.c_int32), ("n_extra", C.c_int32), ("extra_bands", C.c_int32),
                 ("width", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32),
-                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3)]
+                ("aabb_min", C.c_double * 3), ("aabb_max", C.c_double * 3),
+                ("pos_bands", C.c_int32)]
 
 
 class Frame(C.Structure):
@@ -140,6 +141,7 @@ def make_config(d) -> Config:
     for k in ("n_levels", "log2_T", "n_features", "sh_bands", "n_extra", "extra_bands",
               "width", "n_hidden", "n_out"):
         setattr(c, k, int(d[k]))
+    c.pos_bands = int(d.get("pos_bands", 0))
     c.base_res = float(d["base_res"])
     c.per_level_scale = float(d["per_level_scale"])
     c.aabb_min = (C.c_double * 3)(*[float(x) for x in d["aabb_min"]])
@@ -293,7 +295,9 @@ class NIV:
     @property
     def input_dim(self):
         c = self.cfg
-        return c["n_levels"] * c["n_features"] + c["sh_bands"] ** 2 + c["n_extra"] * 2 * c["extra_bands"]
+        pb = c.get("pos_bands", 0)
+        return (c["n_levels"] * c["n_features"] + (3 + 6 * pb if pb > 0 else 0) + c["sh_bands"] ** 2
+                + c["n_extra"] * 2 * c["extra_bands"])
 
     def query(self, pos, nrm, model, prec="fp16", albedo=None, mask=None, extra=(),
               want_flags=True, want_inputs=False):

@@ -84,3 +84,39 @@ def test_unsupported_shape_reports_unsupported(niv):
 def test_status_strings(niv):
     for s in range(6):
         assert isinstance(niv.status_string(s), str) and niv.status_string(s)
+
+
+def test_grid_free_configs(niv):
+    """Models without grid levels (positional code of x) are accepted for the
+    widths of Table 1; other positional-code shapes are valid but not
+    covered by the kernels; a config with neither grid nor code is invalid."""
+    base = dict(get_workload("room_1080p_pe64").model_dict())
+    for width in (16, 32, 64):
+        d = dict(base, width=width)
+        m = niv.NIV(d)
+        oc = O.make_config(**d)
+        assert m.n_params == O.n_params(oc) and m.n_grid_values == 0
+        assert m.input_dim == O.input_dim(oc) == 67
+        for prec in ("fp32", "fp16", "bf16"):
+            n_p, n_g, nb = m.sizes(prec)
+            assert n_g == 0 and nb >= n_p * (4 if prec == "fp32" else 2)
+    for k, v in [("width", 48), ("pos_bands", 4), ("n_hidden", 2), ("n_extra", 1)]:
+        d = dict(base)
+        d[k] = v
+        if k == "n_extra":
+            d["extra_bands"] = 8
+        m = niv.NIV(d)
+        with pytest.raises(niv.NivError) as e:
+            m.sizes("fp16")
+        assert e.value.status == niv.NIV_ERR_UNSUPPORTED, (k, v)
+    d = dict(get_workload("room_1080p").model_dict(), pos_bands=8)  # grid and code together
+    with pytest.raises(niv.NivError) as e:
+        niv.NIV(d).sizes("fp16")
+    assert e.value.status == niv.NIV_ERR_UNSUPPORTED
+    for v in (-1, 17):
+        with pytest.raises(niv.NivError) as e:
+            niv.NIV(dict(base, pos_bands=v))
+        assert e.value.status == niv.NIV_ERR_INVALID_ARG
+    with pytest.raises(niv.NivError) as e:
+        niv.NIV(dict(base, pos_bands=0))
+    assert e.value.status == niv.NIV_ERR_INVALID_ARG
