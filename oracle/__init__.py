@@ -100,6 +100,9 @@ def lib():
         L.orc_mc_irradiance.argtypes = [C.c_void_p, C.c_int, fp, fp, C.c_void_p, C.c_int64, C.c_int,
                                         C.c_int, C.c_int, C.c_uint64, dp, dp,
                                         C.POINTER(C.c_int32), u8p]
+        L.orc_upsample.argtypes = [cp, C.c_int, C.c_int, fp, fp, u8p, fp, dp, C.c_double,
+                                   C.c_double, C.c_int, dp, dp, u8p]
+        L.orc_upsample.restype = None
         L.orc_sample_points.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_int64,
                                         C.c_int64, C.c_uint64, fp, fp]
         _lib = L
@@ -313,6 +316,38 @@ def sample_points(prims, lo, hi, count, n_surface, seed):
                             int(count), int(n_surface), int(seed), _P(x, C.c_float),
                             _P(n, C.c_float))
     return x, n
+
+
+def upsample(cfg: Config, width, height, pos, nrm, half_E, mask=None, albedo=None,
+             sigma_px=1.0, sigma_pos=0.1, normal_power=8):
+    """Half-resolution rendering (Sec. 4.4): joint bilateral upsampling of
+    the irradiance at pixels (2x, 2y) to every pixel, then Eq. 2.
+    Returns (E [H*W, 3], L [H*W, 3], flags [H*W] uint8)."""
+    n = width * height
+    pos = _f32(pos).reshape(n, 3)
+    nrm = _f32(nrm).reshape(n, 3)
+    hw, hh = (width + 1) // 2, (height + 1) // 2
+    hE = np.ascontiguousarray(half_E, dtype=np.float64).reshape(hh * hw, 3)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(n)
+    al = None if albedo is None else _f32(albedo).reshape(n, 3)
+    E = np.zeros((n, 3))
+    Lo = np.zeros((n, 3))
+    fl = np.zeros(n, np.uint8)
+    lib().orc_upsample(C.byref(cfg), int(width), int(height), _P(pos, C.c_float),
+                       _P(nrm, C.c_float), _P(mk, C.c_uint8), _P(al, C.c_float),
+                       _P(hE, C.c_double), float(sigma_px), float(sigma_pos), int(normal_power),
+                       _P(E, C.c_double), _P(Lo, C.c_double), _P(fl, C.c_uint8))
+    return E, Lo, fl
+
+
+def half_samples(width, height, *arrays):
+    """The pixels (2x, 2y) of full-resolution [H*W, ...] arrays, row-major."""
+    out = []
+    for a in arrays:
+        a = np.asarray(a)
+        b = a.reshape((height, width) + a.shape[1:])[::2, ::2]
+        out.append(np.ascontiguousarray(b.reshape((-1,) + a.shape[1:])))
+    return out
 
 
 def config_from_workload(w) -> Config:

@@ -1010,3 +1010,115 @@ void orc_sample_points(const orc_prim *prims, int n_prims, const double lo[3],
     }
     free(fp); free(ff); free(cdf);
 }
+
+/* ------------------------------------------------------------------ */
+/* Half-resolution rendering: joint bilateral upsampling                 */
+/* ------------------------------------------------------------------ */
+/* Sec. 4.4 renders the network at a quarter of the pixels and multiplies by
+ * the full-resolution albedo; it leaves the upsampler to the cited joint
+ * bilateral method.  Readings: the half-resolution samples are the
+ * G-buffer pixels (2x, 2y), x < ceil(W/2), y < ceil(H/2), whose irradiance
+ * half_E [ceil(H/2)][ceil(W/2)][3] is given.  A sample is usable iff its
+ * pixel is covered (mask) and its position and normal are finite with a
+ * non-zero normal.  Full-resolution pixel (X, Y) averages the usable
+ * samples with |2x - X| <= 2 and |2y - Y| <= 2 that face its way
+ * (n . n_s > 0, unit normals), with weights
+ *   exp(-(dx^2 + dy^2) / (2 sigma_px^2))      spatial, dx = 2x - X (pixels)
+ *   (n . n_s)^normal_power                     normal guide
+ *   exp(-|p - p_s|^2 / (2 sigma_pos^2))        position guide (world units)
+ * (the G-buffer guides take the place of the guide image of the cited
+ * method).  The weights are formed as exp(l - l_max) from their logarithms
+ * l, which leaves the average unchanged and keeps it finite however small
+ * the weights.  With no usable sample facing its way the pixel takes the
+ * usable sample nearest in pixels (first in row-major order among equals)
+ * and flag 32; with no usable sample in the window E = 0 and flag 64.  A
+ * covered pixel with a non-finite or zero-normal input gets E = 0 and flag
+ * 2; a position outside the box sets flag 1.  L = albedo * E / pi (Eq. 2)
+ * at full resolution. */
+static int orc_px_usable(const float *pos, const float *nrm, const uint8_t *mask, int64_t i)
+{
+    if (mask && !mask[i]) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(pos[3 * i + a]) || !isfinite(nrm[3 * i + a])) return 0;
+    return !(nrm[3 * i] == 0.0f && nrm[3 * i + 1] == 0.0f && nrm[3 * i + 2] == 0.0f);
+}
+
+static void orc_unit(const float *v, double *u)
+{
+    double n = sqrt((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
+    for (int a = 0; a < 3; ++a) u[a] = v[a] / n;
+}
+
+void orc_upsample(const orc_config *c, int width, int height, const float *pos,
+                  const float *nrm, const uint8_t *mask, const float *albedo,
+                  const double *half_E, double sigma_px, double sigma_pos, int normal_power,
+                  double *out_E, double *out_L, uint8_t *out_flags)
+{
+    const int hw = (width + 1) / 2, hh = (height + 1) / 2;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int Y = 0; Y < height; ++Y)
+        for (int X = 0; X < width; ++X) {
+            const int64_t i = (int64_t)Y * width + X;
+            double E[3] = {0.0, 0.0, 0.0};
+            int flags = 0;
+            int on = mask ? mask[i] != 0 : 1;
+            if (on && !orc_px_usable(pos, nrm, mask, i)) {
+                flags |= ORC_FLAG_BAD_INPUT;
+            } else if (on) {
+                for (int a = 0; a < 3; ++a)
+                    if (pos[3 * i + a] < c->aabb_min[a] || pos[3 * i + a] > c->aabb_max[a])
+                        flags |= ORC_FLAG_OUTSIDE;
+                double n[3];
+                orc_unit(nrm + 3 * i, n);
+                double lw[9], ev[9][3];
+                int ns_ = 0;
+                int64_t nearest = -1;
+                int best_d2 = 1 << 30, any_sample = 0;
+                for (int y = (Y - 1) / 2; y <= (Y + 2) / 2; ++y) {
+                    if (y < 0 || y >= hh || 2 * y - Y < -2 || 2 * y - Y > 2) continue;
+                    for (int x = (X - 1) / 2; x <= (X + 2) / 2; ++x) {
+                        if (x < 0 || x >= hw || 2 * x - X < -2 || 2 * x - X > 2) continue;
+                        const int64_t s = (int64_t)(2 * y) * width + 2 * x;
+                        if (!orc_px_usable(pos, nrm, mask, s)) continue;
+                        any_sample = 1;
+                        const int dx = 2 * x - X, dy = 2 * y - Y, d2 = dx * dx + dy * dy;
+                        if (d2 < best_d2) { best_d2 = d2; nearest = (int64_t)y * hw + x; }
+                        double nsu[3];
+                        orc_unit(nrm + 3 * s, nsu);
+                        double cs = n[0] * nsu[0] + n[1] * nsu[1] + n[2] * nsu[2];
+                        if (!(cs > 0.0)) continue;
+                        double dp2 = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            double d = (double)pos[3 * i + a] - (double)pos[3 * s + a];
+                            dp2 += d * d;
+                        }
+                        lw[ns_] = -(double)d2 / (2.0 * sigma_px * sigma_px) + normal_power * log(cs)
+                                  - dp2 / (2.0 * sigma_pos * sigma_pos);
+                        const double *e = half_E + 3 * ((int64_t)y * hw + x);
+                        for (int a = 0; a < 3; ++a) ev[ns_][a] = e[a];
+                        ++ns_;
+                    }
+                }
+                if (ns_ > 0) {
+                    double lmax = lw[0], wsum = 0.0, acc[3] = {0.0, 0.0, 0.0};
+                    for (int k = 1; k < ns_; ++k) lmax = lw[k] > lmax ? lw[k] : lmax;
+                    for (int k = 0; k < ns_; ++k) {
+                        double w = exp(lw[k] - lmax);
+                        wsum += w;
+                        for (int a = 0; a < 3; ++a) acc[a] += w * ev[k][a];
+                    }
+                    for (int a = 0; a < 3; ++a) E[a] = acc[a] / wsum;
+                } else if (any_sample) {
+                    for (int a = 0; a < 3; ++a) E[a] = half_E[3 * nearest + a];
+                    flags |= 32;
+                } else {
+                    flags |= 64;
+                }
+            }
+            for (int a = 0; a < 3; ++a) {
+                out_E[3 * i + a] = E[a];
+                if (out_L) out_L[3 * i + a] = (albedo ? albedo[3 * i + a] : 1.0) * E[a] / ORC_PI;
+            }
+            if (out_flags) out_flags[i] = (uint8_t)flags;
+        }
+}
