@@ -19,7 +19,11 @@ Also measured, as extra fields of the same JSON line:
               scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16;
   table1      room_1080p_pe16/32/64: the same 1080p G-buffer under the
               grid-free models of Table 1 (eight-band positional code of x,
-              three hidden layers of width 16, 32 or 64), FP16.
+              three hidden layers of width 16, 32 or 64), FP16;
+  half        half-resolution rendering of the 1080p G-buffer (Table 1's
+              "half" column): the query at a quarter of the pixels, joint
+              bilateral upsampling with the G-buffer as guide, full-resolution
+              albedo; for the grid model and the three grid-free models, FP16.
 
 Kernel times come from HIP events recorded on the stream the kernels are
 launched on (torch's current stream).  Prints one JSON line on stdout;
@@ -27,7 +31,7 @@ progress goes to stderr.
 
 `--profile CASE` runs only that case's kernel a few times (for rocprofv3
 counter and trace runs): query_fp16, query_fp32, query_bf16, field_4k,
-train_step, mc, pe16, pe32, pe64, copy (a 1 GiB device copy that calibrates
+train_step, mc, pe16, pe32, pe64, half, copy (a 1 GiB device copy that calibrates
 the HBM byte counters).
 """
 import argparse
@@ -479,6 +483,42 @@ def bench_table1(args, dev):
             "valid_pixels": n_valid, "rows": rows}
 
 
+# Compulsory HBM bytes per pixel of the upsampler: pos, nrm, albedo (3 x 12),
+# mask 1, a quarter of the half-resolution E (12 / 4), E and L out (2 x 12),
+# flags 1.
+UPSAMPLE_BYTES_PER_PX = 12 * 3 + 1 + 3 + 12 * 2 + 1
+
+
+def bench_half(args, dev):
+    """Half-resolution rendering of the room_1080p G-buffer, FP16."""
+    import torch
+    from niv_synth import get_workload, make_params, make_room_gbuffer
+    from paper_2602_12949_amd import NIV
+    w0 = get_workload("room_1080p")
+    Wd, Ht = w0.frames[0]
+    _, g = make_room_gbuffer(w0.scene_seeds[0], Wd, Ht)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = dict(pos=t(g["pos"]), nrm=t(g["nrm"]), alb=t(g["albedo"]), mask=t(g["mask"]))
+    rows = {}
+    for name in ("room_1080p", "room_1080p_pe16", "room_1080p_pe32", "room_1080p_pe64"):
+        w = get_workload(name)
+        m = NIV(w.model_dict())
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+        pm = m.prepare(t(params), "fp16")
+        f, outs = m.half_frame(Wd, Ht, d["pos"], d["nrm"], model=pm, albedo=d["alb"], mask=d["mask"])
+        up = m.upsample_params()
+        tt, tp = time_steps(lambda: m.query_half(f, "fp16", up), args.steps, args.warmup)
+        ut, upr = time_steps(lambda: m.upsample(f, up), args.steps, args.warmup)
+        rows[name] = {**stats(tt, tp), "ms_per_frame": tt, "upsample_ms": ut,
+                      "query_ms": tt - ut, "half_pixels": ((Wd + 1) // 2) * ((Ht + 1) // 2),
+                      "upsample_hbm_GBs": UPSAMPLE_BYTES_PER_PX * Wd * Ht / (ut * 1e-3) / 1e9}
+        log(f"[bench] half {name} fp16: {tt:.4f} ms/frame (upsampling {ut:.4f} ms, "
+            f"{rows[name]['upsample_hbm_GBs']:.0f} GB/s compulsory)")
+    return {"workload": "room_1080p G-buffer rendered at 960x540 samples + joint bilateral "
+                        "upsampling (sigma 1 px, 0.1 m, normal power 8), full-resolution albedo, FP16",
+            "rows": rows}
+
+
 # ---------------------------------------------------------------- profiling cases
 def profile_case(case, steps, tune=None):
     import torch
@@ -548,6 +588,23 @@ def profile_case(case, steps, tune=None):
         torch.cuda.synchronize()
         log(f"[profile] {case}: done")
         return
+    if case == "half":
+        from niv_synth import get_workload, make_params, make_room_gbuffer
+        from paper_2602_12949_amd import NIV
+        w = get_workload("room_1080p")
+        Wd, Ht = w.frames[0]
+        _, g = make_room_gbuffer(w.scene_seeds[0], Wd, Ht)
+        m = NIV(w.model_dict())
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        pm = m.prepare(t(params), "fp16")
+        f, _ = m.half_frame(Wd, Ht, t(g["pos"]), t(g["nrm"]), model=pm, albedo=t(g["albedo"]),
+                            mask=t(g["mask"]))
+        for _ in range(2 * steps):
+            m.query_half(f, "fp16")
+        torch.cuda.synchronize()
+        log(f"[profile] {case}: done")
+        return
     if case == "field_4k":
         from niv_synth import get_workload, make_params, make_workload_gbuffer
         from paper_2602_12949_amd import NIV
@@ -576,7 +633,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precisions", default="fp16,fp32,bf16")
-    ap.add_argument("--only", default="query,train,batched,field_4k,table1",
+    ap.add_argument("--only", default="query,train,batched,field_4k,table1,half",
                     help="comma list of parts to run")
     ap.add_argument("--profile", default=None, help="run one kernel case for rocprofv3")
     ap.add_argument("--tune", default=None,
@@ -634,6 +691,8 @@ def main():
         extra["field_4k"] = bench_field_4k(args, dev)
     if "table1" in parts:
         extra["table1"] = bench_table1(args, dev)
+    if "half" in parts:
+        extra["half"] = bench_half(args, dev)
 
     line = {
         "metric": "1080p NIV query ms/frame, FP16-MFMA vs FP32 at stated err; train samples/s",

@@ -160,6 +160,57 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
                               niv_precision prec, const niv_fallback *fb, void *workspace,
                               int64_t workspace_bytes, hipStream_t stream);
 
+/* Half-resolution rendering (Sec. 4.4): the network runs at a quarter of
+ * the pixels and the full-resolution albedo shades the result.  The
+ * half-resolution samples are the G-buffer pixels (2x, 2y), x < ceil(W/2),
+ * y < ceil(H/2).  Upsampling is joint bilateral (the cited method) with the
+ * G-buffer as guide: pixel (X, Y) averages the usable samples (covered,
+ * finite, non-zero normal) with |2x - X| <= 2 and |2y - Y| <= 2 that face
+ * its way (n . n_s > 0), weighted by exp(-(dx^2 + dy^2) / (2 sigma_px^2))
+ * (n . n_s)^normal_power exp(-|p - p_s|^2 / (2 sigma_pos^2)).  With no
+ * sample facing its way it takes the nearest usable sample (flag bit 5); with
+ * no usable sample in the window E = 0 (flag bit 6).  Full-resolution flags
+ * also carry bit 0 (outside the box) and bit 1 (non-finite input or zero
+ * normal, E = 0); masked-off pixels get E = L = 0, flags 0. */
+typedef struct {
+    float sigma_px;        /* spatial Gaussian in full-resolution pixels, > 0 */
+    float sigma_pos;       /* position guide in world units, > 0 */
+    int32_t normal_power;  /* exponent of the normal guide, 0..64 */
+} niv_upsample_params;
+
+/* One full-resolution G-buffer (device arrays, row-major, 4-byte aligned):
+ *   pos, nrm     [height][width][3] float; albedo the same or NULL
+ *   mask         [height][width] uint8 or NULL
+ *   half_E       [ceil(height/2)][ceil(width/2)][3] float: written by
+ *                niv_query_half, read by niv_upsample
+ *   half_flags   [ceil(height/2)][ceil(width/2)] uint8 or NULL: query flags
+ *                of the samples (niv_query_half)
+ *   out_E, out_L [height][width][3] float (out_L NULL or albedo given)
+ *   out_flags    [height][width] uint8 or NULL
+ * width, height >= 1, width * height < 2^28. */
+typedef struct {
+    int32_t width, height;
+    const float *pos, *nrm, *albedo;
+    const uint8_t *mask;
+    float extra_values[4];
+    const void *model;
+    float *half_E;
+    uint8_t *half_flags;
+    float *out_E, *out_L;
+    uint8_t *out_flags;
+} niv_half_frame;
+
+/* Joint bilateral upsampling of f->half_E to every pixel, then L = albedo E
+ * / pi (Eq. 2).  Uses the handle's box for bit 0; model and extra values
+ * are not read. */
+niv_status niv_upsample(niv_handle *h, const niv_half_frame *f, const niv_upsample_params *p,
+                        hipStream_t stream);
+
+/* The fused query at the half-resolution samples (E into half_E, flags into
+ * half_flags), then niv_upsample; both enqueued on `stream`. */
+niv_status niv_query_half(niv_handle *h, const niv_half_frame *f, const niv_upsample_params *p,
+                          niv_precision prec, hipStream_t stream);
+
 /* Times the fused query on these frames for each candidate launch shape
  * (workgroup of 256 or 512 threads x 1, 2 or all-resident workgroups per
  * CU x tile order: plain, or XCD-grouped, where each of the 8 XCDs walks a

@@ -231,6 +231,91 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, n
     return NIV_OK;
 }
 
+// ---------------------------------------------------------------- half resolution
+static niv_status check_half(const niv_handle *h, const niv_half_frame *f,
+                             const niv_upsample_params *p)
+{
+    if (!h || !f || !p) return NIV_ERR_INVALID_ARG;
+    if (f->width < 1 || f->height < 1 || (int64_t)f->width * f->height >= (int64_t(1) << 28))
+        return NIV_ERR_INVALID_ARG;
+    if (!f->pos || !f->nrm || !f->half_E || !f->out_E) return NIV_ERR_INVALID_ARG;
+    if (f->out_L && !f->albedo) return NIV_ERR_INVALID_ARG;
+    if (!aligned(f->pos, 4) || !aligned(f->nrm, 4) || !aligned(f->half_E, 4) ||
+        !aligned(f->out_E, 4) || (f->albedo && !aligned(f->albedo, 4)) ||
+        (f->out_L && !aligned(f->out_L, 4)))
+        return NIV_ERR_INVALID_ARG;
+    if (!(p->sigma_px > 0.0f) || !(p->sigma_pos > 0.0f) || !isfinite(p->sigma_px) ||
+        !isfinite(p->sigma_pos) || p->normal_power < 0 || p->normal_power > 64)
+        return NIV_ERR_INVALID_ARG;
+    return NIV_OK;
+}
+
+static hipError_t upsample_launch(const niv_handle *h, const niv_half_frame *f,
+                                  const niv_upsample_params *p, hipStream_t stream)
+{
+    UpsampleArgs u;
+    memset(&u, 0, sizeof(u));
+    u.pos = f->pos;
+    u.nrm = f->nrm;
+    u.albedo = f->albedo;
+    u.mask = f->mask;
+    u.half_E = f->half_E;
+    u.out_E = f->out_E;
+    u.out_L = f->out_L;
+    u.out_flags = f->out_flags;
+    u.width = f->width;
+    u.height = f->height;
+    u.half_w = (f->width + 1) / 2;
+    u.half_h = (f->height + 1) / 2;
+    for (int c = 0; c < 3; ++c) {
+        u.lo[c] = (float)h->m.cfg.aabb_min[c];
+        u.hi[c] = (float)h->m.cfg.aabb_max[c];
+    }
+    // log2 of the Gaussian weights: -d^2 / (2 sigma^2 ln 2)
+    const double ln2 = 0.69314718055994531;
+    u.c_px = (float)(1.0 / (2.0 * (double)p->sigma_px * p->sigma_px * ln2));
+    u.c_pos = (float)(1.0 / (2.0 * (double)p->sigma_pos * p->sigma_pos * ln2));
+    u.normal_power = (float)p->normal_power;
+    return launch_upsample(u, stream);
+}
+
+niv_status niv_upsample(niv_handle *h, const niv_half_frame *f, const niv_upsample_params *p,
+                        hipStream_t stream)
+{
+    niv_status s = check_half(h, f, p);
+    if (s != NIV_OK) return s;
+    return hip_status(upsample_launch(h, f, p, stream));
+}
+
+niv_status niv_query_half(niv_handle *h, const niv_half_frame *f, const niv_upsample_params *p,
+                          niv_precision prec, hipStream_t stream)
+{
+    niv_status s = check_half(h, f, p);
+    if (s != NIV_OK) return s;
+    // the query at the half-resolution samples, as a frame of ceil(W/2) x
+    // ceil(H/2) pixels that reads every other pixel of every other row
+    niv_frame q;
+    memset(&q, 0, sizeof(q));
+    q.count = (int64_t)((f->width + 1) / 2) * ((f->height + 1) / 2);
+    q.pos = f->pos;
+    q.nrm = f->nrm;
+    q.mask = f->mask;
+    for (int e = 0; e < 4; ++e) q.extra_values[e] = f->extra_values[e];
+    q.model = f->model;
+    q.out_E = f->half_E;
+    q.out_flags = f->half_flags;
+    s = check_frames(h, &q, 1, prec);
+    if (s != NIV_OK) return s;
+    QueryArgs a;
+    fill_args(h, &q, 1, prec, a);
+    a.f[0].sub_w = (f->width + 1) / 2;
+    a.f[0].src_w = f->width;
+    const LaunchTune tu = tune_of(h, prec);
+    a.xcd_order = tu.xcd_order;
+    if (launch_query(h->m, a, prec, tu, stream) != hipSuccess) return NIV_ERR_HIP;
+    return hip_status(upsample_launch(h, f, p, stream));
+}
+
 niv_status niv_fallback_sizes(const niv_handle *h, int64_t max_flagged, int64_t *workspace_bytes)
 {
     if (!h || !workspace_bytes || max_flagged < 0 || max_flagged > 0x7fffffff) return NIV_ERR_INVALID_ARG;

@@ -46,6 +46,10 @@ struct FrameArgs {
     int64_t count;
     int64_t tile_begin;
     float extra[4];           // scene variables of the frame
+    // half-resolution samples: pixel q of a sub_w wide grid reads its inputs
+    // at pixel (2 (q / sub_w), 2 (q % sub_w)) of a src_w wide G-buffer
+    // (sub_w = 0: pixel q reads pixel q)
+    int32_t sub_w, src_w;
 };
 
 struct QueryArgs {
@@ -113,6 +117,20 @@ LaunchTune default_tune(int kind, niv_precision prec);
 hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
                         hipStream_t stream);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t stream);
+
+// Joint bilateral upsampling (upsample.hip).
+struct UpsampleArgs {
+    const float *pos, *nrm, *albedo;
+    const uint8_t *mask;
+    const float *half_E;
+    float *out_E, *out_L;
+    uint8_t *out_flags;
+    int32_t width, height, half_w, half_h;
+    float lo[3], hi[3];        // box (flag bit 0)
+    float c_px, c_pos;         // log2 weight factors: 1 / (2 sigma^2 ln 2)
+    float normal_power;
+};
+hipError_t launch_upsample(const UpsampleArgs &a, hipStream_t stream);
 
 // Monte Carlo fallback of flagged pixels (mc.hip).
 struct FbFrame {

@@ -107,6 +107,14 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         const uint8_t *f_mask = ka->f[fi].mask;
         const int64_t q = chunk * 64 + lane;
         const bool live = q < count;
+        // G-buffer pixel of this query (half-resolution samples read every
+        // other pixel of every other row)
+        int64_t qs = q;
+        if (ka->f[fi].sub_w > 0) {
+            const uint32_t sw = (uint32_t)ka->f[fi].sub_w;
+            const uint32_t r = (uint32_t)q / sw, c = (uint32_t)q - r * sw;
+            qs = 2 * ((int64_t)r * ka->f[fi].src_w + c);
+        }
         float *f_inputs = ka->f[fi].out_inputs;
         bool on = false, work = false;
         uint32_t flags = 0u;
@@ -127,10 +135,10 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             bool o = false;
             float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             if (live) {
-                o = f_mask ? (f_mask[q] != 0) : true;
+                o = f_mask ? (f_mask[qs] != 0) : true;
                 if (o) {
-                    v[0] = f_pos[3 * q]; v[1] = f_pos[3 * q + 1]; v[2] = f_pos[3 * q + 2];
-                    v[3] = f_nrm[3 * q]; v[4] = f_nrm[3 * q + 1]; v[5] = f_nrm[3 * q + 2];
+                    v[0] = f_pos[3 * qs]; v[1] = f_pos[3 * qs + 1]; v[2] = f_pos[3 * qs + 2];
+                    v[3] = f_nrm[3 * qs]; v[4] = f_nrm[3 * qs + 1]; v[5] = f_nrm[3 * qs + 2];
                 }
             }
 #pragma unroll
@@ -253,11 +261,11 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         // ---- 1. load and encode this lane's pixel
         float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
         if (live) {
-            on = f_mask ? (f_mask[q] != 0) : true;
+            on = f_mask ? (f_mask[qs] != 0) : true;
             if constexpr (TRAIN) on = a.valid ? (a.valid[q] != 0) : true;
             if (on) {
-                px = f_pos[3 * q]; py = f_pos[3 * q + 1]; pz = f_pos[3 * q + 2];
-                nx = f_nrm[3 * q]; ny = f_nrm[3 * q + 1]; nz = f_nrm[3 * q + 2];
+                px = f_pos[3 * qs]; py = f_pos[3 * qs + 1]; pz = f_pos[3 * qs + 2];
+                nx = f_nrm[3 * qs]; ny = f_nrm[3 * qs + 1]; nz = f_nrm[3 * qs + 2];
             }
         }
         bool bad = !(__builtin_isfinite(px) && __builtin_isfinite(py) && __builtin_isfinite(pz) &&
@@ -744,7 +752,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             if (f_L) {
                 const float ip = 0.3183098861837907f;  // 1/pi
                 float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-                if (on) { r0 = f_alb[3 * q]; r1 = f_alb[3 * q + 1]; r2 = f_alb[3 * q + 2]; }
+                if (on) { r0 = f_alb[3 * qs]; r1 = f_alb[3 * qs + 1]; r2 = f_alb[3 * qs + 2]; }
                 f_L[3 * q] = r0 * E0 * ip;
                 f_L[3 * q + 1] = r1 * E1 * ip;
                 f_L[3 * q + 2] = r2 * E2 * ip;

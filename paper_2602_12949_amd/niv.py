@@ -42,6 +42,18 @@ class Frame(C.Structure):
                 ("out_inputs", C.c_void_p), ("in_flags", C.c_void_p), ("scene", C.c_void_p)]
 
 
+class HalfFrame(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("pos", C.c_void_p),
+                ("nrm", C.c_void_p), ("albedo", C.c_void_p), ("mask", C.c_void_p),
+                ("extra_values", C.c_float * 4), ("model", C.c_void_p), ("half_E", C.c_void_p),
+                ("half_flags", C.c_void_p), ("out_E", C.c_void_p), ("out_L", C.c_void_p),
+                ("out_flags", C.c_void_p)]
+
+
+class UpsampleParams(C.Structure):
+    _fields_ = [("sigma_px", C.c_float), ("sigma_pos", C.c_float), ("normal_power", C.c_int32)]
+
+
 class Fallback(C.Structure):
     _fields_ = [("flag_mask", C.c_uint32), ("spp", C.c_int32), ("bounces", C.c_int32),
                 ("mc_flags", C.c_int32), ("seed", C.c_uint64)]
@@ -93,6 +105,8 @@ def lib():
         L.niv_query.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp]
         L.niv_status_string.argtypes = [C.c_int]
         L.niv_status_string.restype = C.c_char_p
+        L.niv_upsample.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), vp]
+        L.niv_query_half.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), C.c_int, vp]
         L.niv_fallback_sizes.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
         L.niv_query_fallback.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
                                          C.POINTER(Fallback), vp, C.c_int64, vp]
@@ -254,6 +268,48 @@ class NIV:
     def query_frames(self, frames, prec="fp16"):
         arr = (Frame * len(frames))(*frames)
         _check(lib().niv_query(self._h, arr, len(frames), _prec(prec), _stream()), "niv_query")
+
+    # ---------------------------------------------------------- half resolution
+    def half_frame(self, width, height, pos, nrm, model=None, albedo=None, mask=None, extra=(),
+                   half_E=None, want_L=True, want_flags=True):
+        """A niv_half_frame (and its tensors) for one full-resolution G-buffer
+        of height x width pixels: half_E / half_flags at the samples (2x, 2y),
+        out_E / out_L / out_flags at every pixel."""
+        dev = pos.device
+        hw, hh = (width + 1) // 2, (height + 1) // 2
+        assert pos.numel() == nrm.numel() == 3 * width * height
+        if half_E is None:
+            half_E = torch.empty((hh * hw, 3), dtype=torch.float32, device=dev)
+        half_flags = torch.empty(hh * hw, dtype=torch.uint8, device=dev) if want_flags else None
+        out_E = torch.empty((width * height, 3), dtype=torch.float32, device=dev)
+        out_L = (torch.empty((width * height, 3), dtype=torch.float32, device=dev)
+                 if (want_L and albedo is not None) else None)
+        out_flags = torch.empty(width * height, dtype=torch.uint8, device=dev) if want_flags else None
+        f = HalfFrame()
+        f.width, f.height = int(width), int(height)
+        f.pos, f.nrm, f.albedo, f.mask = (_ptr(pos).value, _ptr(nrm).value, _ptr(albedo).value,
+                                          _ptr(mask).value)
+        ev = list(extra) + [0.0] * (4 - len(extra))
+        f.extra_values = (C.c_float * 4)(*[float(x) for x in ev])
+        f.model = _ptr(model).value
+        f.half_E, f.half_flags = _ptr(half_E).value, _ptr(half_flags).value
+        f.out_E, f.out_L, f.out_flags = _ptr(out_E).value, _ptr(out_L).value, _ptr(out_flags).value
+        return f, dict(half_E=half_E, half_flags=half_flags, E=out_E, L=out_L, flags=out_flags)
+
+    @staticmethod
+    def upsample_params(sigma_px=1.0, sigma_pos=0.1, normal_power=8):
+        return UpsampleParams(float(sigma_px), float(sigma_pos), int(normal_power))
+
+    def upsample(self, f, params=None):
+        """niv_upsample: joint bilateral upsampling of f.half_E (Sec. 4.4)."""
+        p = params or self.upsample_params()
+        _check(lib().niv_upsample(self._h, C.byref(f), C.byref(p), _stream()), "niv_upsample")
+
+    def query_half(self, f, prec="fp16", params=None):
+        """niv_query_half: the query at a quarter of the pixels, then upsampling."""
+        p = params or self.upsample_params()
+        _check(lib().niv_query_half(self._h, C.byref(f), C.byref(p), _prec(prec), _stream()),
+               "niv_query_half")
 
     def fallback_workspace(self, max_flagged, device="cuda"):
         nb = C.c_int64()
