@@ -99,7 +99,7 @@ def lib():
         L.orc_uniform.restype = C.c_double
         L.orc_mc_irradiance.argtypes = [C.c_void_p, C.c_int, fp, fp, C.c_void_p, C.c_int64, C.c_int,
                                         C.c_int, C.c_int, C.c_uint64, dp, dp,
-                                        C.POINTER(C.c_int32), u8p]
+                                        C.POINTER(C.c_int32), u8p, fp, fp]
         L.orc_upsample.argtypes = [cp, C.c_int, C.c_int, fp, fp, u8p, fp, dp, C.c_double,
                                    C.c_double, C.c_int, dp, dp, u8p]
         L.orc_upsample.restype = None
@@ -282,9 +282,11 @@ def uniform(seed, a, b, stream, dim):
 
 
 # ---------------------------------------------------------------- Monte Carlo
-def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None):
+def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None, motion=None, t=None):
     """Eq. 1 indirect irradiance by Monte Carlo (Sec. 4.5 targets).  The
-    random stream of point i is keyed by point_id[i] (default i).
+    random stream of point i is keyed by point_id[i] (default i).  A scene
+    that changes with a scene variable (Sec. 6): primitive k translated by
+    t[i] * motion[k] at point i.
     Returns (E [n,3], var [n,3], backfaces [n], valid [n])."""
     pr = np.ascontiguousarray(prims)
     x = _f32(x).reshape(-1, 3)
@@ -298,10 +300,13 @@ def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None):
     if point_id is not None:
         ids = np.ascontiguousarray(point_id, dtype=np.uint64).reshape(-1)
         assert ids.size == n
+    mo = None if motion is None else _f32(motion).reshape(len(pr), 3)
+    tv = None if t is None else _f32(t).reshape(n)
     lib().orc_mc_irradiance(pr.ctypes.data, len(pr), _P(x, C.c_float), _P(nrm, C.c_float),
                             None if ids is None else ids.ctypes.data, n, int(spp), int(bounces), int(flags), int(seed),
                             _P(E, C.c_double), _P(var, C.c_double),
-                            _P(bf, C.c_int32), _P(vd, C.c_uint8))
+                            _P(bf, C.c_int32), _P(vd, C.c_uint8), _P(mo, C.c_float),
+                            _P(tv, C.c_float))
     return E, var, bf, vd
 
 

@@ -672,14 +672,20 @@ static int orc_is_light(const orc_prim *pr)
     return pr->emission[0] > 0.f || pr->emission[1] > 0.f || pr->emission[2] > 0.f;
 }
 
-/* Closest hit with t > tmin; ties go to the lowest primitive index. */
-static int orc_trace(const orc_prim *prims, int n, const double o[3],
-                     const double d[3], double tmin, orc_hit *h)
+/* Closest hit with t > tmin; ties go to the lowest primitive index.
+ * shift (or NULL): primitive k is translated by shift[3k..3k+2]; it is
+ * tested with the ray origin moved by the opposite amount, which gives the
+ * same distance, side and normal. */
+static int orc_trace_at(const orc_prim *prims, int n, const double o_in[3],
+                        const double d[3], double tmin, orc_hit *h, const double *shift)
 {
     h->t = INFINITY;
     h->prim = -1;
     for (int k = 0; k < n; ++k) {
         const orc_prim *pr = &prims[k];
+        double o[3] = {o_in[0], o_in[1], o_in[2]};
+        if (shift)
+            for (int a = 0; a < 3; ++a) o[a] -= shift[3 * k + a];
         if (pr->kind == 0) {
             double tn = -INFINITY, tf = INFINITY;
             int an = -1, af = -1, miss = 0;
@@ -738,6 +744,12 @@ static int orc_trace(const orc_prim *prims, int n, const double o[3],
         }
     }
     return h->prim >= 0;
+}
+
+static int orc_trace(const orc_prim *prims, int n, const double o[3],
+                     const double d[3], double tmin, orc_hit *h)
+{
+    return orc_trace_at(prims, n, o, d, tmin, h, 0);
 }
 
 /* Orthonormal basis around a unit vector (Duff et al., "Building an
@@ -808,11 +820,16 @@ static double orc_light_point(const orc_prim *pr, double u1, double u2, double q
  * (1-based) uses 2 + (k-1)(2J+2) + 2j for light j and 2 + (k-1)(2J+2) + 2J
  * for the continuation, J = number of lights.  DIRECT_AT_ORIGIN uses 2j.
  * Outputs per point: mean E (3), variance of the mean (3), back-face count,
- * valid = (back-face count <= S/2) and some channel of E > 0. */
+ * valid = (back-face count <= S/2) and some channel of E > 0.
+ * A scene that changes with a scene variable (Sec. 6: moving emitters or
+ * occluders): motion [n_prims][3] (or NULL) and tvar [count] (or NULL, t =
+ * 0); at point i primitive k occupies its place translated by
+ * tvar[i] * motion[k].  The ray offset eps uses the scene's extent at t = 0. */
 void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                        const float *nrm, const uint64_t *point_id, int64_t count, int spp,
                        int bounces, int flags, uint64_t seed, double *out_E, double *out_var,
-                       int32_t *out_backfaces, uint8_t *out_valid)
+                       int32_t *out_backfaces, uint8_t *out_valid, const float *motion,
+                       const float *tvar)
 {
     int lights[64], J = 0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -841,6 +858,12 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < count; ++i) {
         const uint64_t pid = point_id ? point_id[i] : (uint64_t)i;
+        double *shift = 0;
+        if (motion) {
+            const double tv = tvar ? (double)tvar[i] : 0.0;
+            shift = (double *)malloc(sizeof(double) * 3 * (size_t)n_prims);
+            for (int k = 0; k < 3 * n_prims; ++k) shift[k] = tv * (double)motion[k];
+        }
         double sum[3] = {0, 0, 0}, sum2[3] = {0, 0, 0};
         int backs = 0;
         double px[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
@@ -857,6 +880,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                     double q[3], nq[3];
                     double A = orc_light_point(L, orc_uniform(seed, pid, s, 0, 2 * j),
                                                orc_uniform(seed, pid, s, 0, 2 * j + 1), q, nq);
+                    if (shift) for (int a = 0; a < 3; ++a) q[a] += shift[3 * lights[j] + a];
                     double w[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
                     double d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], dl = sqrt(d2);
                     for (int a = 0; a < 3; ++a) w[a] /= dl;
@@ -864,7 +888,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                     double cq = -(nq[0] * w[0] + nq[1] * w[1] + nq[2] * w[2]);
                     if (cy <= 0.0 || cq <= 0.0) continue;
                     orc_hit hh;
-                    if (!orc_trace(prims, n_prims, o, w, 0.0, &hh) || hh.prim != lights[j]) continue;
+                    if (!orc_trace_at(prims, n_prims, o, w, 0.0, &hh, shift) || hh.prim != lights[j]) continue;
                     for (int c = 0; c < 3; ++c) val[c] += L->emission[c] * cy * cq / d2 * A;
                 }
             } else {
@@ -873,7 +897,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                 orc_cosine_dir(pn, orc_uniform(seed, pid, s, 0, 0),
                                orc_uniform(seed, pid, s, 0, 1), d);
                 orc_hit h;
-                int ok = orc_trace(prims, n_prims, o, d, 0.0, &h);
+                int ok = orc_trace_at(prims, n_prims, o, d, 0.0, &h, shift);
                 if (ok && h.back) { backs++; ok = 0; }
                 if (ok) {
                     const orc_prim *pr = &prims[h.prim];
@@ -895,6 +919,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                                 double q[3], nq[3];
                                 double A = orc_light_point(L, orc_uniform(seed, pid, s, 0, base + 2 * j),
                                                            orc_uniform(seed, pid, s, 0, base + 2 * j + 1), q, nq);
+                                if (shift) for (int a = 0; a < 3; ++a) q[a] += shift[3 * lights[j] + a];
                                 double w[3] = {q[0] - oy[0], q[1] - oy[1], q[2] - oy[2]};
                                 double d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], dl = sqrt(d2);
                                 for (int a = 0; a < 3; ++a) w[a] /= dl;
@@ -902,7 +927,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                                 double cq = -(nq[0] * w[0] + nq[1] * w[1] + nq[2] * w[2]);
                                 if (cy <= 0.0 || cq <= 0.0) continue;
                                 orc_hit hh;
-                                if (!orc_trace(prims, n_prims, oy, w, 0.0, &hh) || hh.prim != lights[j])
+                                if (!orc_trace_at(prims, n_prims, oy, w, 0.0, &hh, shift) || hh.prim != lights[j])
                                     continue;
                                 double G = cy * cq / d2 * A;
                                 for (int c = 0; c < 3; ++c)
@@ -915,7 +940,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
                         if (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0) break;
                         orc_cosine_dir(ny, orc_uniform(seed, pid, s, 0, base + 2 * J),
                                        orc_uniform(seed, pid, s, 0, base + 2 * J + 1), d);
-                        if (!orc_trace(prims, n_prims, oy, d, 0.0, &h) || h.back) break;
+                        if (!orc_trace_at(prims, n_prims, oy, d, 0.0, &h, shift) || h.back) break;
                         if (flags & ORC_MC_EMIT_ON_HIT) {
                             const orc_prim *pe = &prims[h.prim];
                             for (int c = 0; c < 3; ++c) rad[c] += beta[c] * pe->emission[c];
@@ -938,6 +963,7 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
         }
         if (out_backfaces) out_backfaces[i] = backs;
         if (out_valid) out_valid[i] = (uint8_t)((2 * backs <= spp) && any);
+        free(shift);
     }
 }
 

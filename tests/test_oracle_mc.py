@@ -244,3 +244,53 @@ def test_sampler_volume_and_surface_points():
     assert counts.sum() == n_surf
     areas = np.array([6, 6, 3, 3, 2, 2], float)
     np.testing.assert_allclose(counts / n_surf, areas / areas.sum(), atol=0.01)
+
+
+# ------------------------------------------------------------ scenes that change with t (Sec. 6)
+@pytest.mark.parametrize("flags", [O.MC_INCLUDE_DIRECT, O.MC_DIRECT_AT_ORIGIN])
+def test_moving_disk_closed_form(flags):
+    """A disk light moving away along its axis: at scene variable t it sits
+    at distance h + t, and E = pi L r^2 / (r^2 + (h + t)^2) on the axis."""
+    h, r, L = 1.0, 0.8, 3.0
+    prims, x, n, _ = _disk_case(h=h, r=r, L=L)
+    motion = np.float32([[0.0, 0.0, 1.0]])
+    ts = np.float32([0.0, 0.5, 1.0])
+    E, var, _, _ = O.mc_irradiance(prims, np.repeat(x, 3, 0), np.repeat(n, 3, 0), 200000, 1,
+                                   flags, 12, motion=motion, t=ts)
+    for k, tv in enumerate(ts):
+        want = math.pi * L * r * r / (r * r + (h + tv) ** 2)
+        z = (E[k] - want) / np.sqrt(var[k])
+        assert np.abs(z).max() < 4.0, (tv, E[k], want)
+        assert np.abs(E[k] / want - 1).max() < 0.01
+
+
+def test_motion_equals_translated_scene():
+    """Translating primitives by t * motion inside the estimator gives the
+    estimate of the scene built already translated (same random streams)."""
+    room = make_room(2001)
+    prims = np.array(room["prims"], copy=True)
+    motion = np.zeros((len(prims), 3), np.float32)
+    lights = np.nonzero(prims["emission"].max(axis=1) > 0)[0]
+    motion[lights] = [0.5, 0.0, -0.25]      # both ceiling lights slide
+    motion[-1] = [0.0, 0.0, 0.5]            # and the last box moves
+    tv = 0.5
+    moved = np.array(prims, copy=True)
+    for k in np.nonzero(np.abs(motion).sum(1))[0]:
+        off = (tv * motion[k]).astype(np.float32)
+        moved["p"][k] += off
+        if prims["kind"][k] == 0:
+            moved["q"][k] += off
+    rng = np.random.default_rng(41)
+    x = rng.uniform([1, 0.5, 3], [9, 3.5, 9], size=(8, 3)).astype(np.float32)
+    nn = _rand_dirs(rng, 8)
+    a = O.mc_irradiance(prims, x, nn, 256, 3, O.MC_NEE, 9, motion=motion,
+                        t=np.full(8, tv, np.float32))
+    b = O.mc_irradiance(moved, x, nn, 256, 3, O.MC_NEE, 9)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-9, atol=1e-12)
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])
+    # t = 0 is the static scene, and t changes the answer
+    c = O.mc_irradiance(prims, x, nn, 256, 3, O.MC_NEE, 9, motion=motion, t=np.zeros(8, np.float32))
+    d = O.mc_irradiance(prims, x, nn, 256, 3, O.MC_NEE, 9)
+    np.testing.assert_array_equal(c[0], d[0])
+    assert not np.allclose(a[0], d[0])
