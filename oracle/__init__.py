@@ -104,7 +104,7 @@ def lib():
                                    C.c_double, C.c_int, dp, dp, u8p]
         L.orc_upsample.restype = None
         L.orc_sample_points.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_int64,
-                                        C.c_int64, C.c_uint64, fp, fp]
+                                        C.c_int64, C.c_uint64, fp, fp, fp]
         _lib = L
     return _lib
 
@@ -310,17 +310,19 @@ def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None, motio
     return E, var, bf, vd
 
 
-def sample_points(prims, lo, hi, count, n_surface, seed):
-    """Sec. 4.5 training points: volume points then surface points."""
+def sample_points(prims, lo, hi, count, n_surface, seed, with_t=False):
+    """Sec. 4.5 training points: volume points then surface points (and a
+    scene variable per point, uniform on [0, 1), with with_t)."""
     pr = np.ascontiguousarray(prims)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
     x = np.zeros((count, 3), np.float32)
     n = np.zeros((count, 3), np.float32)
+    t = np.zeros(count, np.float32) if with_t else None
     lib().orc_sample_points(pr.ctypes.data, len(pr), _P(lo, C.c_double), _P(hi, C.c_double),
                             int(count), int(n_surface), int(seed), _P(x, C.c_float),
-                            _P(n, C.c_float))
-    return x, n
+                            _P(n, C.c_float), _P(t, C.c_float))
+    return (x, n, t) if with_t else (x, n)
 
 
 def upsample(cfg: Config, width, height, pos, nrm, half_E, mask=None, albedo=None,

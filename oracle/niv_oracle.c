@@ -974,10 +974,11 @@ void orc_mc_irradiance(const orc_prim *prims, int n_prims, const float *x,
  * Random stream 1 of the counter-based generator, counter (i, 0, block, 1).
  * Volume point: dims 0-2 position, 3-4 direction (z = 1 - 2u, phi = 2 pi u).
  * Surface point: dim 0 picks the face through the cumulative area table,
- * dims 1-2 place the point on it. */
+ * dims 1-2 place the point on it.  out_t (or NULL): a scene variable per
+ * point uniform on [0, 1) (Sec. 6: sampled at random for training), dim 7. */
 void orc_sample_points(const orc_prim *prims, int n_prims, const double lo[3],
                        const double hi[3], int64_t count, int64_t n_surface,
-                       uint64_t seed, float *out_x, float *out_n)
+                       uint64_t seed, float *out_x, float *out_n, float *out_t)
 {
     /* faces: (prim, face) with area; box faces 0..5 = -x,+x,-y,+y,-z,+z */
     int64_t nf = 0;
@@ -1009,6 +1010,7 @@ void orc_sample_points(const orc_prim *prims, int n_prims, const double lo[3],
             double z = 1.0 - 2.0 * u3, phi = 2.0 * ORC_PI * u4, r = sqrt(fmax(0.0, 1.0 - z * z));
             double n[3] = {r * cos(phi), r * sin(phi), z};
             for (int a = 0; a < 3; ++a) { out_x[3 * i + a] = (float)p[a]; out_n[3 * i + a] = (float)n[a]; }
+            if (out_t) out_t[i] = (float)orc_uniform(seed, (uint64_t)i, 0, 1, 7);
         } else {
             double target = u0 * acc;
             int64_t lo_i = 0, hi_i = nf - 1;
@@ -1032,6 +1034,7 @@ void orc_sample_points(const orc_prim *prims, int n_prims, const double lo[3],
                 n[a] = (f & 1) ? 1.0 : -1.0;
             }
             for (int a = 0; a < 3; ++a) { out_x[3 * i + a] = (float)p[a]; out_n[3 * i + a] = (float)n[a]; }
+            if (out_t) out_t[i] = (float)orc_uniform(seed, (uint64_t)i, 0, 1, 7);
         }
     }
     free(fp); free(ff); free(cdf);

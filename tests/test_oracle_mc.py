@@ -294,3 +294,19 @@ def test_motion_equals_translated_scene():
     d = O.mc_irradiance(prims, x, nn, 256, 3, O.MC_NEE, 9)
     np.testing.assert_array_equal(c[0], d[0])
     assert not np.allclose(a[0], d[0])
+
+
+def test_sampler_scene_variable():
+    """The scene variable drawn with each training point is uniform on
+    [0, 1) (dimension 7 of the point's stream) and leaves the points as they
+    were."""
+    prims = enclosure_prims((0, 0, 0), (1, 2, 3), (0.5, 0.5, 0.5), (0, 0, 0))
+    lo, hi = np.zeros(3), np.array([1.0, 2.0, 3.0])
+    x0, n0 = O.sample_points(prims, lo, hi, 20000, 4000, 11)
+    x, n, t = O.sample_points(prims, lo, hi, 20000, 4000, 11, with_t=True)
+    np.testing.assert_array_equal(x, x0)
+    np.testing.assert_array_equal(n, n0)
+    assert (t >= 0).all() and (t < 1).all()
+    from scipy.stats import kstest
+    assert kstest(t, "uniform").pvalue > 1e-3
+    assert t[5] == np.float32(O.uniform(11, 5, 0, 1, 7))
