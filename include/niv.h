@@ -357,6 +357,21 @@ niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, in
                          double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
                          uint8_t *out_valid, hipStream_t stream);
 
+/* Scenes that change with a scene variable t (Sec. 6: moving emitters,
+ * moving occluders): motion (host, [n_prims][3] float, or NULL for a static
+ * scene) translates primitive k by t * motion[k]; t comes per point
+ * (mc_irradiance_at) or per frame (extra value 0 of a niv_frame, for the
+ * Monte Carlo fallback).  Training points on surfaces are drawn only on
+ * primitives that do not move.  The ray offset uses the extent at t = 0. */
+niv_status mc_scene_set_motion(mc_scene *s, const float *motion);
+
+/* mc_irradiance with the scene variable of each point: t [count] float
+ * (device), or NULL for t = 0. */
+niv_status mc_irradiance_at(const mc_scene *s, const float *x, const float *nrm, const float *t,
+                            int64_t count, int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
+                            double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
+                            uint8_t *out_valid, hipStream_t stream);
+
 /* Training points (Sec. 4.2 and 4.5): points [0, count - n_surface) uniform in
  * the box [lo, hi] (host arrays of 3) with a normal uniform on the sphere;
  * points [count - n_surface, count) uniform by area over the non-emitting
@@ -365,6 +380,13 @@ niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, in
 niv_status mc_sample_points(const mc_scene *s, const double *lo, const double *hi, int64_t count,
                             int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
                             hipStream_t stream);
+
+/* mc_sample_points that also draws a scene variable per point, uniform on
+ * [0, 1) (Sec. 6: the variable is sampled at random during training):
+ * out_t [count] float (device), dimension 7 of the point's stream. */
+niv_status mc_sample_points_t(const mc_scene *s, const double *lo, const double *hi, int64_t count,
+                              int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
+                              float *out_t, hipStream_t stream);
 
 const char *niv_status_string(niv_status s);
 

@@ -11,7 +11,7 @@ from .workloads import WORKLOADS, Workload, get_workload
 from .params import make_params, xavier_bound
 from .scene import (PRIM_DTYPE, PRIM_BOX, PRIM_RECT, PRIM_DISK, make_room,
                     room_prims, enclosure_prims, disk_prim, rect_prim, box_prim,
-                    scene_bounds)
+                    scene_bounds, room_motion)
 from .gbuffer import (Camera, default_camera, cast_gbuffer, make_room_gbuffer,
                       make_workload_gbuffer)
 from .mesh import icosphere, displaced_sphere
@@ -24,5 +24,5 @@ __all__ = [
     "enclosure_prims", "disk_prim", "rect_prim", "box_prim", "scene_bounds",
     "Camera", "default_camera", "cast_gbuffer", "make_room_gbuffer",
     "unit_cube_queries", "uniform_unit_normals", "make_room_gbuffers",
-    "make_workload_gbuffer", "icosphere", "displaced_sphere",
+    "make_workload_gbuffer", "icosphere", "displaced_sphere", "room_motion",
 ]

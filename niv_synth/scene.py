@@ -176,3 +176,20 @@ def make_room(seed: int, n_boxes: int = 32, n_lights: int = 2,
         "prims": np.array(prims, dtype=PRIM_DTYPE),
         "prims_no_lights": prims_no_lights,
     }
+
+
+def room_motion(room, light_dx: float = 3.0, box_dz: float = 1.5):
+    """Motion vectors for a room that changes with a scene variable t in
+    [0, 1] (Sec. 6): each ceiling light slides along x by light_dx towards the
+    middle of the room, and the first box moves along z by box_dz (a moving
+    occluder).  Returns [n_prims, 3] float32 (zero for static primitives)."""
+    prims = room["prims"]
+    motion = np.zeros((len(prims), 3), np.float32)
+    mid = 0.5 * (room["lo"][0] + room["hi"][0])
+    for k in range(len(prims)):
+        if prims["emission"][k].max() > 0:
+            motion[k, 0] = light_dx if prims["p"][k][0] < mid else -light_dx
+    boxes = np.nonzero(prims["kind"] == 0)[0]
+    if len(boxes):
+        motion[boxes[0], 2] = box_dz
+    return motion

@@ -105,5 +105,17 @@ for _w in (16, 32, 64):
         param_seed=2002 + _w, precision="fp16", pos_bands=8)
 
 
+# On-GPU training of the field with one scene variable (Sec. 6): the room of
+# room_train with its two ceiling lights sliding along x and one box moving
+# along z as t goes from 0 to 1 (niv_synth.scene.room_motion); the hash
+# table doubled as the paper does for this application.
+WORKLOADS["room_train_6d"] = Workload(
+    name="room_train_6d", n_levels=16, log2_T=18, n_features=2, base_res=16.0,
+    per_level_scale=math.sqrt(2.0), sh_bands=4, n_extra=1, extra_bands=8, width=64,
+    n_hidden=3, n_out=3, aabb_min=ROOM_LO, aabb_max=ROOM_HI, grid_init=(-1e-4, 1e-4),
+    n_queries=1 << 18, scene_seeds=(2001,), param_seed=6002, point_seed=6001,
+    precision="fp16", extra_values=(0.0, 0.5, 1.0))
+
+
 def get_workload(name: str) -> Workload:
     return WORKLOADS[name]

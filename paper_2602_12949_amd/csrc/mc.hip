@@ -11,6 +11,7 @@
 #include <math.h>
 #include <new>
 #include <string.h>
+#include <vector>
 
 #include "niv_internal.h"
 
@@ -122,47 +123,80 @@ __device__ inline void rect_hit(ConstPrims prims, int k, const Ray &r, float &be
     bback = r.d[A] * prims[k].sign > 0.0f;
 }
 
+struct Motion4 {
+    float x, y, z, w;   // translation per unit of the scene variable; w != 0: moving
+};
+typedef const __attribute__((address_space(4))) Motion4 *ConstMotion;
+
+// the ray origin moved by -shift (a primitive translated by shift is tested
+// with the translated ray: same distance, side and normal)
+__device__ inline Ray shifted(const Ray &r, float sx, float sy, float sz)
+{
+    Ray q = r;
+    q.o[0] = r.o[0] - sx; q.o[1] = r.o[1] - sy; q.o[2] = r.o[2] - sz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.oi[a] = q.o[a] * q.inv[a];
+    return q;
+}
+
+// Primitive k against ray r: updates (best, bp, bback).
+__device__ inline void prim_hit(ConstPrims prims, int k, const Ray &r, float &best, int &bp, bool &bback)
+{
+    const int kind = prims[k].kind;
+    if (kind == 0) {
+        const float x1 = slab(prims[k].p[0], r, 0), x2 = slab(prims[k].q[0], r, 0);
+        const float y1 = slab(prims[k].p[1], r, 1), y2 = slab(prims[k].q[1], r, 1);
+        const float z1 = slab(prims[k].p[2], r, 2), z2 = slab(prims[k].q[2], r, 2);
+        const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
+        const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
+        if (!(tn <= tf)) return;
+        const bool front = tn > 0.0f;
+        const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
+        if (t > 0.0f && t < best) { best = t; bp = k; bback = !front; }
+    } else if (kind == 1) {
+        const int a = prims[k].axis;
+        if (a == 0) rect_hit<0>(prims, k, r, best, bp, bback);
+        else if (a == 1) rect_hit<1>(prims, k, r, best, bp, bback);
+        else rect_hit<2>(prims, k, r, best, bp, bback);
+    } else {
+        const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
+        const float den = r.d[0] * nx + r.d[1] * ny + r.d[2] * nz;
+        if (den == 0.0f) return;
+        const float t = ((prims[k].p[0] - r.o[0]) * nx + (prims[k].p[1] - r.o[1]) * ny +
+                         (prims[k].p[2] - r.o[2]) * nz) / den;
+        if (!(t > 0.0f) || !(t < best)) return;
+        float r2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float e = __builtin_fmaf(t, r.d[c], r.o[c]) - prims[k].p[c];
+            r2 = __builtin_fmaf(e, e, r2);
+        }
+        if (r2 > prims[k].radius * prims[k].radius) return;
+        best = t; bp = k;
+        bback = den > 0.0f;
+    }
+}
+
+// MOVING: the scene changes with the point's scene variable tv (uniform over
+// the wave): primitive k is translated by tv * motion[k] (motion[k].w != 0
+// marks a moving primitive).
+template <bool MOVING>
 __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], const float d[3],
-                             Hit &h)
+                             Hit &h, ConstMotion motion = nullptr, float tv = 0.0f)
 {
     const Ray r = make_ray(o, d);
     float best = INFINITY;
     int bp = -1;
     bool bback = false;
     for (int k = 0; k < n_prims; ++k) {
-        const int kind = prims[k].kind;
-        if (kind == 0) {
-            const float x1 = slab(prims[k].p[0], r, 0), x2 = slab(prims[k].q[0], r, 0);
-            const float y1 = slab(prims[k].p[1], r, 1), y2 = slab(prims[k].q[1], r, 1);
-            const float z1 = slab(prims[k].p[2], r, 2), z2 = slab(prims[k].q[2], r, 2);
-            const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
-            const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
-            if (!(tn <= tf)) continue;
-            const bool front = tn > 0.0f;
-            const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
-            if (t > 0.0f && t < best) { best = t; bp = k; bback = !front; }
-        } else if (kind == 1) {
-            const int a = prims[k].axis;
-            if (a == 0) rect_hit<0>(prims, k, r, best, bp, bback);
-            else if (a == 1) rect_hit<1>(prims, k, r, best, bp, bback);
-            else rect_hit<2>(prims, k, r, best, bp, bback);
-        } else {
-            const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
-            const float den = r.d[0] * nx + r.d[1] * ny + r.d[2] * nz;
-            if (den == 0.0f) continue;
-            const float t = ((prims[k].p[0] - r.o[0]) * nx + (prims[k].p[1] - r.o[1]) * ny +
-                             (prims[k].p[2] - r.o[2]) * nz) / den;
-            if (!(t > 0.0f) || !(t < best)) continue;
-            float r2 = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float e = __builtin_fmaf(t, r.d[c], r.o[c]) - prims[k].p[c];
-                r2 = __builtin_fmaf(e, e, r2);
+        if constexpr (MOVING) {
+            if (motion[k].w != 0.0f) {
+                prim_hit(prims, k, shifted(r, tv * motion[k].x, tv * motion[k].y, tv * motion[k].z),
+                         best, bp, bback);
+                continue;
             }
-            if (r2 > prims[k].radius * prims[k].radius) continue;
-            best = t; bp = k;
-            bback = den > 0.0f;
         }
+        prim_hit(prims, k, r, best, bp, bback);
     }
     h.t = best;
     h.prim = bp;
@@ -173,11 +207,16 @@ __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], co
     // normal is assembled with selects (no indexing of a register array)
     const int kind = prims[bp].kind;
     if (kind == 0) {
+        Ray rb = r;
+        if constexpr (MOVING) {
+            if (motion[bp].w != 0.0f)
+                rb = shifted(r, tv * motion[bp].x, tv * motion[bp].y, tv * motion[bp].z);
+        }
         // the face whose slab distance is the hit distance: entry (front) or exit (back)
         float n3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float t1 = slab(prims[bp].p[c], r, c), t2 = slab(prims[bp].q[c], r, c);
+            const float t1 = slab(prims[bp].p[c], rb, c), t2 = slab(prims[bp].q[c], rb, c);
             const float tc = bback ? fmaxf(t1, t2) : fminf(t1, t2);
             n3[c] = tc == best ? ((r.d[c] > 0.0f) != bback ? -1.0f : 1.0f) : 0.0f;
         }
@@ -250,6 +289,8 @@ __device__ inline float light_point(ConstPrims prims, int k, float u1, float u2,
 struct McArgs {
     const Prim *prims;
     const int32_t *lights;
+    const Motion4 *motion;    // [n_prims] (x, y, z, moving) or null
+    const float *t;           // [count] scene variable per point or null (0)
     int32_t n_prims, n_lights;
     float eps;
     int32_t spp, bounces, flags;
@@ -263,11 +304,16 @@ struct McArgs {
 };
 
 // Next-event estimate at y with normal ny toward light j: L cos cos / d^2 A.
+template <bool MOVING>
 __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy[3],
-                           const float ny[3], float u1, float u2, float &G)
+                           const float ny[3], float u1, float u2, float &G, ConstMotion motion,
+                           float tv)
 {
     float q[3], nq[3];
     float A = light_point(prims, lk, u1, u2, q, nq);
+    if constexpr (MOVING) {
+        q[0] += tv * motion[lk].x; q[1] += tv * motion[lk].y; q[2] += tv * motion[lk].z;
+    }
     float w[3] = {q[0] - oy[0], q[1] - oy[1], q[2] - oy[2]};
     float d2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], il = 1.0f / sqrtf(d2);
 #pragma unroll
@@ -276,7 +322,7 @@ __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy
     float cq = -(nq[0] * w[0] + nq[1] * w[1] + nq[2] * w[2]);
     if (cy <= 0.0f || cq <= 0.0f) return false;
     Hit hh;
-    if (!trace(prims, n_prims, oy, w, hh) || hh.prim != lk) return false;
+    if (!trace<MOVING>(prims, n_prims, oy, w, hh, motion, tv) || hh.prim != lk) return false;
     G = cy * cq / d2 * A;
     return true;
 }
@@ -284,10 +330,11 @@ __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy
 // Wave-cooperative estimate at one point: lanes take samples lane, lane+64,
 // ...; returns (in every lane) the FP64 sums of the sample values and of
 // their squares, and the back-face count.
+template <bool MOVING>
 __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int J, float eps,
                                 const float px[3], const float pn_in[3], int spp, int bounces,
                                 int flags, uint64_t seed, uint64_t point, int lane, double s1[3],
-                                double s2[3], int &backs)
+                                double s2[3], int &backs, ConstMotion motion, float tv)
 {
     const int stride = 2 * J + 2;
     float pn[3] = {pn_in[0], pn_in[1], pn_in[2]};
@@ -306,14 +353,14 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
             for (int j = 0; j < J; ++j) {
                 int lk = lights[j];
                 float G;
-                if (nee(prims, np, lk, o, pn, rng.u(2 * j), rng.u(2 * j + 1), G))
+                if (nee<MOVING>(prims, np, lk, o, pn, rng.u(2 * j), rng.u(2 * j + 1), G, motion, tv))
                     for (int c = 0; c < 3; ++c) val[c] += prims[lk].emission[c] * G;
             }
         } else {
             float d[3];
             cosine_dir(pn, rng.u(0), rng.u(1), d);
             Hit h;
-            bool ok = trace(prims, np, o, d, h);
+            bool ok = trace<MOVING>(prims, np, o, d, h, motion, tv);
             if (ok && h.back) { backs++; ok = false; }
             if (ok) {
                 float rad[3] = {0.f, 0.f, 0.f};
@@ -332,7 +379,8 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
                         for (int j = 0; j < J; ++j) {
                             int lk = lights[j];
                             float G;
-                            if (nee(prims, np, lk, oy, ny, rng.u(base + 2 * j), rng.u(base + 2 * j + 1), G))
+                            if (nee<MOVING>(prims, np, lk, oy, ny, rng.u(base + 2 * j), rng.u(base + 2 * j + 1), G,
+                                            motion, tv))
                                 for (int c = 0; c < 3; ++c)
                                     rad[c] += beta[c] * rho[c] * 0.318309886183790672f * prims[lk].emission[c] * G;
                         }
@@ -342,7 +390,7 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
                     for (int c = 0; c < 3; ++c) beta[c] *= rho[c];
                     if (beta[0] == 0.f && beta[1] == 0.f && beta[2] == 0.f) break;
                     cosine_dir(ny, rng.u(base + 2 * J), rng.u(base + 2 * J + 1), d);
-                    if (!trace(prims, np, oy, d, h) || h.back) break;
+                    if (!trace<MOVING>(prims, np, oy, d, h, motion, tv) || h.back) break;
                     if (flags & 2)
                         for (int c = 0; c < 3; ++c) rad[c] += beta[c] * prims[h.prim].emission[c];
                     for (int c = 0; c < 3; ++c) { y[c] = oy[c] + h.t * d[c]; ny[c] = h.n[c]; }
@@ -367,6 +415,7 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
     }
 }
 
+template <bool MOVING>
 __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -378,8 +427,9 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
     const float pn[3] = {a.nrm[3 * i], a.nrm[3 * i + 1], a.nrm[3 * i + 2]};
     double s1[3], s2[3];
     int backs;
-    mc_point(prims, a.n_prims, lights, a.n_lights, a.eps, px, pn, a.spp, a.bounces, a.flags, a.seed,
-             (uint64_t)i, lane, s1, s2, backs);
+    const float tv = (MOVING && a.t) ? a.t[i] : 0.0f;
+    mc_point<MOVING>(prims, a.n_prims, lights, a.n_lights, a.eps, px, pn, a.spp, a.bounces, a.flags,
+                     a.seed, (uint64_t)i, lane, s1, s2, backs, (ConstMotion)a.motion, tv);
     if (lane == 0) {
         const double S = (double)a.spp;
         bool any = false;
@@ -417,8 +467,14 @@ __global__ __launch_bounds__(256) void k_mc_fallback(const FbArgs a)
         const float pn[3] = {nrm[3 * q], nrm[3 * q + 1], nrm[3 * q + 2]};
         double s1[3], s2[3];
         int backs;
-        mc_point(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn, a.spp,
-                 a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs);
+        if (ka->f[fi].motion)  // scene variable of the frame
+            mc_point<true>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
+                           a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
+                           (ConstMotion)ka->f[fi].motion, ka->f[fi].t);
+        else
+            mc_point<false>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
+                            a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
+                            nullptr, 0.0f);
         if (lane == 0) {
             float *oE = ka->f[fi].out_E, *oL = ka->f[fi].out_L;
             const float *alb = ka->f[fi].albedo;
@@ -445,6 +501,7 @@ struct SampleArgs {
     int64_t count, n_surface;
     uint64_t seed;
     float *out_x, *out_n;
+    float *out_t;               // scene variable per point (dimension 7), or null
 };
 
 __device__ inline double u64(Rng &r, int d) { return (double)r.u(d); }
@@ -494,6 +551,7 @@ __global__ __launch_bounds__(256) void k_sample_points(const SampleArgs a)
         a.out_x[3 * i + c] = (float)p[c];
         a.out_n[3 * i + c] = (float)n[c];
     }
+    if (a.out_t) a.out_t[i] = rng.u(7);
 }
 
 }  // namespace niv
@@ -505,20 +563,23 @@ struct mc_scene {
     int32_t *d_lights = nullptr;   // indices of emitting primitives
     int32_t *d_face_prim = nullptr, *d_face_id = nullptr;
     double *d_cdf = nullptr;
+    Motion4 *d_motion = nullptr;   // per primitive (x, y, z, moving), or null: static scene
     int32_t n_prims = 0, n_lights = 0, n_faces = 0;
     double total_area = 0.0;
     float eps = 0.0f;
+    std::vector<Prim> prims;       // host copy (rebuilds the sampler's face table)
 };
 
 namespace niv {
 void mc_scene_device_view(const struct mc_scene *s, const void **prims, const int32_t **lights,
-                          int32_t *n_prims, int32_t *n_lights, float *eps)
+                          int32_t *n_prims, int32_t *n_lights, float *eps, const void **motion)
 {
     *prims = s ? s->d_prims : nullptr;
     *lights = s ? s->d_lights : nullptr;
     *n_prims = s ? s->n_prims : 0;
     *n_lights = s ? s->n_lights : 0;
     *eps = s ? s->eps : 0.0f;
+    *motion = s ? s->d_motion : nullptr;
 }
 
 hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream)
@@ -547,7 +608,48 @@ void release(mc_scene *s)
     (void)hipFree(s->d_face_prim);
     (void)hipFree(s->d_face_id);
     (void)hipFree(s->d_cdf);
+    (void)hipFree(s->d_motion);
     delete s;
+}
+// Cumulative-area table of the sampler's surfaces: every rectangle and box
+// face that does not emit and does not move.
+niv_status upload_faces(mc_scene *s, const float *motion)
+{
+    const int n = s->n_prims;
+    std::vector<int32_t> fp, ff;
+    std::vector<double> cdf;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const Prim &p = s->prims[k];
+        if (is_light(p)) continue;
+        if (motion && (motion[3 * k] != 0.f || motion[3 * k + 1] != 0.f || motion[3 * k + 2] != 0.f)) continue;
+        if (p.kind == 1) {
+            acc += 4.0 * (double)p.q[0] * p.q[1];
+            fp.push_back(k); ff.push_back(-1); cdf.push_back(acc);
+        } else if (p.kind == 0) {
+            for (int f = 0; f < 6; ++f) {
+                int ax = f / 2, u = (ax + 1) % 3, v = (ax + 2) % 3;
+                acc += ((double)p.q[u] - p.p[u]) * ((double)p.q[v] - p.p[v]);
+                fp.push_back(k); ff.push_back(f); cdf.push_back(acc);
+            }
+        }
+    }
+    const int nf = (int)fp.size();
+    s->n_faces = nf;
+    s->total_area = acc;
+    niv_status st = NIV_OK;
+    if (!s->d_face_prim) {
+        // room for every face of every primitive, so a later table fits too
+        st = hs(hipMalloc(&s->d_face_prim, sizeof(int32_t) * (6 * n + 1)));
+        if (st == NIV_OK) st = hs(hipMalloc(&s->d_face_id, sizeof(int32_t) * (6 * n + 1)));
+        if (st == NIV_OK) st = hs(hipMalloc(&s->d_cdf, sizeof(double) * (6 * n + 1)));
+    }
+    if (st == NIV_OK && nf > 0) {
+        st = hs(hipMemcpy(s->d_face_prim, fp.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+        if (st == NIV_OK) st = hs(hipMemcpy(s->d_face_id, ff.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice));
+        if (st == NIV_OK) st = hs(hipMemcpy(s->d_cdf, cdf.data(), sizeof(double) * nf, hipMemcpyHostToDevice));
+    }
+    return st;
 }
 }  // namespace
 
@@ -564,10 +666,6 @@ niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene *
     int32_t lights[kMaxLights];
     int n_lights = 0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    int32_t *fp = new int32_t[6 * n_prims], *ff = new int32_t[6 * n_prims];
-    double *cdf = new double[6 * n_prims];
-    int nf = 0;
-    double acc = 0.0;
     niv_status st = NIV_OK;
     for (int k = 0; k < n_prims && st == NIV_OK; ++k) {
         const Prim &p = P[k];
@@ -593,17 +691,6 @@ niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene *
             if (a[c] < lo[c]) lo[c] = a[c];
             if (b[c] > hi[c]) hi[c] = b[c];
         }
-        if (is_light(p)) continue;
-        if (p.kind == 1) {
-            acc += 4.0 * (double)p.q[0] * p.q[1];
-            fp[nf] = k; ff[nf] = -1; cdf[nf] = acc; nf++;
-        } else if (p.kind == 0) {
-            for (int f = 0; f < 6; ++f) {
-                int ax = f / 2, u = (ax + 1) % 3, v = (ax + 2) % 3;
-                acc += ((double)p.q[u] - p.p[u]) * ((double)p.q[v] - p.p[v]);
-                fp[nf] = k; ff[nf] = f; cdf[nf] = acc; nf++;
-            }
-        }
     }
     if (st == NIV_OK) {
         double extent = 0.0;
@@ -611,24 +698,13 @@ niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene *
         s->eps = (float)(1e-4 * extent);
         s->n_prims = n_prims;
         s->n_lights = n_lights;
-        s->n_faces = nf;
-        s->total_area = acc;
+        s->prims.assign(P, P + n_prims);
         st = hs(hipMalloc(&s->d_prims, sizeof(Prim) * n_prims));
         if (st == NIV_OK) st = hs(hipMalloc(&s->d_lights, sizeof(int32_t) * kMaxLights));
-        if (st == NIV_OK) st = hs(hipMalloc(&s->d_face_prim, sizeof(int32_t) * (nf + 1)));
-        if (st == NIV_OK) st = hs(hipMalloc(&s->d_face_id, sizeof(int32_t) * (nf + 1)));
-        if (st == NIV_OK) st = hs(hipMalloc(&s->d_cdf, sizeof(double) * (nf + 1)));
         if (st == NIV_OK) st = hs(hipMemcpy(s->d_prims, P, sizeof(Prim) * n_prims, hipMemcpyHostToDevice));
         if (st == NIV_OK) st = hs(hipMemcpy(s->d_lights, lights, sizeof(int32_t) * kMaxLights, hipMemcpyHostToDevice));
-        if (st == NIV_OK && nf > 0) {
-            st = hs(hipMemcpy(s->d_face_prim, fp, sizeof(int32_t) * nf, hipMemcpyHostToDevice));
-            if (st == NIV_OK) st = hs(hipMemcpy(s->d_face_id, ff, sizeof(int32_t) * nf, hipMemcpyHostToDevice));
-            if (st == NIV_OK) st = hs(hipMemcpy(s->d_cdf, cdf, sizeof(double) * nf, hipMemcpyHostToDevice));
-        }
+        if (st == NIV_OK) st = upload_faces(s, nullptr);
     }
-    delete[] fp;
-    delete[] ff;
-    delete[] cdf;
     if (st != NIV_OK) {
         release(s);
         return st;
@@ -637,12 +713,37 @@ niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene *
     return NIV_OK;
 }
 
+niv_status mc_scene_set_motion(mc_scene *s, const float *motion)
+{
+    if (!s) return NIV_ERR_INVALID_ARG;
+    if (motion)
+        for (int k = 0; k < 3 * s->n_prims; ++k)
+            if (!isfinite(motion[k])) return NIV_ERR_INVALID_ARG;
+    niv_status st = NIV_OK;
+    if (!motion) {
+        (void)hipFree(s->d_motion);
+        s->d_motion = nullptr;
+    } else {
+        std::vector<Motion4> m(s->n_prims);
+        for (int k = 0; k < s->n_prims; ++k) {
+            const float x = motion[3 * k], y = motion[3 * k + 1], z = motion[3 * k + 2];
+            m[k] = Motion4{x, y, z, (x != 0.f || y != 0.f || z != 0.f) ? 1.0f : 0.0f};
+        }
+        if (!s->d_motion) st = hs(hipMalloc(&s->d_motion, sizeof(Motion4) * s->n_prims));
+        if (st == NIV_OK)
+            st = hs(hipMemcpy(s->d_motion, m.data(), sizeof(Motion4) * s->n_prims, hipMemcpyHostToDevice));
+    }
+    // surface training points only on what does not move
+    if (st == NIV_OK) st = upload_faces(s, motion);
+    return st;
+}
+
 void mc_scene_destroy(mc_scene *s) { release(s); }
 
-niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
-                         int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
-                         double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
-                         uint8_t *out_valid, hipStream_t stream)
+niv_status mc_irradiance_at(const mc_scene *s, const float *x, const float *nrm, const float *t,
+                            int64_t count, int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
+                            double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
+                            uint8_t *out_valid, hipStream_t stream)
 {
     if (!s || count < 0 || spp < 1 || bounces < 0 || bounces > 16 || (flags & ~15)) return NIV_ERR_INVALID_ARG;
     if ((flags & 1) && (flags & 2)) return NIV_ERR_INVALID_ARG;  // NEE and emission-on-hit exclude each other
@@ -653,6 +754,8 @@ niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, in
     memset(&a, 0, sizeof(a));
     a.prims = s->d_prims;
     a.lights = s->d_lights;
+    a.motion = s->d_motion;
+    a.t = t;
     a.n_prims = s->n_prims;
     a.n_lights = s->n_lights;
     a.eps = s->eps;
@@ -670,13 +773,25 @@ niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, in
     a.out_valid = out_valid;
     int64_t blocks = (count + 3) / 4;
     if (blocks > 0x7fffffff) return NIV_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(k_mc_irradiance, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    if (s->d_motion)
+        hipLaunchKernelGGL(k_mc_irradiance<true>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_mc_irradiance<false>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
     return hs(hipGetLastError());
 }
 
-niv_status mc_sample_points(const mc_scene *s, const double *lo, const double *hi, int64_t count,
-                            int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
-                            hipStream_t stream)
+niv_status mc_irradiance(const mc_scene *s, const float *x, const float *nrm, int64_t count,
+                         int32_t spp, int32_t bounces, int32_t flags, uint64_t seed,
+                         double *out_E, float *out_E32, double *out_var, int32_t *out_backfaces,
+                         uint8_t *out_valid, hipStream_t stream)
+{
+    return mc_irradiance_at(s, x, nrm, nullptr, count, spp, bounces, flags, seed, out_E, out_E32,
+                            out_var, out_backfaces, out_valid, stream);
+}
+
+niv_status mc_sample_points_t(const mc_scene *s, const double *lo, const double *hi, int64_t count,
+                              int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
+                              float *out_t, hipStream_t stream)
 {
     if (!s || !lo || !hi || count < 0 || n_surface < 0 || n_surface > count) return NIV_ERR_INVALID_ARG;
     if (count == 0) return NIV_OK;
@@ -698,9 +813,17 @@ niv_status mc_sample_points(const mc_scene *s, const double *lo, const double *h
     a.seed = seed;
     a.out_x = out_x;
     a.out_n = out_n;
+    a.out_t = out_t;
     int64_t blocks = (count + 255) / 256;
     hipLaunchKernelGGL(k_sample_points, dim3((unsigned)blocks), dim3(256), 0, stream, a);
     return hs(hipGetLastError());
+}
+
+niv_status mc_sample_points(const mc_scene *s, const double *lo, const double *hi, int64_t count,
+                            int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
+                            hipStream_t stream)
+{
+    return mc_sample_points_t(s, lo, hi, count, n_surface, seed, out_x, out_n, nullptr, stream);
 }
 
 }  // extern "C"

@@ -88,6 +88,7 @@ int kernel_kind(const Model &m)
     if (c.n_levels == 8 && c.n_extra == 0 && c.width == 64 && c.n_hidden == 2) return kUnitCube;
     if (c.n_levels == 16 && c.n_extra == 0 && c.width == 64 && c.n_hidden == 3) return kRoom;
     if (c.n_levels == 16 && c.n_extra == 1 && c.width == 128 && c.n_hidden == 4) return kWide6D;
+    if (c.n_levels == 16 && c.n_extra == 1 && c.width == 64 && c.n_hidden == 3) return kRoom6D;
     return -1;
 }
 
@@ -368,7 +369,8 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
         d.out_E = fr.out_E;
         d.out_L = fr.out_L;
         d.out_flags = fr.out_flags;
-        mc_scene_device_view(fr.scene, &d.prims, &d.lights, &d.n_prims, &d.n_lights, &d.eps);
+        mc_scene_device_view(fr.scene, &d.prims, &d.lights, &d.n_prims, &d.n_lights, &d.eps, &d.motion);
+        d.t = fr.extra_values[0];
     }
     return launch_mc_fallback(b, stream) == hipSuccess ? NIV_OK : NIV_ERR_HIP;
 }

@@ -158,6 +158,8 @@ using ShapeWide6D = Shape<16, 1, 128, 4, true>;
 template <int P> using ShapeWide6DFor =
     typename std::conditional<P == NIV_FP32, Shape<16, 1, 128, 4>, ShapeWide6D>::type;
 template <int W> using ShapePE = Shape<0, 0, W, 3, false, 8>;
+// the room network with one scene variable (Sec. 6), trainable
+using ShapeRoom6D = Shape<16, 1, 64, 3>;
 
 // Lane-sliced layer-0 input order.  Virtual element v (0..15) of lane group
 // g: v < 8 is feature v % 2 of level 4 (v / 2) + g; then SH coefficients

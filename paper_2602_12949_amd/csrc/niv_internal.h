@@ -79,7 +79,8 @@ struct QueryArgs {
 };
 
 // Shapes the fused kernels are instantiated for.
-enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kPE16 = 3, kPE32 = 4, kPE64 = 5, kNumKinds = 6 };
+enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kPE16 = 3, kPE32 = 4, kPE64 = 5, kRoom6D = 6,
+                 kNumKinds = 7 };
 
 // Launch shape of the fused query: workgroup size and resident workgroups
 // per CU (0 = as many as fit); chosen by niv_autotune, else defaults.
@@ -139,9 +140,10 @@ struct FbFrame {
     uint8_t *out_flags;
     const void *prims;        // device primitives of the frame's scene, or null
     const int32_t *lights;
+    const void *motion;       // float4 per primitive (scene variable), or null
     int32_t n_prims, n_lights;
     float eps;
-    int32_t pad;
+    float t;                  // the frame's scene variable (extra value 0)
 };
 struct FbArgs {
     const uint32_t *list;
@@ -153,7 +155,7 @@ struct FbArgs {
 };
 hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream);
 void mc_scene_device_view(const struct mc_scene *s, const void **prims, const int32_t **lights,
-                          int32_t *n_prims, int32_t *n_lights, float *eps);
+                          int32_t *n_prims, int32_t *n_lights, float *eps, const void **motion);
 
 }  // namespace niv
 

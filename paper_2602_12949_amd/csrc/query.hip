@@ -71,6 +71,7 @@ OpLayout op_layout(int kind, niv_precision prec)
     case kPE16: return layout_of<P, ShapePE<16>>();                     \
     case kPE32: return layout_of<P, ShapePE<32>>();                     \
     case kPE64: return layout_of<P, ShapePE<64>>();                     \
+    case kRoom6D: return layout_of<P, ShapeRoom6D>();                   \
     default: return layout_of<P, ShapeWide6DFor<P>>();                  \
     }
     if (prec == NIV_FP32) { NIV_LAYOUT(NIV_FP32) }
@@ -112,6 +113,7 @@ hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
     case kPE16: return prepare_t<P, ShapePE<16>>(m, params, prepared, st);              \
     case kPE32: return prepare_t<P, ShapePE<32>>(m, params, prepared, st);              \
     case kPE64: return prepare_t<P, ShapePE<64>>(m, params, prepared, st);              \
+    case kRoom6D: return prepare_t<P, ShapeRoom6D>(m, params, prepared, st);            \
     default: return prepare_t<P, ShapeWide6DFor<P>>(m, params, prepared, st);           \
     }
     if (prec == NIV_FP32) { NIV_PREP(NIV_FP32) }
@@ -215,6 +217,10 @@ hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const 
         if (prec == NIV_FP32) return query_b<NIV_FP32, ShapePE<64>, true, 4>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapePE<64>, true, 4>(a, tu, st);
         return query_b<NIV_BF16, ShapePE<64>, true, 4>(a, tu, st);
+    case kRoom6D:
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeRoom6D, true, 4>(a, tu, st);
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeRoom6D, true, 4>(a, tu, st);
+        return query_b<NIV_BF16, ShapeRoom6D, true, 4>(a, tu, st);
     default:  // lane-sliced encoding: the LDS holds the whole weight block
         if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6DFor<NIV_FP32>, false, 2>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeWide6D, true, 2>(a, tu, st);

@@ -834,6 +834,9 @@ static int64_t train_bytes(const Model &m, niv_precision prec, int64_t n)
     if (m.kind == kUnitCube)
         return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeUnitCube>(n).total
                                 : train_layout_t<NIV_FP16, ShapeUnitCube>(n).total;
+    if (m.kind == kRoom6D)
+        return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom6D>(n).total
+                                : train_layout_t<NIV_FP16, ShapeRoom6D>(n).total;
     return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom>(n).total
                             : train_layout_t<NIV_FP16, ShapeRoom>(n).total;
 }
@@ -845,7 +848,7 @@ using namespace niv;
 namespace {
 niv_status hst(hipError_t e) { return e == hipSuccess ? NIV_OK : NIV_ERR_HIP; }
 bool al(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
-bool trainable(const Model &m) { return m.kind == kUnitCube || m.kind == kRoom; }
+bool trainable(const Model &m) { return m.kind == kUnitCube || m.kind == kRoom || m.kind == kRoom6D; }
 }  // namespace
 
 extern "C" {
@@ -878,6 +881,9 @@ niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state
     if (m.kind == kUnitCube)
         e = prec == NIV_FP32 ? backward_t<NIV_FP32, ShapeUnitCube>(m, *b, *st, stream)
                              : backward_t<NIV_FP16, ShapeUnitCube>(m, *b, *st, stream);
+    else if (m.kind == kRoom6D)
+        e = prec == NIV_FP32 ? backward_t<NIV_FP32, ShapeRoom6D>(m, *b, *st, stream)
+                             : backward_t<NIV_FP16, ShapeRoom6D>(m, *b, *st, stream);
     else
         e = prec == NIV_FP32 ? backward_t<NIV_FP32, ShapeRoom>(m, *b, *st, stream)
                              : backward_t<NIV_FP16, ShapeRoom>(m, *b, *st, stream);

@@ -128,6 +128,10 @@ def lib():
         L.mc_scene_destroy.restype = None
         L.mc_irradiance.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_uint64, vp, vp, vp, vp, vp, vp]
+        L.mc_scene_set_motion.argtypes = [vp, vp]
+        L.mc_sample_points_t.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, C.c_uint64, vp, vp, vp, vp]
+        L.mc_irradiance_at.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_uint64, vp, vp, vp, vp, vp, vp]
         L.mc_sample_points.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, C.c_uint64, vp, vp, vp]
         _lib = L
     return _lib
@@ -389,8 +393,21 @@ class McScene:
             _lib.mc_scene_destroy(h)
             self._h = None
 
-    def irradiance(self, x, nrm, spp, bounces, flags, seed, out=None):
-        """(E [n,3] f64, var [n,3] f64, back faces [n] i32, valid [n] u8)."""
+    def set_motion(self, motion):
+        """mc_scene_set_motion: primitive k translated by t * motion[k] (Sec. 6);
+        None makes the scene static again."""
+        import numpy as np
+        if motion is None:
+            _check(lib().mc_scene_set_motion(self._h, None), "mc_scene_set_motion")
+            self.motion = None
+            return
+        m = np.ascontiguousarray(motion, dtype=np.float32).reshape(len(self.prims), 3)
+        _check(lib().mc_scene_set_motion(self._h, m.ctypes.data), "mc_scene_set_motion")
+        self.motion = m
+
+    def irradiance(self, x, nrm, spp, bounces, flags, seed, out=None, t=None):
+        """(E [n,3] f64, var [n,3] f64, back faces [n] i32, valid [n] u8);
+        t: scene variable per point (device float [n]) or None."""
         n = x.numel() // 3
         dev = x.device
         if out is None:
@@ -399,35 +416,40 @@ class McScene:
                    torch.empty(n, dtype=torch.int32, device=dev),
                    torch.empty(n, dtype=torch.uint8, device=dev))
         E, var, bf, vd = out
-        _check(lib().mc_irradiance(self._h, _ptr(x), _ptr(nrm), n, int(spp), int(bounces),
-                                   int(flags), C.c_uint64(int(seed)), _ptr(E), None, _ptr(var),
-                                   _ptr(bf), _ptr(vd), _stream()), "mc_irradiance")
+        _check(lib().mc_irradiance_at(self._h, _ptr(x), _ptr(nrm), _ptr(t), n, int(spp), int(bounces),
+                                      int(flags), C.c_uint64(int(seed)), _ptr(E), None, _ptr(var),
+                                      _ptr(bf), _ptr(vd), _stream()), "mc_irradiance_at")
         return out
 
-    def targets(self, x, nrm, spp, bounces, seed, flags=1, out=None):
+    def targets(self, x, nrm, spp, bounces, seed, flags=1, out=None, t=None):
         """Training targets: (E [n,3] float32, valid [n] uint8)."""
         n = x.numel() // 3
         if out is None:
             out = (torch.empty((n, 3), dtype=torch.float32, device=x.device),
                    torch.empty(n, dtype=torch.uint8, device=x.device))
         E32, vd = out
-        _check(lib().mc_irradiance(self._h, _ptr(x), _ptr(nrm), n, int(spp), int(bounces),
-                                   int(flags), C.c_uint64(int(seed)), None, _ptr(E32), None,
-                                   None, _ptr(vd), _stream()), "mc_irradiance")
+        _check(lib().mc_irradiance_at(self._h, _ptr(x), _ptr(nrm), _ptr(t), n, int(spp), int(bounces),
+                                      int(flags), C.c_uint64(int(seed)), None, _ptr(E32), None,
+                                      None, _ptr(vd), _stream()), "mc_irradiance_at")
         return out
 
-    def sample_points(self, lo, hi, count, n_surface, seed, device="cuda", out=None):
-        """Training points: (x [count,3], n [count,3]) float32 on the device."""
+    def sample_points(self, lo, hi, count, n_surface, seed, device="cuda", out=None, with_t=False):
+        """Training points: (x [count,3], n [count,3]) float32 on the device,
+        and with with_t a scene variable per point (t [count], uniform)."""
         lo_a = (C.c_double * 3)(*[float(v) for v in lo])
         hi_a = (C.c_double * 3)(*[float(v) for v in hi])
         if out is None:
             out = (torch.empty((count, 3), dtype=torch.float32, device=device),
                    torch.empty((count, 3), dtype=torch.float32, device=device))
-        x, n = out
-        _check(lib().mc_sample_points(self._h, lo_a, hi_a, int(count), int(n_surface),
-                                      C.c_uint64(int(seed)), _ptr(x), _ptr(n), _stream()),
-               "mc_sample_points")
-        return x, n
+            if with_t:
+                out = out + (torch.empty(count, dtype=torch.float32, device=device),)
+        x, n = out[0], out[1]
+        t = out[2] if with_t else None
+        _check(lib().mc_sample_points_t(self._h, lo_a, hi_a, int(count), int(n_surface),
+                                        C.c_uint64(int(seed)), _ptr(x), _ptr(n), _ptr(t), _stream()),
+               "mc_sample_points_t")
+        return (x, n, t) if with_t else (x, n)
+
 
 class Graph:
     """niv_graph_capture / niv_graph_launch: the frame's launches replayed

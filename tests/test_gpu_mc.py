@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle as O
-from niv_synth import (enclosure_prims, disk_prim, rect_prim, make_room, PRIM_DTYPE)
+from niv_synth import (enclosure_prims, disk_prim, rect_prim, make_room, PRIM_DTYPE, room_motion)
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -123,6 +123,59 @@ def test_sampler_parity_with_oracle():
     xo, no = O.sample_points(room["prims"], lo, hi, cnt, ns, 123)
     np.testing.assert_array_equal(xg.cpu().numpy(), xo)
     np.testing.assert_allclose(ng.cpu().numpy(), no, atol=1e-6)
+
+
+@pytest.mark.parametrize("flags,bounces", [(O.MC_NEE, 3), (O.MC_EMIT_ON_HIT, 2)])
+def test_moving_scene_parity_with_oracle(room_points, flags, bounces):
+    """A room whose lights slide and one box moves with a per-point scene
+    variable t (Sec. 6): same random streams on both sides."""
+    from paper_2602_12949_amd import McScene
+    room, x, n = room_points
+    motion = room_motion(room)
+    tv = np.random.default_rng(17).uniform(0, 1, size=len(x)).astype(np.float32)
+    sc = McScene(room["prims"])
+    sc.set_motion(motion)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    spp = 96
+    E, var, bf, vd = [a.cpu().numpy() for a in sc.irradiance(t(x), t(n), spp, bounces, flags, 78,
+                                                             t=t(tv))]
+    Eo, varo, bfo, vdo = O.mc_irradiance(room["prims"], x, n, spp, bounces, flags, 78,
+                                         motion=motion, t=tv)
+    scale = np.maximum(np.abs(Eo).max(1, keepdims=True), 1e-3)
+    close = (np.abs(E - Eo) / scale).max(1) <= 1e-4
+    print(f"points agreeing to 1e-4: {close.mean():.4f}; back faces equal {(bf == bfo).mean():.4f}",
+          flush=True)
+    assert close.mean() >= 0.9
+    assert (bf == bfo).mean() >= 0.97 and (vd == vdo).mean() >= 0.97
+    d = ~close
+    if d.any():
+        z = (E[d] - Eo[d]) / np.sqrt(var[d] + varo[d] + 1e-30)
+        assert np.abs(z).max() < 6
+    # the static estimate differs: the motion is seen
+    Es, _, _, _ = O.mc_irradiance(room["prims"], x, n, spp, bounces, flags, 78)
+    assert np.abs(Es - Eo).max() > 1e-3
+
+
+def test_sampler_scene_variable_and_motion():
+    """The scene variable of each training point matches the oracle's bit
+    for bit; once primitives move, no surface point lands on them."""
+    from paper_2602_12949_amd import McScene
+    room = make_room(2001)
+    sc = McScene(room["prims"])
+    lo, hi = room["lo"], room["hi"]
+    xg, ng, tg = sc.sample_points(lo, hi, 20000, 4000, 321, with_t=True)
+    torch.cuda.synchronize()
+    xo, no, to = O.sample_points(room["prims"], lo, hi, 20000, 4000, 321, with_t=True)
+    np.testing.assert_array_equal(tg.cpu().numpy(), to)
+    np.testing.assert_array_equal(xg.cpu().numpy(), xo)
+    motion = room_motion(room)
+    sc.set_motion(motion)
+    xs, ns = sc.sample_points(lo, hi, 20000, 20000, 5)
+    xs = xs.cpu().numpy()
+    k = int(np.nonzero(np.abs(motion).sum(1))[0][-1])   # the moving box
+    b_lo, b_hi = room["prims"]["p"][k], room["prims"]["q"][k]
+    on_box = np.all((xs >= b_lo - 1e-5) & (xs <= b_hi + 1e-5), axis=1)
+    assert not on_box.any()
 
 
 def test_argument_checks():

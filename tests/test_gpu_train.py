@@ -6,7 +6,10 @@ Gradient bars: FP32 path relative L2 <= 1e-4 over each parameter block and
 max error <= 1e-3 of the block's largest gradient (FP32 atomics sum in
 arbitrary order); FP16 path relative L2 <= 2e-2 (activations and gradients
 are FP16 operands with unit roundoff 2^-11, summed over 64-sample chunks)
-against the oracle on the FP16-rounded parameters."""
+against the oracle on the FP16-rounded parameters, and 3e-2 for the grid
+block: a hashed grid entry holds the contribution of about one sample, a
+64-term FP16 contraction W_0^T delta_1 whose terms cancel, so its error is
+not averaged over samples as the weight blocks' errors are."""
 import numpy as np
 import pytest
 import torch
@@ -31,13 +34,14 @@ def _setup(wname, n, seed=3, grid=(-0.5, 0.5)):
     return w, oc, params, x, nrm, tgt
 
 
-def _gpu_grad(w, params, x, nrm, tgt, prec, valid=None):
+def _gpu_grad(w, params, x, nrm, tgt, prec, valid=None, extra=None):
     from paper_2602_12949_amd import NIV, Trainer
     m = NIV(w.model_dict())
     p = torch.from_numpy(params).to(DEV)
     tr = Trainer(m, p, prec, max_batch=len(x))
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
-    loss = tr.backward(t(x), t(nrm), t(tgt), valid=None if valid is None else t(valid))
+    loss = tr.backward(t(x), t(nrm), t(tgt), valid=None if valid is None else t(valid),
+                       extra=None if extra is None else t(extra))
     torch.cuda.synchronize()
     return float(loss.item()), tr.grads.cpu().numpy().astype(np.float64)
 
@@ -52,14 +56,17 @@ def _blocks(oc, g):
     return out
 
 
-def _compare(oc, g, g_ref, rel_l2_bar, max_bar=None):
+def _compare(oc, g, g_ref, rel_l2_bar, max_bar=None, grid_bar=None):
     gb, rb = _blocks(oc, g), _blocks(oc, g_ref)
+    res = {}
     for name in gb:
         a, b = gb[name], rb[name]
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         mx = np.abs(a - b).max() / np.abs(b).max()
         print(f"  {name}: rel-L2 {rel:.2e}, max/max {mx:.2e}", flush=True)
-        assert rel <= rel_l2_bar, (name, rel)
+        res[name] = (rel, mx)
+    for name, (rel, mx) in res.items():
+        assert rel <= (grid_bar if (name == "grid" and grid_bar) else rel_l2_bar), (name, rel)
         if max_bar is not None:
             assert mx <= max_bar, (name, mx)
 
@@ -82,7 +89,28 @@ def test_fp16_gradient_matches_oracle(wname, n):
     p16 = params.astype(np.float16).astype(np.float64)
     l_ref, g_ref = O.loss_grad(oc, p16, x, nrm, tgt)
     assert loss == pytest.approx(l_ref, rel=5e-3)
-    _compare(oc, g, g_ref, 2e-2)
+    _compare(oc, g, g_ref, 2e-2, grid_bar=3e-2)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_scene_variable_gradient_matches_oracle(prec):
+    """The field with one scene variable (Sec. 6): each sample carries its own
+    t, frequency-encoded into the input; gradients of every block."""
+    w, oc, params, x, nrm, tgt = _setup("room_train_6d", 4096)
+    tv = np.random.default_rng(9).uniform(0, 1, size=(4096, 1)).astype(np.float32)
+    print(f"room_train_6d {prec}", flush=True)
+    loss, g = _gpu_grad(w, params, x, nrm, tgt, prec, extra=tv)
+    pr = params.astype(np.float64) if prec == "fp32" else params.astype(np.float16).astype(np.float64)
+    l_ref, g_ref = O.loss_grad(oc, pr, x, nrm, tgt, extra=tv)
+    if prec == "fp32":
+        assert loss == pytest.approx(l_ref, rel=1e-5)
+        _compare(oc, g, g_ref, 1e-4, 1e-3)
+    else:
+        assert loss == pytest.approx(l_ref, rel=5e-3)
+        _compare(oc, g, g_ref, 2e-2, grid_bar=3e-2)
+    # the variable reaches the network: another t gives another loss
+    l2, _ = _gpu_grad(w, params, x, nrm, tgt, prec, extra=1.0 - tv)
+    assert abs(l2 - loss) > 1e-6 * abs(loss)
 
 
 def test_invalid_samples_and_ragged_batch():
