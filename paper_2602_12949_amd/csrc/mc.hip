@@ -190,13 +190,47 @@ __device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], co
     bool bback = false;
     for (int k = 0; k < n_prims; ++k) {
         if constexpr (MOVING) {
-            if (motion[k].w != 0.0f) {
+            if (motion[k].w != 0.0f)
                 prim_hit(prims, k, shifted(r, tv * motion[k].x, tv * motion[k].y, tv * motion[k].z),
                          best, bp, bback);
-                continue;
-            }
+            else
+                prim_hit(prims, k, r, best, bp, bback);
+            continue;
         }
-        prim_hit(prims, k, r, best, bp, bback);
+        // static scenes: the primitive tests written out in the loop
+        const int kind = prims[k].kind;
+        if (kind == 0) {
+            const float x1 = slab(prims[k].p[0], r, 0), x2 = slab(prims[k].q[0], r, 0);
+            const float y1 = slab(prims[k].p[1], r, 1), y2 = slab(prims[k].q[1], r, 1);
+            const float z1 = slab(prims[k].p[2], r, 2), z2 = slab(prims[k].q[2], r, 2);
+            const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
+            const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
+            if (!(tn <= tf)) continue;
+            const bool front = tn > 0.0f;
+            const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
+            if (t > 0.0f && t < best) { best = t; bp = k; bback = !front; }
+        } else if (kind == 1) {
+            const int a = prims[k].axis;
+            if (a == 0) rect_hit<0>(prims, k, r, best, bp, bback);
+            else if (a == 1) rect_hit<1>(prims, k, r, best, bp, bback);
+            else rect_hit<2>(prims, k, r, best, bp, bback);
+        } else {
+            const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
+            const float den = r.d[0] * nx + r.d[1] * ny + r.d[2] * nz;
+            if (den == 0.0f) continue;
+            const float t = ((prims[k].p[0] - r.o[0]) * nx + (prims[k].p[1] - r.o[1]) * ny +
+                             (prims[k].p[2] - r.o[2]) * nz) / den;
+            if (!(t > 0.0f) || !(t < best)) continue;
+            float r2 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float e = __builtin_fmaf(t, r.d[c], r.o[c]) - prims[k].p[c];
+                r2 = __builtin_fmaf(e, e, r2);
+            }
+            if (r2 > prims[k].radius * prims[k].radius) continue;
+            best = t; bp = k;
+            bback = den > 0.0f;
+        }
     }
     h.t = best;
     h.prim = bp;
@@ -449,6 +483,7 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
 
 // Monte Carlo replacement of the pixels a query appended to its fallback
 // list (one wave per pixel, persistent grid, length read on the device).
+template <bool MOVING>
 __global__ __launch_bounds__(256) void k_mc_fallback(const FbArgs a)
 {
     typedef const __attribute__((address_space(4))) FbArgs *ConstFb;
@@ -467,10 +502,13 @@ __global__ __launch_bounds__(256) void k_mc_fallback(const FbArgs a)
         const float pn[3] = {nrm[3 * q], nrm[3 * q + 1], nrm[3 * q + 2]};
         double s1[3], s2[3];
         int backs;
-        if (ka->f[fi].motion)  // scene variable of the frame
-            mc_point<true>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
-                           a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
-                           (ConstMotion)ka->f[fi].motion, ka->f[fi].t);
+        // MOVING: the frames' scenes change with the frame's scene variable;
+        // a static scene in such a launch has no motion table and reads none
+        const bool moving = MOVING && ka->f[fi].motion != nullptr;
+        if (moving)
+            mc_point<MOVING>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
+                             a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
+                             (ConstMotion)ka->f[fi].motion, ka->f[fi].t);
         else
             mc_point<false>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
                             a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
@@ -592,7 +630,12 @@ hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream)
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_mc_fallback, dim3((unsigned)(n_cu * 8)), dim3(256), 0, stream, a);
+    bool moving = false;
+    for (int f = 0; f < kMaxFrames; ++f) moving |= a.f[f].motion != nullptr;
+    if (moving)
+        hipLaunchKernelGGL(k_mc_fallback<true>, dim3((unsigned)(n_cu * 8)), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_mc_fallback<false>, dim3((unsigned)(n_cu * 8)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 }  // namespace niv
