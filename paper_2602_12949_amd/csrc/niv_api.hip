@@ -34,6 +34,8 @@ void build_levels(Model &m)
             double k = (double)N / (c.aabb_max[a] - c.aabb_min[a]);
             lv.k[a] = k;
             lv.o[a] = -(c.aabb_min[a] * k);
+            lv.kf[a] = (float)lv.k[a];
+            lv.of[a] = (float)lv.o[a];
         }
         lv.nm1 = (int32_t)(N - 1);
         lv.dense = dense ? 1 : 0;

@@ -404,9 +404,13 @@ __device__ inline void level_corners(const LV &lv, const double p[3], uint32_t h
 // table offset rides in the scalar offset of the load, the hash primes are
 // pre-scaled by the entry size, and dense corners differ only by scalar or
 // immediate offsets, so no 64-bit address arithmetic is spent per corner.
-template <int P, class LV>
+// F32C: cell coordinates in FP32 (the FP16 query: an FP32 coordinate of
+// ~2900 cells is off by ~2e-4 of a cell, below the operand rounding, and
+// trilinear interpolation is continuous across cell faces, so a cell chosen
+// differently at a face gives the same features); else in FP64.
+template <int P, bool F32C = false, class LV>
 __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t hmask,
-                                      __amdgpu_buffer_rsrc_t rsrc)
+                                      __amdgpu_buffer_rsrc_t rsrc, const float *pf = nullptr)
 {
     constexpr int SH = (P == NIV_FP32) ? 3 : 2;   // log2 of the entry size in bytes
     constexpr uint32_t EB = 1u << SH;
@@ -414,11 +418,19 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
     float fr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
-        int32_t c = (int32_t)s;
-        c = c < lv.nm1 ? c : lv.nm1;
-        ci[a] = c;
-        fr[a] = (float)(s - (double)c);
+        if constexpr (F32C) {
+            const float s = __builtin_fmaf(pf[a], lv.kf[a], lv.of[a]);
+            int32_t c = (int32_t)s;            // s > -1: truncation = floor clamped at 0
+            c = c < lv.nm1 ? c : lv.nm1;
+            ci[a] = c;
+            fr[a] = s - (float)c;              // exact (Sterbenz)
+        } else {
+            double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+            int32_t c = (int32_t)s;
+            c = c < lv.nm1 ? c : lv.nm1;
+            ci[a] = c;
+            fr[a] = (float)(s - (double)c);
+        }
     }
     f2 v[8];
     auto ld = [&](uint32_t voff, uint32_t soff) -> f2 {

@@ -22,6 +22,7 @@ struct LevelConst {
     uint32_t s1;     // N + 1
     uint32_t s2;     // (N + 1)^2
     uint32_t pad;
+    float kf[3], of[3];  // k and o rounded to FP32 (cell coordinates of the FP16 query)
 };
 
 // Prepared model: [level table, kLevelBytes][operand block][grid latents].

@@ -316,9 +316,12 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     row[2 * l + 1] = f2u(f.y);
                 }
             } else {
+                // the FP16 query takes its cell coordinates in FP32
+                constexpr bool F32C = (P == NIV_FP16) && !TRAIN;
+                const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
-                    f2 f = encode_level_buf<P>(lvs[l], p, a.hash_mask, grid_rsrc);
+                    f2 f = encode_level_buf<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
                     if constexpr (O::NS == 2) Prec<P>::split(f.x, f.y, row[l], row[O::PART_DW + l]);
                     else row[l] = Prec<P>::pack(f.x, f.y);
                 }
