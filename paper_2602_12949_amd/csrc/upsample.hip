@@ -37,136 +37,145 @@ __device__ inline bool unit_normal(const float *v, float *u)
     return ok;
 }
 
-struct Sample {
-    float e[3], p[3], n[3];
-    bool usable;
+// Samples a workgroup of QX x QY quads can reach: quads qx0 .. qx0 + QX - 1
+// use samples qx0 - 1 .. qx0 + QX (the same in y).
+constexpr int kSX = kQuadsX + 2, kSY = kQuadsY + 2, kStaged = kSX * kSY;
+
+// Staged samples, one array per component (consecutive lanes read
+// consecutive samples: no bank conflicts); u = 0 marks an unusable sample.
+struct Staged {
+    float ex[kStaged], ey[kStaged], ez[kStaged];
+    float px[kStaged], py[kStaged], pz[kStaged];
+    float nx[kStaged], ny[kStaged], nz[kStaged];
+    float u[kStaged];
 };
 
-// One full-resolution pixel from its window of samples: slots (sx, sy) of
-// the quad's 3 x 3 samples, NX x NY of them starting at (X0S, Y0S); dx, dy
-// of slot k are 2 (sx - 1) - i and 2 (sy - 1) - j for pixel (i, j) of the quad.
-// Computes E and the flags (L = albedo E / pi is formed by the caller).
+// E and flags of full-resolution pixel (2qx + I, 2qy + J) from its window
+// of staged samples: sx = I .. 2, sy = J .. 2 around the quad's sample
+// (sx, sy) = (1, 1) (3 per axis for an even pixel, 2 for an odd one).
 template <int I, int J>
-__device__ inline void upsample_pixel(const UpsampleArgs &a, const Sample (&s)[9], int64_t pix,
+__device__ inline void upsample_pixel(const UpsampleArgs &a, const Staged &S, int base, int64_t pix,
                                       bool on, float (&E)[3], uint32_t &flags)
 {
-    constexpr int NX = I ? 2 : 3, NY = J ? 2 : 3, X0S = I, Y0S = J;
+    constexpr int NX = I ? 2 : 3, NY = J ? 2 : 3, N = NX * NY;
     E[0] = E[1] = E[2] = 0.f;
     flags = 0;
     const float p[3] = {a.pos[3 * pix], a.pos[3 * pix + 1], a.pos[3 * pix + 2]};
     const float nr[3] = {a.nrm[3 * pix], a.nrm[3 * pix + 1], a.nrm[3 * pix + 2]};
-    if (on) {
-        float n[3];
-        const bool nok = unit_normal(nr, n);
-        if (!(finite3(p) && finite3(nr) && nok)) {
-            flags = 2u;
-        } else {
-            for (int c = 0; c < 3; ++c)
-                if (p[c] < a.lo[c] || p[c] > a.hi[c]) flags |= 1u;
-            bool fac[NX * NY], any = false, have = false;
-            float lg[NX * NY], dp[NX * NY], lw[NX * NY];
-            int nearest = -1, best = 1 << 30;
-            int d2r = 0;
-            float lgr = 0.f, pr[3] = {0.f, 0.f, 0.f}, dmin = __builtin_huge_valf();
-#pragma unroll
-            for (int k = 0; k < NX * NY; ++k) {
-                const int sx = X0S + k % NX, sy = Y0S + k / NX, si = sy * 3 + sx;
-                const int dx = 2 * (sx - 1) - I, dy = 2 * (sy - 1) - J, d2 = dx * dx + dy * dy;
-                const Sample &q = s[si];
-                if (q.usable && d2 < best) { best = d2; nearest = si; }
-                any |= q.usable;
-                const float cs = n[0] * q.n[0] + n[1] * q.n[1] + n[2] * q.n[2];
-                fac[k] = q.usable && cs > 0.0f;
-                lg[k] = fac[k] ? a.normal_power * __builtin_amdgcn_logf(cs) : 0.0f;
-                const float q0 = p[0] - q.p[0], q1 = p[1] - q.p[1], q2 = p[2] - q.p[2];
-                dp[k] = q0 * q0 + q1 * q1 + q2 * q2;
-                // reference: the facing sample nearest in position
-                const bool take = fac[k] && (!have || dp[k] < dmin);
-                dmin = take ? dp[k] : dmin;
-                d2r = take ? d2 : d2r;
-                lgr = take ? lg[k] : lgr;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) pr[c] = take ? q.p[c] : pr[c];
-                have |= fac[k];
-            }
-            if (have) {
-                // log2 weights relative to the reference r; the position term as
-                // |p - p_k|^2 - |p - p_r|^2 = (p_r - p_k) . ((p - p_k) + (p - p_r)),
-                // which keeps its precision however far the pixel is from the samples
-                float lmax = -__builtin_huge_valf();
-#pragma unroll
-                for (int k = 0; k < NX * NY; ++k) {
-                    const int sx = X0S + k % NX, sy = Y0S + k / NX;
-                    const int dx = 2 * (sx - 1) - I, dy = 2 * (sy - 1) - J, d2 = dx * dx + dy * dy;
-                    const Sample &q = s[sy * 3 + sx];
-                    float dd = 0.f;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        dd = __builtin_fmaf(pr[c] - q.p[c], (p[c] - q.p[c]) + (p[c] - pr[c]), dd);
-                    lw[k] = (lg[k] - lgr) - (float)(d2 - d2r) * a.c_px - dd * a.c_pos;
-                    if (fac[k]) lmax = fmaxf(lmax, lw[k]);
-                }
-                float ws = 0.f, acc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                for (int k = 0; k < NX * NY; ++k) {
-                    const int sx = X0S + k % NX, sy = Y0S + k / NX;
-                    const Sample &q = s[sy * 3 + sx];
-                    const float w = fac[k] ? __builtin_amdgcn_exp2f(lw[k] - lmax) : 0.0f;
-                    ws += w;
-                    acc[0] = __builtin_fmaf(w, q.e[0], acc[0]);
-                    acc[1] = __builtin_fmaf(w, q.e[1], acc[1]);
-                    acc[2] = __builtin_fmaf(w, q.e[2], acc[2]);
-                }
-                const float r = __builtin_amdgcn_rcpf(ws);
-                E[0] = acc[0] * r; E[1] = acc[1] * r; E[2] = acc[2] * r;
-            } else if (any) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    if (k == nearest) { E[0] = s[k].e[0]; E[1] = s[k].e[1]; E[2] = s[k].e[2]; }
-                flags |= 32u;
-            } else {
-                flags |= 64u;
-            }
-        }
+    if (!on) return;
+    float n[3];
+    const bool nok = unit_normal(nr, n);
+    if (!(finite3(p) && finite3(nr) && nok)) {
+        flags = 2u;
+        return;
     }
+    for (int c = 0; c < 3; ++c)
+        if (p[c] < a.lo[c] || p[c] > a.hi[c]) flags |= 1u;
+    // pass 1: which samples face this pixel, the log2 normal term, the
+    // nearest usable sample in pixels and the facing sample nearest in
+    // position (the reference of the log-weights)
+    bool fac[N];
+    float lg[N];
+    int nearest = -1, best = 1 << 30, ref = -1;
+    float dmin = __builtin_huge_valf();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int sx = I + k % NX, sy = J + k / NX, si = base + sy * kSX + sx;
+        const int dx = 2 * (sx - 1) - I, dy = 2 * (sy - 1) - J, d2 = dx * dx + dy * dy;
+        const bool use = S.u[si] != 0.0f;
+        if (use && d2 < best) { best = d2; nearest = si; }
+        const float cs = n[0] * S.nx[si] + n[1] * S.ny[si] + n[2] * S.nz[si];
+        fac[k] = use && cs > 0.0f;
+        lg[k] = fac[k] ? a.normal_power * __builtin_amdgcn_logf(cs) : 0.0f;
+        const float q0 = p[0] - S.px[si], q1 = p[1] - S.py[si], q2 = p[2] - S.pz[si];
+        const float dp2 = q0 * q0 + q1 * q1 + q2 * q2;
+        const bool take = fac[k] && (ref < 0 || dp2 < dmin);
+        dmin = take ? dp2 : dmin;
+        ref = take ? k : ref;
+    }
+    if (ref < 0) {
+        if (nearest >= 0) {
+            E[0] = S.ex[nearest]; E[1] = S.ey[nearest]; E[2] = S.ez[nearest];
+            flags |= 32u;
+        } else {
+            flags |= 64u;
+        }
+        return;
+    }
+    // the reference's values (a runtime slot: selected, not indexed)
+    float lgr = 0.f, pr[3] = {0.f, 0.f, 0.f};
+    int d2r = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int sx = I + k % NX, sy = J + k / NX, si = base + sy * kSX + sx;
+        const int dx = 2 * (sx - 1) - I, dy = 2 * (sy - 1) - J, d2 = dx * dx + dy * dy;
+        if (k == ref) { lgr = lg[k]; d2r = d2; pr[0] = S.px[si]; pr[1] = S.py[si]; pr[2] = S.pz[si]; }
+    }
+    // pass 2: log2 weights relative to the reference; the position term as
+    // |p - p_k|^2 - |p - p_r|^2 = (p_r - p_k) . ((p - p_k) + (p - p_r)),
+    // which keeps its precision however far the pixel is from the samples
+    float lw[N], lmax = -__builtin_huge_valf();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int sx = I + k % NX, sy = J + k / NX, si = base + sy * kSX + sx;
+        const int dx = 2 * (sx - 1) - I, dy = 2 * (sy - 1) - J, d2 = dx * dx + dy * dy;
+        const float sp[3] = {S.px[si], S.py[si], S.pz[si]};
+        float dd = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            dd = __builtin_fmaf(pr[c] - sp[c], (p[c] - sp[c]) + (p[c] - pr[c]), dd);
+        lw[k] = (lg[k] - lgr) - (float)(d2 - d2r) * a.c_px - dd * a.c_pos;
+        if (fac[k]) lmax = fmaxf(lmax, lw[k]);
+    }
+    float ws = 0.f, acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int sx = I + k % NX, sy = J + k / NX, si = base + sy * kSX + sx;
+        const float w = fac[k] ? __builtin_amdgcn_exp2f(lw[k] - lmax) : 0.0f;
+        ws += w;
+        acc[0] = __builtin_fmaf(w, S.ex[si], acc[0]);
+        acc[1] = __builtin_fmaf(w, S.ey[si], acc[1]);
+        acc[2] = __builtin_fmaf(w, S.ez[si], acc[2]);
+    }
+    const float r = __builtin_amdgcn_rcpf(ws);
+    E[0] = acc[0] * r; E[1] = acc[1] * r; E[2] = acc[2] * r;
 }
 }  // namespace
 
-// One lane per 2 x 2 pixel quad (2qx + i, 2qy + j): the union of its four
-// windows is the 3 x 3 samples qx - 1 .. qx + 1, qy - 1 .. qy + 1, loaded
-// once (neighbouring lanes' pixels, through the caches); each pixel then
-// visits exactly its own 9, 6, 6 or 4 samples.
+// One lane per 2 x 2 pixel quad (2qx + i, 2qy + j).  The workgroup first
+// stages every sample its quads can reach in LDS (loaded once, coalesced),
+// then each pixel visits exactly its own 9, 6, 6 or 4 samples there.
 __global__ __launch_bounds__(kQuadsX * kQuadsY) void k_upsample(const UpsampleArgs a)
 {
-    const int qx = blockIdx.x * kQuadsX + (int)(threadIdx.x % kQuadsX);
-    const int qy = blockIdx.y * kQuadsY + (int)(threadIdx.x / kQuadsX);
-    if (qx >= a.half_w || qy >= a.half_h) return;
-    // the 3 x 3 samples: loads at clamped coordinates, all issued before any
-    // test, then validity by selects
-    Sample s[9];
-    float mk[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int x = qx - 1 + k % 3, y = qy - 1 + k / 3;
-        const int xc = x < 0 ? 0 : (x >= a.half_w ? a.half_w - 1 : x);
-        const int yc = y < 0 ? 0 : (y >= a.half_h ? a.half_h - 1 : y);
-        const int64_t i = (int64_t)(2 * yc) * a.width + 2 * xc;
-        const int64_t h = (int64_t)yc * a.half_w + xc;
-        Sample &q = s[k];
-        for (int c = 0; c < 3; ++c) {
-            q.p[c] = a.pos[3 * i + c];
-            q.n[c] = a.nrm[3 * i + c];
-            q.e[c] = a.half_E[3 * h + c];
+    __shared__ Staged S;
+    const int qx0 = blockIdx.x * kQuadsX, qy0 = blockIdx.y * kQuadsY;
+    for (int t = threadIdx.x; t < kStaged; t += blockDim.x) {
+        const int x = qx0 - 1 + t % kSX, y = qy0 - 1 + t / kSX;
+        float e[3] = {0.f, 0.f, 0.f}, p[3] = {0.f, 0.f, 0.f}, n[3] = {0.f, 0.f, 0.f};
+        float use = 0.f;
+        if (x >= 0 && x < a.half_w && y >= 0 && y < a.half_h) {
+            const int64_t i = (int64_t)(2 * y) * a.width + 2 * x;
+            const int64_t h = (int64_t)y * a.half_w + x;
+            const bool on = a.mask ? a.mask[i] != 0 : true;
+            const float pp[3] = {a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2]};
+            const float nn[3] = {a.nrm[3 * i], a.nrm[3 * i + 1], a.nrm[3 * i + 2]};
+            const float ee[3] = {a.half_E[3 * h], a.half_E[3 * h + 1], a.half_E[3 * h + 2]};
+            const bool nok = unit_normal(nn, n);
+            if (on && finite3(pp) && finite3(nn) && nok) {
+                use = 1.f;
+                for (int c = 0; c < 3; ++c) { p[c] = pp[c]; e[c] = ee[c]; }
+            }
         }
-        mk[k] = (x == xc && y == yc && (a.mask ? a.mask[i] != 0 : true)) ? 1.0f : 0.0f;
+        S.ex[t] = e[0]; S.ey[t] = e[1]; S.ez[t] = e[2];
+        S.px[t] = p[0]; S.py[t] = p[1]; S.pz[t] = p[2];
+        S.nx[t] = n[0]; S.ny[t] = n[1]; S.nz[t] = n[2];
+        S.u[t] = use;
     }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        Sample &q = s[k];
-        const float raw[3] = {q.n[0], q.n[1], q.n[2]};
-        const bool nok = unit_normal(raw, q.n);
-        q.usable = mk[k] != 0.0f && finite3(q.p) && finite3(raw) && nok;
-    }
+    __syncthreads();
+    const int lx = (int)(threadIdx.x % kQuadsX), ly = (int)(threadIdx.x / kQuadsX);
+    const int qx = qx0 + lx, qy = qy0 + ly;
+    if (qx >= a.half_w || qy >= a.half_h) return;
+    const int base = ly * kSX + lx;   // staged sample (qx - 1, qy - 1)
     // per row of the quad: both pixels first, then their outputs stored
     // back to back (24 contiguous bytes of E and of L per lane)
     const int X = 2 * qx, Y = 2 * qy;
@@ -180,11 +189,11 @@ __global__ __launch_bounds__(kQuadsX * kQuadsY) void k_upsample(const UpsampleAr
         const bool onb = xin && (a.mask ? a.mask[pb] != 0 : true);
         float Ea[3], Eb[3] = {0.f, 0.f, 0.f};
         uint32_t fa, fb = 0;
-        if (j == 0) upsample_pixel<0, 0>(a, s, pa, ona, Ea, fa);
-        else upsample_pixel<0, 1>(a, s, pa, ona, Ea, fa);
+        if (j == 0) upsample_pixel<0, 0>(a, S, base, pa, ona, Ea, fa);
+        else upsample_pixel<0, 1>(a, S, base, pa, ona, Ea, fa);
         if (xin) {
-            if (j == 0) upsample_pixel<1, 0>(a, s, pb, onb, Eb, fb);
-            else upsample_pixel<1, 1>(a, s, pb, onb, Eb, fb);
+            if (j == 0) upsample_pixel<1, 0>(a, S, base, pb, onb, Eb, fb);
+            else upsample_pixel<1, 1>(a, S, base, pb, onb, Eb, fb);
         }
         float *oe = a.out_E + 3 * pa;
         oe[0] = Ea[0]; oe[1] = Ea[1]; oe[2] = Ea[2];
