@@ -11,7 +11,8 @@ with its error against the FP64 oracle.
 Also measured, as extra fields of the same JSON line:
   train       room_train: niv_train_step at B = 2^18 (FP16), the Monte Carlo
               targets (256 spp, 3 bounces, NEE) and the sampler, and the whole
-              baking step (samples/s);
+              baking step (samples/s); then a model baked on the GPU judged
+              against 4096-spp Monte Carlo on 2^16 held-out points;
   batched     batched_8_rooms: eight uneven G-buffers (16.3 M pixels), eight
               models, one persistent launch replayed from a HIP graph, after
               the autotuner; with and without the Monte Carlo fallback (64 spp);
@@ -303,19 +304,60 @@ def bench_train(args, dev):
         "valid_fraction": float(valid.float().mean().item()),
     }
     if not args.no_cpu:
-        # the estimator's oracle on a bounded sample: 64 points x 4096 spp
+        # the estimator's oracle on a bounded sample: 512 points x 4096 spp
         import oracle as O
-        xs, ns = x[:64].cpu().numpy(), n[:64].cpu().numpy()
+        xs, ns = x[:512].cpu().numpy(), n[:512].cpu().numpy()
         t0 = time.perf_counter()
         O.mc_irradiance(room["prims"], xs, ns, 4096, 3, O.MC_NEE, 5)
         cs = time.perf_counter() - t0
-        res["mc_cpu_oracle"] = {"points_per_s_at_256spp": 64 * 16 / cs, "s": cs,
-                                "sample": "64 points x 4096 spp, 3 bounces, NEE, FP64 on the "
+        res["mc_cpu_oracle"] = {"points_per_s_at_256spp": 512 * 16 / cs, "s": cs,
+                                "threads": os.cpu_count(),
+                                "sample": "512 points x 4096 spp, 3 bounces, NEE, FP64 on the "
                                           "host threads (points/s scaled to 256 spp)"}
-        log(f"[bench] MC oracle: 64 x 4096 spp in {cs:.2f} s")
+        log(f"[bench] MC oracle: 512 x 4096 spp in {cs:.2f} s")
     log(f"[bench] train: step {tt:.3f} ms ({B / (tt * 1e-3) / 1e6:.2f} M samples/s), "
         f"MC {mt:.1f} ms ({B / (mt * 1e-3) / 1e6:.3f} M points/s), bake step {et:.1f} ms")
     return res
+
+
+def bench_trained(args, dev, steps=2000, batch=1 << 16, spp=64):
+    """The on-GPU-trained model judged by the estimator: bake room_train for
+    `steps` steps, then held-out relative L2 against 4096-spp Monte Carlo on
+    2^16 points, next to Monte Carlo at 1 sample per point."""
+    import torch
+    from niv_synth import get_workload, make_params, make_room
+    from paper_2602_12949_amd import NIV
+    from paper_2602_12949_amd.bake import Baker, held_out_error
+    w = get_workload("room_train")
+    room = make_room(w.scene_seeds[0])
+    m = NIV(w.model_dict())
+    params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
+    bk = Baker(m, torch.from_numpy(params).to(dev), room["prims"], room["lo"], room["hi"],
+               prec="fp16", batch=batch, spp=spp, bounces=3, seed=11)
+    hx, hn = bk.scene.sample_points(room["lo"], room["hi"], 1 << 16, int(0.2 * (1 << 16)),
+                                    seed=3003)
+    Eh, _, _, vh = bk.scene.irradiance(hx, hn, 4096, 3, 1, 199)
+    Eh = Eh.float()
+    err0 = held_out_error(m, bk.trainer.model, "fp16", hx, hn, Eh, vh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bk.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err1 = held_out_error(m, bk.trainer.model, "fp16", hx, hn, Eh, vh)
+    qt, _ = time_steps(lambda: m.query(hx, hn, bk.trainer.model, "fp16"), 20, 3)
+    mt, _ = time_steps(lambda: bk.scene.irradiance(hx, hn, 1, 3, 1, 777), 5, 1)
+    E1, _, _, _ = bk.scene.irradiance(hx, hn, 1, 3, 1, 778)
+    v = vh.bool()
+    mc1 = float(torch.linalg.norm((E1.float() - Eh)[v]) / torch.linalg.norm(Eh[v]))
+    log(f"[bench] trained model: {steps} steps x {batch} at {spp} spp in {dt:.1f} s; held-out "
+        f"rel-L2 {err0[0]:.3f} -> {err1[0]:.3f}; query {qt:.3f} ms vs 1-spp MC {mt:.3f} ms "
+        f"(rel-L2 {mc1:.3f})")
+    return {"workload": f"room_train baked {steps} steps x {batch} points at {spp} spp (FP16), "
+                        "judged on 2^16 held-out points against 4096-spp Monte Carlo",
+            "bake_s": dt, "held_out_rel_l2_before": err0[0], "held_out_rel_l2": err1[0],
+            "held_out_relmse": err1[1], "valid_fraction": float(vh.float().mean().item()),
+            "query_ms": qt, "mc_1spp_ms": mt, "mc_1spp_rel_l2": mc1}
 
 
 def bench_batched(args, dev):
@@ -685,6 +727,7 @@ def main():
     extra = {}
     if "train" in parts:
         extra["train"] = bench_train(args, dev)
+        extra["trained_model"] = bench_trained(args, dev)
     if "batched" in parts:
         extra["batched"] = bench_batched(args, dev)
     if "field_4k" in parts:

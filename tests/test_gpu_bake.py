@@ -29,8 +29,9 @@ def test_bake_room_learns_irradiance():
                bounces=3, seed=7)
     # held-out points and a 1024-spp reference
     from paper_2602_12949_amd import McScene
-    hx, hn = bk.scene.sample_points(room["lo"], room["hi"], 4096, 819, seed=3003)
-    Eh, varh, bfh, vh = bk.scene.irradiance(hx, hn, 1024, 3, 1, 99)
+    # held out: 2^16 points against 4096-spp Monte Carlo
+    hx, hn = bk.scene.sample_points(room["lo"], room["hi"], 1 << 16, 13107, seed=3003)
+    Eh, varh, bfh, vh = bk.scene.irradiance(hx, hn, 4096, 3, 1, 99)
     Eh = Eh.float()
     err0 = held_out_error(niv, bk.trainer.model, "fp16", hx, hn, Eh, vh)
     t0 = time.perf_counter()
