@@ -320,20 +320,23 @@ __device__ inline void sincospi_half(float r, float &s, float &c)
 // floats): sin and cos of 2^b pi u for b < PB.  2^b u = th + tl exactly;
 // n = rint(th) and th - n are exact (Sterbenz), so r = (th - n) + tl is the
 // reduced argument with one rounding, and sin(pi (n + r)) = (-1)^n sin(pi r)
-// (the same for cos).  DOUBLING (for 16-bit operands): only every fourth
-// band is evaluated so; the three after it follow from the double-angle
-// formulas sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a, which at most
-// multiply the error of the evaluated band by 8 (about 1.3e-6, far below
-// the rounding of a 16-bit operand).
-template <int PB, bool DOUBLING>
+// (the same for cos).  EVERY (16-bit operands): only every EVERY-th band
+// is evaluated so; the bands after it follow from the double-angle formulas
+// sin 2a = 2 sin a cos a, cos 2a = (cos a - sin a)(cos a + sin a).  That
+// step is twice a rotation, so it doubles the error of the evaluated band
+// and no more (1 - 2 sin^2 a would multiply it by up to 4): EVERY = 4 (BF16,
+// whose hi + lo operands keep ~16 bits) ends below 2e-6, EVERY = 8 (FP16, 11
+// bits) below 3e-5, under the operand rounding either way.  EVERY = 1: all
+// bands evaluated.
+template <int PB, int EVERY>
 __device__ inline void pos_code_axis(float uh, float ul, float *sv, float *cv)
 {
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
-        if (DOUBLING && (b % 4) != 0) {
+        if ((b % EVERY) != 0) {
             const float s0 = sv[b - 1], c0 = cv[b - 1];
             sv[b] = 2.0f * (s0 * c0);
-            cv[b] = __builtin_fmaf(-2.0f * s0, s0, 1.0f);
+            cv[b] = (c0 - s0) * (c0 + s0);
             continue;
         }
         const float th = uh * (float)(1 << b), tl = ul * (float)(1 << b);

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 // positional code of the grid-free models (Sec. 4.1): u on the
                 // unit cube in FP64, split into two floats, then sin and cos
                 // of 2^k pi u with an exact argument reduction (16-bit
-                // operands: bands between evaluated ones by angle doubling)
+                // operands: the other bands by angle doubling)
                 float pe[S::PEW];
                 double ud[3];
 #pragma unroll
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     const float uh = (float)ud[c];
                     const float ul = (float)(ud[c] - (double)uh);
                     float sv[S::PB], cv[S::PB];
-                    pos_code_axis<S::PB, P != NIV_FP32>(uh, ul, sv, cv);
+                    pos_code_axis<S::PB, P == NIV_FP32 ? 1 : (P == NIV_FP16 ? 8 : 4)>(uh, ul, sv, cv);
 #pragma unroll
                     for (int b = 0; b < S::PB; ++b) {
                         pe[6 * b + c] = sv[b];
