@@ -429,76 +429,165 @@ struct ScatterArgs {
     double lo[3], hi[3];
 };
 
-// One wave handles one level for 64 samples (the level is wave-uniform, so
-// its constants are scalar loads); the work is strided identically in the
-// count and the write pass.
-template <bool WRITE>
-__global__ __launch_bounds__(256) void k_grid_bins(const ScatterArgs a)
+// Both passes: one wave takes a 64-sample chunk through every level (the
+// level is wave-uniform, so its constants are scalar loads), with the chunks
+// strided identically, so a workgroup writes exactly the records it counted.
+constexpr int kScatterWaves = 4;
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline bool scatter_sample(const ScatterArgs &a, int64_t q, double p[3])
+{
+    if (q >= a.n || !a.sflag[q]) return false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double v = a.x[3 * q + c];
+        p[c] = v < a.lo[c] ? a.lo[c] : (v > a.hi[c] ? a.hi[c] : v);
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_grid_count(const ScatterArgs a)
 {
     __shared__ uint32_t cnt[kMaxBins];
     typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int b = threadIdx.x; b < a.n_bins; b += 256)
-        cnt[b] = WRITE ? a.bin_start[b] + a.counts[(int64_t)b * kScatterBlocks + blockIdx.x] : 0u;
+    for (int b = threadIdx.x; b < a.n_bins; b += 256) cnt[b] = 0u;
     __syncthreads();
     const int64_t n_chunks = (a.n + 63) / 64;
-    const int64_t items = n_chunks * a.n_levels;
     ConstLevels lvs = (ConstLevels)a.model;
-    [[maybe_unused]] float vmax = 0.0f;
-    const int NF = 2 * a.n_levels;
-    for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < items; it += (int64_t)gridDim.x * 4) {
-        const int64_t chunk = it / a.n_levels;
-        const int l = (int)(it - chunk * a.n_levels);
-        const int64_t q = chunk * 64 + lane;
-        if (q >= a.n || !a.sflag[q]) continue;
+    for (int64_t chunk = (int64_t)blockIdx.x * kScatterWaves + wave; chunk < n_chunks;
+         chunk += (int64_t)gridDim.x * kScatterWaves) {
         double p[3];
+        if (!scatter_sample(a, chunk * 64 + lane, p)) continue;
+        for (int l = 0; l < a.n_levels; ++l) {
+            uint32_t idx[8];
+            float w[8];
+            level_corners(lvs[l], p, a.hash_mask, idx, w);
+            // corners in the bin of corner 0 (all of them on coarse levels)
+            // take one counter update together; the others one each
+            const uint32_t b0 = idx[0] >> kBinShift;
+            uint32_t n0 = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double v = a.x[3 * q + c];
-            p[c] = v < a.lo[c] ? a.lo[c] : (v > a.hi[c] ? a.hi[c] : v);
+            for (int c = 0; c < 8; ++c) n0 += (idx[c] >> kBinShift) == b0 ? 1u : 0u;
+            atomicAdd(&cnt[b0], n0);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if ((idx[c] >> kBinShift) != b0) atomicAdd(&cnt[idx[c] >> kBinShift], 1u);
         }
-        uint32_t idx[8];
-        float w[8];
-        level_corners(lvs[l], p, a.hash_mask, idx, w);
-        float g0 = 0.f, g1 = 0.f;
-        if constexpr (WRITE) {
-            g0 = a.dx0[q * NF + 2 * l] * a.loss_scale;
-            g1 = a.dx0[q * NF + 2 * l + 1] * a.loss_scale;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < a.n_bins; b += 256)
+        a.counts[(int64_t)b * kScatterBlocks + blockIdx.x] = cnt[b];
+}
+
+// Per-wave LDS of the write pass: the chunk's feature gradients as [64][L + 1]
+// float pairs (one pad pair per row spreads a level's column over the
+// banks), 512 staged records, and three 64-entry per-bin arrays.
+__host__ __device__ constexpr int write_wave_bytes(int n_levels)
+{
+    return 64 * (n_levels + 1) * 8 + 512 * 16 + 3 * 64 * 4;
+}
+
+// Write pass.  The chunk's feature gradients are read once, coalesced, into
+// LDS.  Per level, the wave orders its 512 records by bin in LDS: a histogram
+// over (a window of 64 of) the level's bins gives each record its rank in its
+// bin, one counter update per bin reserves the wave's run in the workgroup's
+// segment of that bin, and a scan of the histogram places the runs one after
+// the other.  The records are then stored in that order, so consecutive lanes
+// write consecutive slots of a bin's segment (runs of ~16 records on a hashed
+// level instead of single 4- and 8-byte stores).
+__global__ __launch_bounds__(256) void k_grid_write(const ScatterArgs a)
+{
+    __shared__ uint32_t cnt[kMaxBins];
+    extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
+    typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int L = a.n_levels;
+    uint8_t *mine = dyn + wave * write_wave_bytes(L);
+    float2 *gblk = reinterpret_cast<float2 *>(mine);
+    u4 *stage = reinterpret_cast<u4 *>(mine + 64 * (L + 1) * 8);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(mine + 64 * (L + 1) * 8 + 512 * 16);
+    uint32_t *bbase = hist + 64, *lstart = hist + 128;
+    for (int b = threadIdx.x; b < a.n_bins; b += 256)
+        cnt[b] = a.bin_start[b] + a.counts[(int64_t)b * kScatterBlocks + blockIdx.x];
+    __syncthreads();
+    const int64_t n_chunks = (a.n + 63) / 64;
+    ConstLevels lvs = (ConstLevels)a.model;
+    float vmax = 0.0f;
+    for (int64_t chunk = (int64_t)blockIdx.x * kScatterWaves + wave; chunk < n_chunks;
+         chunk += (int64_t)gridDim.x * kScatterWaves) {
+        const int64_t q0 = chunk * 64;
+        const int rows = (int)(a.n - q0 < 64 ? a.n - q0 : 64);
+        const float2 *src = reinterpret_cast<const float2 *>(a.dx0) + q0 * L;
+        for (int u = lane; u < rows * L; u += 64) {   // pair u = (sample u / L, level u % L)
+            const int r = u / L;
+            gblk[r * (L + 1) + (u - r * L)] = src[u];
         }
-        // corners in the bin of corner 0 (all of them on coarse levels) take
-        // one counter update together; the others one each
-        const uint32_t b0 = idx[0] >> kBinShift;
-        uint32_t n0 = 0;
+        double p[3] = {a.lo[0], a.lo[1], a.lo[2]};
+        const bool live = scatter_sample(a, q0 + lane, p);
+        wave_lds_sync();
+        for (int l = 0; l < L; ++l) {
+            uint32_t idx[8];
+            float w[8];
+            level_corners(lvs[l], p, a.hash_mask, idx, w);
+            const float2 gg = gblk[lane * (L + 1) + l];
+            const float g0 = gg.x * a.loss_scale, g1 = gg.y * a.loss_scale;
+            const uint32_t off = lvs[l].off;
+            const uint32_t size = lvs[l].dense ? lvs[l].s1 * lvs[l].s2 : a.hash_mask + 1u;
+            const uint32_t fb = off >> kBinShift;                  // first bin of the level
+            const uint32_t nlb = ((off + size - 1u) >> kBinShift) - fb + 1u;
+            for (uint32_t w0 = 0; w0 < nlb; w0 += 64) {
+                hist[lane] = 0u;
+                wave_lds_sync();
+                uint32_t rb[8], slot[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) n0 += (idx[c] >> kBinShift) == b0 ? 1u : 0u;
-        uint32_t pos0 = atomicAdd(&cnt[b0], n0);
+                for (int c = 0; c < 8; ++c) {
+                    rb[c] = (idx[c] >> kBinShift) - fb - w0;      // >= 64 (wrapped) outside the window
+                    slot[c] = (live && rb[c] < 64u) ? atomicAdd(&hist[rb[c]], 1u) : ~0u;
+                }
+                wave_lds_sync();
+                const uint32_t nb = hist[lane];
+                const uint32_t base = nb ? atomicAdd(&cnt[fb + w0 + lane], nb) : 0u;
+                uint32_t incl = nb;   // inclusive scan over the lanes
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const uint32_t b = idx[c] >> kBinShift;
-            uint32_t pos;
-            if (b == b0) pos = pos0++;
-            else pos = atomicAdd(&cnt[b], 1u);
-            if constexpr (WRITE) {
-                const float v0 = w[c] * g0, v1 = w[c] * g1;
-                a.keys[pos] = idx[c];
-                a.vals[pos] = make_float2(v0, v1);
-                vmax = fmaxf(vmax, fmaxf(fabsf(v0), fabsf(v1)));
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t t = __shfl_up(incl, d);
+                    if (lane >= d) incl += t;
+                }
+                const uint32_t total = __shfl(incl, 63);
+                bbase[lane] = base;
+                lstart[lane] = incl - nb;
+                wave_lds_sync();
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (slot[c] == ~0u) continue;
+                    const float v0 = w[c] * g0, v1 = w[c] * g1;
+                    stage[lstart[rb[c]] + slot[c]] = (u4){bbase[rb[c]] + slot[c], idx[c], f2u(v0), f2u(v1)};
+                    vmax = fmaxf(vmax, fmaxf(fabsf(v0), fabsf(v1)));
+                }
+                wave_lds_sync();
+                for (uint32_t k = lane; k < total; k += 64) {
+                    const u4 e = stage[k];
+                    a.keys[e.x] = e.y;
+                    a.vals[e.x] = make_float2(u2f(e.z), u2f(e.w));
+                }
+                wave_lds_sync();   // hist and stage are reused
             }
         }
     }
-    if constexpr (WRITE) {   // the step's largest |contribution|, for the fixed-point sums
-        __shared__ uint32_t smax;
-        if (threadIdx.x == 0) smax = 0u;
-        __syncthreads();
-        if (vmax == vmax) atomicMax(&smax, f2u(vmax));   // NaN contributions are left out
-        __syncthreads();
-        if (threadIdx.x == 0 && smax) atomicMax(a.vmax, smax);
-    }
-    if constexpr (!WRITE) {
-        __syncthreads();
-        for (int b = threadIdx.x; b < a.n_bins; b += 256)
-            a.counts[(int64_t)b * kScatterBlocks + blockIdx.x] = cnt[b];
-    }
+    // the step's largest |contribution|, for the fixed-point sums
+    __shared__ uint32_t smax;
+    if (threadIdx.x == 0) smax = 0u;
+    __syncthreads();
+    if (vmax == vmax) atomicMax(&smax, f2u(vmax));   // NaN contributions are left out
+    __syncthreads();
+    if (threadIdx.x == 0 && smax) atomicMax(a.vmax, smax);
 }
 
 // Per bin (one workgroup of kScatterBlocks threads): exclusive scan of the
@@ -816,11 +905,20 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.loss_scale = loss_scale;
     for (int c = 0; c < 3; ++c) { sa.lo[c] = a.lo[c]; sa.hi[c] = a.hi[c]; }
     if (sa.n_bins > kMaxBins) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_grid_bins<false>), dim3(kScatterBlocks), dim3(256), 0, stream, sa);
+    hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(256), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
     if ((e = launch_zero_u32(sa.vmax, 1, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_grid_bins<true>), dim3(kScatterBlocks), dim3(256), 0, stream, sa);
+    const int write_lds = kScatterWaves * write_wave_bytes(sa.n_levels);
+    static bool write_lds_set = false;   // dynamic LDS beyond 64 KB must be allowed per kernel
+    if (!write_lds_set) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_grid_write),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kScatterWaves * write_wave_bytes(kMaxLevels));
+        if (e != hipSuccess) return e;
+        write_lds_set = true;
+    }
+    hipLaunchKernelGGL(k_grid_write, dim3(kScatterBlocks), dim3(256), (size_t)write_lds, stream, sa);
     // an upper bound of the accumulating workgroups: one per bin plus one per
     // kAccumRecords records; the excess ones return at once
     const int64_t records = b.count * (int64_t)m.cfg.n_levels * 8;
