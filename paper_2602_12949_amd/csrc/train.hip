@@ -12,9 +12,9 @@
 //      MFMA (the gradient is transposed through LDS), the input gradients
 //      W_k^T G_{k+1} on MFMA with pre-permuted transposed weights so that
 //      they come out in the same lane layout as the forward activations;
-//      weight gradients accumulate in LDS per workgroup and are added to
-//      the global gradient once; the gradient of each sample's grid
-//      features is written out;
+//      weight gradients accumulate in LDS per workgroup, each workgroup
+//      writes its sum to a row of its own, and k_dw_sum adds the rows; the
+//      gradient of each sample's grid features is written out;
 //   3. the scatter of those feature gradients to the 8 corners of every
 //      level, without global atomics (device-scope atomics execute at the
 //      memory side of this part, ~22 G/s): the contributions are counted
@@ -58,8 +58,14 @@ template <int P, class S> struct Bwd {
     static constexpr int GB_BYTES = S::W * 64 * ES;            // gradient, [neuron][64]
     static constexpr int DX_BYTES = 64 * 2 * S::L * 4;         // grid-feature gradient, [64][2L]
     static constexpr int WB_BYTES = (GB_BYTES > DX_BYTES ? GB_BYTES : DX_BYTES) + 3 * 64 * 4;
-    static constexpr int DW_BYTES = (NMLP * 4 + 15) / 16 * 16;
+    // weight-gradient tiles (16x16, f4 per lane) a wave accumulates in registers
+    // over all its chunks: the output layer's, then layer H-1 down to 0
+    static constexpr int T_OUT = S::W / 16;
+    static constexpr int T_HID = NOB * NIB;
+    static constexpr int N_TILES = T_OUT + (S::H - 1) * T_HID + NOB * (S::DIN / 16);
+    static constexpr int tile_base(int k) { return T_OUT + (S::H - 1 - k) * T_HID; }
     static_assert(S::L % 8 == 0, "grid rows come in blocks of 16");
+    static_assert(S::DIN % 16 == 0, "input rows come in blocks of 16");
 };
 
 // Source parameter of element e of lane `lane` of backward operand `op`:
@@ -135,6 +141,7 @@ struct BwdArgs {
     const float *x;            // [n][3] sample positions
     const uint8_t *model;      // prepared model (level table first)
     float *grads;              // [n_params]
+    float *dw_part;            // [wave][weights] each wave's weight gradient
     float *dx0;                // [n][2L] gradient of each sample's grid features
     uint8_t *sflag;            // [n] 1: the sample's features scatter into the grid
     int64_t n, n_grid;
@@ -156,15 +163,16 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
 {
     using B = Bwd<P, S>;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    float *dW = reinterpret_cast<float *>(smem);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, j = lane & 15;
-    uint8_t *wbuf = smem + B::DW_BYTES + wave * B::WB_BYTES;
+    uint8_t *wbuf = smem + wave * B::WB_BYTES;
     float *debuf = reinterpret_cast<float *>(wbuf + (B::GB_BYTES > B::DX_BYTES ? B::GB_BYTES : B::DX_BYTES));
-    for (int k = threadIdx.x; k < B::NMLP; k += 256) dW[k] = 0.0f;
-    __syncthreads();
+    // the wave's weight gradient, summed over its chunks in the matrix-core
+    // accumulators (no LDS atomics per chunk)
+    f4 dwacc[B::N_TILES];
+#pragma unroll
+    for (int t = 0; t < B::N_TILES; ++t) dwacc[t] = (f4){0.f, 0.f, 0.f, 0.f};
 
-    typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
     const int64_t n_chunks = (a.n + 63) / 64;
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave; chunk < n_chunks; chunk += n_waves) {
@@ -183,34 +191,43 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
         const uint8_t *bw = a.bwd;
 
         // ---- output layer: dW_H[c][n] = sum_px dE[px][c] X_H[n][px]
+        // (the X_H operands are loaded together first: one memory latency)
         {
             const int xrow = S::DIN + (S::H - 1) * S::W;
-            const int woff = S::W * S::DIN + (S::H - 1) * S::W * S::W;
+            if constexpr (B::F32) {
+                const float *xf = reinterpret_cast<const float *>(xs);
+                float xv[S::W / 16][16];
 #pragma unroll
-            for (int nb = 0; nb < S::W / 16; ++nb) {
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
-                if constexpr (B::F32) {
-                    const float *xf = reinterpret_cast<const float *>(xs);
+                for (int nb = 0; nb < S::W / 16; ++nb)
+#pragma unroll
+                    for (int s = 0; s < 16; ++s) xv[nb][s] = xf[(xrow + 16 * nb + j) * 64 + 4 * s + g];
+#pragma unroll
+                for (int nb = 0; nb < S::W / 16; ++nb) {
+                    f4 acc = dwacc[nb];
 #pragma unroll
                     for (int s = 0; s < 16; ++s) {
                         const float av = j < 3 ? debuf[j * 64 + 4 * s + g] : 0.f;
-                        const float bv = xf[(xrow + 16 * nb + j) * 64 + 4 * s + g];
-                        acc = Prec<NIV_FP32>::mma1(av, bv, acc);
+                        acc = Prec<NIV_FP32>::mma1(av, xv[nb][s], acc);
                     }
-                } else {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        u4 av = {0u, 0u, 0u, 0u};
-                        if (j < 3) av = Mm<P>::h8(debuf + j * 64 + 32 * h + 8 * g);
-                        const u4 bv = *reinterpret_cast<const u4 *>(
-                            xs + ((int64_t)(xrow + 16 * nb + j) * 64 + 32 * h + 8 * g) * 2);
-                        acc = Prec<P>::mma(av, bv, acc);
-                    }
+                    dwacc[nb] = acc;
                 }
-                if (g == 0) {
-                    atomicAdd(&dW[woff + 0 * S::W + 16 * nb + j], acc.x);
-                    atomicAdd(&dW[woff + 1 * S::W + 16 * nb + j], acc.y);
-                    atomicAdd(&dW[woff + 2 * S::W + 16 * nb + j], acc.z);
+            } else {
+                u4 xv[S::W / 16][2];
+#pragma unroll
+                for (int nb = 0; nb < S::W / 16; ++nb)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        xv[nb][h] = *reinterpret_cast<const u4 *>(
+                            xs + ((int64_t)(xrow + 16 * nb + j) * 64 + 32 * h + 8 * g) * 2);
+                u4 av[2] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+                if (j < 3) {
+                    av[0] = Mm<P>::h8(debuf + j * 64 + 8 * g);
+                    av[1] = Mm<P>::h8(debuf + j * 64 + 32 + 8 * g);
+                }
+#pragma unroll
+                for (int nb = 0; nb < S::W / 16; ++nb) {
+                    dwacc[nb] = Prec<P>::mma(av[0], xv[nb][0], dwacc[nb]);
+                    dwacc[nb] = Prec<P>::mma(av[1], xv[nb][1], dwacc[nb]);
                 }
             }
         }
@@ -280,41 +297,54 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // dW_k += G X_k^T over the chunk's 64 samples
+            // dW_k += G X_k^T over the chunk's 64 samples; the X_k operands do
+            // not depend on the output block and are loaded together first
             constexpr int DK_MAX = S::DIN > S::W ? S::DIN : S::W;
             const int dk = (k == 0) ? S::DIN : S::W;
             const int xrow = (k == 0) ? 0 : S::DIN + (k - 1) * S::W;
-            const int woff = (k == 0) ? 0 : S::W * S::DIN + (k - 1) * S::W * S::W;
+            const int tb = B::tile_base(k);   // this layer's tiles: ob * (dk / 16) + ib
+            if constexpr (B::F32) {
+                const float *gb = reinterpret_cast<const float *>(wbuf);
+                const float *xf = reinterpret_cast<const float *>(xs);
+                float xv[DK_MAX / 16][16];
 #pragma unroll
-            for (int ob = 0; ob < B::NOB; ++ob)
+                for (int ib = 0; ib < DK_MAX / 16; ++ib)
 #pragma unroll
-                for (int ib = 0; ib < DK_MAX / 16; ++ib) {
-                    if (ib * 16 >= dk) break;
-                    f4 acc = {0.f, 0.f, 0.f, 0.f};
-                    if constexpr (B::F32) {
-                        const float *gb = reinterpret_cast<const float *>(wbuf);
-                        const float *xf = reinterpret_cast<const float *>(xs);
+                    for (int s = 0; s < 16; ++s)
+                        xv[ib][s] = ib * 16 < dk ? xf[(int64_t)(xrow + 16 * ib + j) * 64 + 4 * s + g] : 0.f;
 #pragma unroll
-                        for (int s = 0; s < 16; ++s) {
-                            const float av = gb[(16 * ob + j) * 64 + 4 * s + g];
-                            const float bv = xf[(int64_t)(xrow + 16 * ib + j) * 64 + 4 * s + g];
-                            acc = Prec<NIV_FP32>::mma1(av, bv, acc);
-                        }
-                    } else {
+                for (int ob = 0; ob < B::NOB; ++ob)
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const u4 av = *reinterpret_cast<const u4 *>(wbuf + ((16 * ob + j) * 64 + 32 * h + 8 * g) * 2);
-                            const u4 bv = *reinterpret_cast<const u4 *>(
-                                xs + ((int64_t)(xrow + 16 * ib + j) * 64 + 32 * h + 8 * g) * 2);
-                            acc = Prec<P>::mma(av, bv, acc);
-                        }
+                    for (int ib = 0; ib < DK_MAX / 16; ++ib) {
+                        if (ib * 16 >= dk) break;
+                        f4 acc = dwacc[tb + ob * (dk / 16) + ib];
+#pragma unroll
+                        for (int s = 0; s < 16; ++s)
+                            acc = Prec<NIV_FP32>::mma1(gb[(16 * ob + j) * 64 + 4 * s + g], xv[ib][s], acc);
+                        dwacc[tb + ob * (dk / 16) + ib] = acc;
                     }
-                    float *dst = dW + woff + (16 * ob + 4 * g) * dk + 16 * ib + j;
-                    atomicAdd(dst, acc.x);
-                    atomicAdd(dst + dk, acc.y);
-                    atomicAdd(dst + 2 * dk, acc.z);
-                    atomicAdd(dst + 3 * dk, acc.w);
+            } else {
+                u4 xv[DK_MAX / 16][2];
+#pragma unroll
+                for (int ib = 0; ib < DK_MAX / 16; ++ib)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        xv[ib][h] = ib * 16 < dk ? *reinterpret_cast<const u4 *>(
+                                        xs + ((int64_t)(xrow + 16 * ib + j) * 64 + 32 * h + 8 * g) * 2)
+                                                 : (u4){0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int ob = 0; ob < B::NOB; ++ob) {
+                    const u4 av0 = *reinterpret_cast<const u4 *>(wbuf + ((16 * ob + j) * 64 + 8 * g) * 2);
+                    const u4 av1 = *reinterpret_cast<const u4 *>(wbuf + ((16 * ob + j) * 64 + 32 + 8 * g) * 2);
+#pragma unroll
+                    for (int ib = 0; ib < DK_MAX / 16; ++ib) {
+                        if (ib * 16 >= dk) break;
+                        f4 &acc = dwacc[tb + ob * (dk / 16) + ib];
+                        acc = Prec<P>::mma(av0, xv[ib][0], acc);
+                        acc = Prec<P>::mma(av1, xv[ib][1], acc);
+                    }
                 }
+            }
             // d loss / d x_k = W_k^T G (grid rows only for k = 0)
             const int nib = (k == 0) ? B::GIB : B::NIB;
             const uint8_t *bk = (k == 0) ? bw + B::OUT_BYTES + (S::H - 1) * B::HID_BYTES
@@ -395,9 +425,53 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
             }
         }
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < B::NMLP; k += 256)
-        atomicAdd(&a.grads[a.n_grid + k], dW[k] * a.loss_scale);
+    // this wave's weight gradient to a row of its own; k_dw_sum adds the rows
+    // (no atomics, and a fixed summation order).  Tile element r of lane (g, j)
+    // is row 16 ob + 4 g + r, column 16 ib + j of the layer's matrix.
+    float *row = a.dw_part + ((int64_t)blockIdx.x * 4 + wave) * B::NMLP;
+    {
+        const int woff = S::W * S::DIN + (S::H - 1) * S::W * S::W;   // output layer [3][W]
+#pragma unroll
+        for (int nb = 0; nb < S::W / 16; ++nb)
+            if (g == 0) {
+                row[woff + 0 * S::W + 16 * nb + j] = dwacc[nb].x;
+                row[woff + 1 * S::W + 16 * nb + j] = dwacc[nb].y;
+                row[woff + 2 * S::W + 16 * nb + j] = dwacc[nb].z;
+            }
+    }
+#pragma unroll
+    for (int k = S::H - 1; k >= 0; --k) {
+        const int dk = (k == 0) ? S::DIN : S::W;
+        const int woff = (k == 0) ? 0 : S::W * S::DIN + (k - 1) * S::W * S::W;
+        const int tb = B::tile_base(k);
+#pragma unroll
+        for (int ob = 0; ob < B::NOB; ++ob)
+#pragma unroll
+            for (int ib = 0; ib < (S::DIN > S::W ? S::DIN : S::W) / 16; ++ib) {
+                if (ib * 16 >= dk) break;
+                const f4 v = dwacc[tb + ob * (dk / 16) + ib];
+                float *dst = row + woff + (16 * ob + 4 * g) * dk + 16 * ib + j;
+                dst[0] = v.x;
+                dst[dk] = v.y;
+                dst[2 * dk] = v.z;
+                dst[3 * dk] = v.w;
+            }
+    }
+}
+
+// Column sums of the per-workgroup weight gradients: rows r, r + Y, r + 2Y,
+// ... of column k are added into row r (Y = gridDim.y); with out given (and
+// Y = 1) the sum, scaled, is stored to the gradient instead.
+__global__ __launch_bounds__(256) void k_dw_sum(float *part, int64_t nmlp, int rows, float *out,
+                                               float scale)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nmlp) return;
+    const int r0 = blockIdx.y, step = gridDim.y;
+    float s = 0.0f;
+    for (int r = r0; r < rows; r += step) s += part[(int64_t)r * nmlp + k];
+    if (out) out[k] = s * scale;
+    else part[(int64_t)r0 * nmlp + k] = s;
 }
 
 // ---------------------------------------------------------------- grid scatter
@@ -406,6 +480,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
 constexpr int kBinShift = 12;                 // 4096 entries (32 KB of FP32 pairs) per bin
 constexpr int kBinEntries = 1 << kBinShift;
 constexpr int kMaxBins = 2048;
+constexpr int kBwdMaxBlocks = 512;            // workgroups of the backward (4 dW rows each)
 constexpr int kScatterBlocks = 1024;          // workgroups of the count and write passes
 constexpr int kAccumRecords = 98304;          // records one accumulating workgroup takes (1.5x a
                                               // hashed level's bin at 2^18 samples: those stay whole)
@@ -419,7 +494,7 @@ struct ScatterArgs {
     uint32_t *bin_start;       // [bins + 1]
     uint32_t *work_start;      // [bins + 1] first accumulating workgroup of each bin
     uint32_t *vmax;            // bits of the largest |contribution| of the step (>= 0 floats order as integers)
-    uint32_t *keys;            // [records] entry index
+    uint16_t *keys;            // [records] entry index within its bin
     float2 *vals;              // [records] contributions of the two features
     float *grads;              // grid part of the gradient: [entries][2]
     int64_t n, n_entries;
@@ -574,7 +649,7 @@ __global__ __launch_bounds__(256) void k_grid_write(const ScatterArgs a)
                 wave_lds_sync();
                 for (uint32_t k = lane; k < total; k += 64) {
                     const u4 e = stage[k];
-                    a.keys[e.x] = e.y;
+                    a.keys[e.x] = (uint16_t)(e.y & (kBinEntries - 1));
                     a.vals[e.x] = make_float2(u2f(e.z), u2f(e.w));
                 }
                 wave_lds_sync();   // hist and stage are reused
@@ -692,7 +767,6 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     const uint32_t b0 = a.bin_start[b], b1 = a.bin_start[b + 1];
     const uint32_t r0 = b0 + part * (uint32_t)kAccumRecords;
     const uint32_t r1 = parts == 1 ? b1 : (r0 + kAccumRecords < b1 ? r0 + kAccumRecords : b1);
-    const uint32_t base = (uint32_t)b << kBinShift;
     int e;
     (void)frexpf(u2f(*a.vmax), &e);            // M < 2^e (M = 0 gives e = 0: all terms are zero)
     const int sh = 62 - 17 - e;
@@ -705,7 +779,7 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
         float2 v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            i[k] = a.keys[r + k * 1024] - base;
+            i[k] = a.keys[r + k * 1024];
             v[k] = a.vals[r + k * 1024];
         }
 #pragma unroll
@@ -715,7 +789,7 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
         }
     }
     for (; r < r1; r += 1024) {
-        const uint32_t i = a.keys[r] - base;
+        const uint32_t i = a.keys[r];
         const float2 v = a.vals[r];
         atomicAdd(&acc[2 * i], fx(v.x));
         atomicAdd(&acc[2 * i + 1], fx(v.y));
@@ -753,7 +827,7 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, floa
 // ---------------------------------------------------------------- host side
 struct TrainLayout {
     int64_t bwd_off, x_off, mask_off, dE_off, dx0_off, sflag_off, counts_off, start_off, work_off,
-        vmax_off, keys_off, vals_off, total;
+        vmax_off, keys_off, vals_off, dw_off, total;
 };
 
 template <int P, class S> TrainLayout train_layout_t(int64_t n)
@@ -773,8 +847,9 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n)
     L.vmax_off = L.work_off + align256((kMaxBins + 1) * 4);
     L.keys_off = L.vmax_off + 256;
     const int64_t records = n * S::L * 8;
-    L.vals_off = L.keys_off + align256(records * 4);
-    L.total = L.vals_off + align256(records * 8);
+    L.vals_off = L.keys_off + align256(records * 2);
+    L.dw_off = L.vals_off + align256(records * 8);
+    L.total = L.dw_off + align256((int64_t)kBwdMaxBlocks * 4 * Bwd<P, S>::NMLP * 4);
     return L;
 }
 
@@ -853,6 +928,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     ba.model = static_cast<const uint8_t *>(st.model);
     const float loss_scale = (float)(1.0 / (3.0 * (double)b.count));
     ba.grads = st.grads;
+    ba.dw_part = reinterpret_cast<float *>(ws + L.dw_off);
     ba.dx0 = reinterpret_cast<float *>(ws + L.dx0_off);
     ba.sflag = ws + L.sflag_off;
     ba.n = b.count;
@@ -862,7 +938,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     for (int c = 0; c < 3; ++c) { ba.lo[c] = a.lo[c]; ba.hi[c] = a.hi[c]; }
     {
         auto kern = k_train_bwd<P, S>;
-        const size_t lds = B::DW_BYTES + 4 * (size_t)B::WB_BYTES;
+        const size_t lds = 4 * (size_t)B::WB_BYTES;
         static int max_blocks = -1, n_cu = 0;
         if (max_blocks < 0) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -880,7 +956,18 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
         const int64_t n_chunks = (b.count + 63) / 64;
         int64_t blocks = (n_chunks + 3) / 4;
         blocks = blocks < (int64_t)max_blocks * n_cu ? blocks : (int64_t)max_blocks * n_cu;
-        hipLaunchKernelGGL(kern, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), lds, stream, ba);
+        blocks = blocks < kBwdMaxBlocks ? blocks : kBwdMaxBlocks;
+        blocks = blocks < 1 ? 1 : blocks;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, stream, ba);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // weight gradient: the workgroups' rows summed in two passes
+        const unsigned cols = (unsigned)((B::NMLP + 255) / 256);
+        const int rows = (int)blocks * 4;   // one per wave
+        const int fold = 16;
+        hipLaunchKernelGGL(k_dw_sum, dim3(cols, (unsigned)fold), dim3(256), 0, stream, ba.dw_part,
+                           (int64_t)B::NMLP, rows, (float *)nullptr, 1.0f);
+        hipLaunchKernelGGL(k_dw_sum, dim3(cols, 1u), dim3(256), 0, stream, ba.dw_part, (int64_t)B::NMLP,
+                           fold, st.grads + m.n_grid_values, ba.loss_scale);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 3. grid scatter through bins
@@ -894,7 +981,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
     sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
     sa.vmax = reinterpret_cast<uint32_t *>(ws + L.vmax_off);
-    sa.keys = reinterpret_cast<uint32_t *>(ws + L.keys_off);
+    sa.keys = reinterpret_cast<uint16_t *>(ws + L.keys_off);
     sa.vals = reinterpret_cast<float2 *>(ws + L.vals_off);
     sa.grads = st.grads;
     sa.n = b.count;
