@@ -468,10 +468,16 @@ __global__ __launch_bounds__(256) void k_dw_sum(float *part, int64_t nmlp, int r
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= nmlp) return;
     const int r0 = blockIdx.y, step = gridDim.y;
-    float s = 0.0f;
-    for (int r = r0; r < rows; r += step) s += part[(int64_t)r * nmlp + k];
-    if (out) out[k] = s * scale;
-    else part[(int64_t)r0 * nmlp + k] = s;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // eight loads in flight
+    int r = r0;
+    for (; r + 7 * step < rows; r += 8 * step)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(r + u * step) * nmlp + k];
+    for (; r < rows; r += step) s[0] += part[(int64_t)r * nmlp + k];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) s[0] += s[u];
+    if (out) out[k] = s[0] * scale;
+    else part[(int64_t)r0 * nmlp + k] = s[0];
 }
 
 // ---------------------------------------------------------------- grid scatter
@@ -861,8 +867,10 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     using O = Ops<P, S>;
     TrainLayout L = train_layout_t<P, S>(b.count);
     uint8_t *ws = static_cast<uint8_t *>(st.workspace);
-    // zero the gradient and the loss (a kernel, so the step can be captured)
-    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, stream, st.grads, m.n_params);
+    if (m.n_params - m.n_grid_values != B::NMLP) return hipErrorInvalidValue;   // shape mismatch
+    // zero the grid part of the gradient (the MLP part is stored whole by
+    // k_dw_sum) and the loss, with kernels, so the step can be captured
+    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, stream, st.grads, m.n_grid_values);
     hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, stream, st.loss, (int64_t)1);
     hipLaunchKernelGGL((k_prepare_bwd<P, S>), dim3((B::N_OPS * 64 + 255) / 256), dim3(256), 0,
                        stream, st.params, ws + L.bwd_off, m.n_grid_values);
@@ -963,7 +971,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
         // weight gradient: the workgroups' rows summed in two passes
         const unsigned cols = (unsigned)((B::NMLP + 255) / 256);
         const int rows = (int)blocks * 4;   // one per wave
-        const int fold = 16;
+        const int fold = 32;
         hipLaunchKernelGGL(k_dw_sum, dim3(cols, (unsigned)fold), dim3(256), 0, stream, ba.dw_part,
                            (int64_t)B::NMLP, rows, (float *)nullptr, 1.0f);
         hipLaunchKernelGGL(k_dw_sum, dim3(cols, 1u), dim3(256), 0, stream, ba.dw_part, (int64_t)B::NMLP,
