@@ -487,7 +487,7 @@ constexpr int kBinShift = 12;                 // 4096 entries (32 KB of FP32 pai
 constexpr int kBinEntries = 1 << kBinShift;
 constexpr int kMaxBins = 2048;
 constexpr int kBwdMaxBlocks = 512;            // workgroups of the backward (4 dW rows each)
-constexpr int kScatterBlocks = 1024;          // workgroups of the count and write passes
+constexpr int kScatterBlocks = 256;           // workgroups of the count and write passes
 constexpr int kAccumRecords = 98304;          // records one accumulating workgroup takes (1.5x a
                                               // hashed level's bin at 2^18 samples: those stay whole)
 
@@ -513,7 +513,9 @@ struct ScatterArgs {
 // Both passes: one wave takes a 64-sample chunk through every level (the
 // level is wave-uniform, so its constants are scalar loads), with the chunks
 // strided identically, so a workgroup writes exactly the records it counted.
-constexpr int kScatterWaves = 4;
+constexpr int kScatterWaves = 8;
+constexpr int kScatterThreads = 64 * kScatterWaves;
+constexpr int kScatterMaxLevels = 16;          // levels of the trainable shapes (LDS of the write pass)
 
 __device__ inline void wave_lds_sync()
 {
@@ -533,12 +535,12 @@ __device__ inline bool scatter_sample(const ScatterArgs &a, int64_t q, double p[
     return true;
 }
 
-__global__ __launch_bounds__(256) void k_grid_count(const ScatterArgs a)
+__global__ __launch_bounds__(kScatterThreads) void k_grid_count(const ScatterArgs a)
 {
     __shared__ uint32_t cnt[kMaxBins];
     typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int b = threadIdx.x; b < a.n_bins; b += 256) cnt[b] = 0u;
+    for (int b = threadIdx.x; b < a.n_bins; b += kScatterThreads) cnt[b] = 0u;
     __syncthreads();
     const int64_t n_chunks = (a.n + 63) / 64;
     ConstLevels lvs = (ConstLevels)a.model;
@@ -563,7 +565,7 @@ __global__ __launch_bounds__(256) void k_grid_count(const ScatterArgs a)
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < a.n_bins; b += 256)
+    for (int b = threadIdx.x; b < a.n_bins; b += kScatterThreads)
         a.counts[(int64_t)b * kScatterBlocks + blockIdx.x] = cnt[b];
 }
 
@@ -583,7 +585,7 @@ __host__ __device__ constexpr int write_wave_bytes(int n_levels)
 // the other.  The records are then stored in that order, so consecutive lanes
 // write consecutive slots of a bin's segment (runs of ~16 records on a hashed
 // level instead of single 4- and 8-byte stores).
-__global__ __launch_bounds__(256) void k_grid_write(const ScatterArgs a)
+__global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArgs a)
 {
     __shared__ uint32_t cnt[kMaxBins];
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(256) void k_grid_write(const ScatterArgs a)
     u4 *stage = reinterpret_cast<u4 *>(mine + 64 * (L + 1) * 8);
     uint32_t *hist = reinterpret_cast<uint32_t *>(mine + 64 * (L + 1) * 8 + 512 * 16);
     uint32_t *bbase = hist + 64, *lstart = hist + 128;
-    for (int b = threadIdx.x; b < a.n_bins; b += 256)
+    for (int b = threadIdx.x; b < a.n_bins; b += kScatterThreads)
         cnt[b] = a.bin_start[b] + a.counts[(int64_t)b * kScatterBlocks + blockIdx.x];
     __syncthreads();
     const int64_t n_chunks = (a.n + 63) / 64;
@@ -1000,7 +1002,8 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.loss_scale = loss_scale;
     for (int c = 0; c < 3; ++c) { sa.lo[c] = a.lo[c]; sa.hi[c] = a.hi[c]; }
     if (sa.n_bins > kMaxBins) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(256), 0, stream, sa);
+    if (sa.n_levels > kScatterMaxLevels) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
     if ((e = launch_zero_u32(sa.vmax, 1, stream)) != hipSuccess) return e;
@@ -1009,11 +1012,12 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     if (!write_lds_set) {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_grid_write),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kScatterWaves * write_wave_bytes(kMaxLevels));
+                                kScatterWaves * write_wave_bytes(kScatterMaxLevels));
         if (e != hipSuccess) return e;
         write_lds_set = true;
     }
-    hipLaunchKernelGGL(k_grid_write, dim3(kScatterBlocks), dim3(256), (size_t)write_lds, stream, sa);
+    hipLaunchKernelGGL(k_grid_write, dim3(kScatterBlocks), dim3(kScatterThreads), (size_t)write_lds,
+                       stream, sa);
     // an upper bound of the accumulating workgroups: one per bin plus one per
     // kAccumRecords records; the excess ones return at once
     const int64_t records = b.count * (int64_t)m.cfg.n_levels * 8;
