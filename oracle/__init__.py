@@ -105,6 +105,9 @@ def lib():
         L.orc_upsample.restype = None
         L.orc_sample_points.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_int64,
                                         C.c_int64, C.c_uint64, fp, fp, fp]
+        L.orc_dynamic_ao.argtypes = [fp, C.c_int64, fp, fp, C.c_void_p, C.c_int64, C.c_int,
+                                     C.c_double, C.c_double, C.c_uint64, dp]
+        L.orc_dynamic_ao.restype = None
         _lib = L
     return _lib
 
@@ -308,6 +311,26 @@ def mc_irradiance(prims, x, nrm, spp, bounces, flags, seed, point_id=None, motio
                             _P(bf, C.c_int32), _P(vd, C.c_uint8), _P(mo, C.c_float),
                             _P(tv, C.c_float))
     return E, var, bf, vd
+
+
+def dynamic_ao(tris, pos, nrm, rays, radius, eps, seed, point_id=None):
+    """Dynamic ambient occlusion (Sec. 4.4): visibility of the hemisphere of
+    each point against the dynamic triangles [m,3,3] within `radius`, from
+    `rays` cosine-distributed directions of the point's stream (keyed by
+    point_id[i], default i).  Returns [n] visibilities in [0, 1]."""
+    tr = _f32(tris).reshape(-1, 9)
+    pos = _f32(pos).reshape(-1, 3)
+    nrm = _f32(nrm).reshape(-1, 3)
+    n = pos.shape[0]
+    ids = None
+    if point_id is not None:
+        ids = np.ascontiguousarray(point_id, dtype=np.uint64).reshape(-1)
+        assert ids.size == n
+    vis = np.zeros(n)
+    lib().orc_dynamic_ao(_P(tr, C.c_float), tr.shape[0], _P(pos, C.c_float), _P(nrm, C.c_float),
+                         None if ids is None else ids.ctypes.data, n, int(rays), float(radius),
+                         float(eps), int(seed), _P(vis, C.c_double))
+    return vis
 
 
 def sample_points(prims, lo, hi, count, n_surface, seed, with_t=False):

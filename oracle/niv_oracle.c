@@ -15,7 +15,9 @@
  *   - training: relative L2 loss with a stop-gradient denominator, Eq. 3;
  *     Adam with an exponentially decaying learning rate (Sec. 4.5);
  *   - targets: Monte Carlo estimates of the indirect part of Eq. 1 with
- *     back-face culling and null-irradiance rejection (Sec. 4.5, App. H).
+ *     back-face culling and null-irradiance rejection (Sec. 4.5, App. H);
+ *   - rendering: joint bilateral upsampling of a half-resolution query and
+ *     dynamic ambient occlusion from the dynamic geometry only (Sec. 4.4).
  * Readings of points the paper leaves open are listed next to the code that
  * takes them.
  *
@@ -1150,4 +1152,68 @@ void orc_upsample(const orc_config *c, int width, int height, const float *pos,
             }
             if (out_flags) out_flags[i] = (uint8_t)flags;
         }
+}
+
+/* ---------------------------------------------------------------- dynamic AO
+ * Dynamic ambient occlusion (Sec. 4.4): at a shading point only the dynamic
+ * geometry (triangles placed at render time) is tested for obstruction of
+ * the hemisphere.  Reading: the returned visibility is one minus the
+ * cosine-weighted fraction of directions whose ray from x + eps n meets a
+ * dynamic triangle at a distance in (0, radius]; triangles count from both
+ * sides.  It is estimated with `rays` cosine-distributed directions from the
+ * point's own random stream (stream 2, dimensions 0 and 1 of sample k), so
+ * the estimate is a deterministic function of (seed, point id).  The shaded
+ * irradiance is the model's E times this visibility. */
+
+/* Ray-triangle test (Moller and Trumbore, 1997): barycentric (u, v) and
+ * distance t from Cramer's rule on o + t d = v0 + u e1 + v e2. */
+static int orc_tri_hit(const double o[3], const double d[3], const float *tri, double tmax)
+{
+    double v0[3], e1[3], e2[3], p[3], s[3], q[3];
+    for (int a = 0; a < 3; ++a) {
+        v0[a] = tri[a];
+        e1[a] = (double)tri[3 + a] - v0[a];
+        e2[a] = (double)tri[6 + a] - v0[a];
+        s[a] = o[a] - v0[a];
+    }
+    p[0] = d[1] * e2[2] - d[2] * e2[1];
+    p[1] = d[2] * e2[0] - d[0] * e2[2];
+    p[2] = d[0] * e2[1] - d[1] * e2[0];
+    double det = e1[0] * p[0] + e1[1] * p[1] + e1[2] * p[2];
+    if (det == 0.0) return 0;                 /* ray parallel to the plane */
+    double u = (s[0] * p[0] + s[1] * p[1] + s[2] * p[2]) / det;
+    if (!(u >= 0.0 && u <= 1.0)) return 0;
+    q[0] = s[1] * e1[2] - s[2] * e1[1];
+    q[1] = s[2] * e1[0] - s[0] * e1[2];
+    q[2] = s[0] * e1[1] - s[1] * e1[0];
+    double v = (d[0] * q[0] + d[1] * q[1] + d[2] * q[2]) / det;
+    if (!(v >= 0.0 && u + v <= 1.0)) return 0;
+    double t = (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]) / det;
+    return t > 0.0 && t <= tmax;
+}
+
+void orc_dynamic_ao(const float *tris, int64_t n_tris, const float *pos, const float *nrm,
+                    const uint64_t *point_id, int64_t count, int rays, double radius, double eps,
+                    uint64_t seed, double *out_vis)
+{
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t i = 0; i < count; ++i) {
+        uint64_t pid = point_id ? point_id[i] : (uint64_t)i;
+        double n[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+        double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int a = 0; a < 3; ++a) n[a] /= ln;
+        double o[3];
+        for (int a = 0; a < 3; ++a) o[a] = (double)pos[3 * i + a] + eps * n[a];
+        int hits = 0;
+        for (int k = 0; k < rays; ++k) {
+            double d[3];
+            orc_cosine_dir(n, orc_uniform(seed, pid, (uint64_t)k, 2, 0),
+                           orc_uniform(seed, pid, (uint64_t)k, 2, 1), d);
+            for (int64_t j = 0; j < n_tris; ++j)
+                if (orc_tri_hit(o, d, tris + 9 * j, radius)) { ++hits; break; }
+        }
+        out_vis[i] = 1.0 - (double)hits / (double)rays;
+    }
 }
