@@ -17,7 +17,9 @@ Also measured, as extra fields of the same JSON line:
               models, one persistent launch replayed from a HIP graph, after
               the autotuner; with and without the Monte Carlo fallback (64 spp);
   field_4k    room_4k_6d: 3840x2160 G-buffer with two displaced icospheres,
-              scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16;
+              scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16; then the
+              dynamic ambient occlusion pass over the frame (Sec. 4.4: the
+              icospheres' 40,960 triangles, 16 rays per pixel within 1 m);
   table1      room_1080p_pe16/32/64: the same 1080p G-buffer under the
               grid-free models of Table 1 (eight-band positional code of x,
               three hidden layers of width 16, 32 or 64), FP16;
@@ -471,13 +473,54 @@ def bench_field_4k(args, dev):
         del graph
     ms = float(np.mean([v["ms"] for v in per_t.values()]))
     fl = mlp_flops(cfg) * n_valid
+    ao = bench_dynamic_ao(args, w, g, d, outs, s_near_seed=7)
     return {
         "workload": "room_4k_6d: 3840x2160 G-buffer, room + 2 displaced icospheres "
                     "(20,480 triangles each), 16 levels T=2^19, MLP 64-128^4-3, BF16",
         "pixels": len(mask), "valid_pixels": n_valid, "ms_per_frame": ms, "per_t": per_t,
         "mlp_tflops": fl / (ms * 1e-3) / 1e12,
         "mfma_frac": fl / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"],
+        "dynamic_ao": ao,
     }
+
+
+AO_RAYS, AO_RADIUS, AO_EPS = 16, 1.0, 1e-3
+
+
+def bench_dynamic_ao(args, w, g, d, outs, s_near_seed):
+    """Dynamic ambient occlusion (Sec. 4.4) over the frame's query output:
+    the two meshes' 40,960 triangles, 16 rays per pixel within 1 m; sampled
+    pixels near the meshes checked ray for ray against the oracle."""
+    import torch
+    import oracle as O
+    from niv_synth import workload_meshes, mesh_triangles
+    from paper_2602_12949_amd.niv import DynamicAO
+    meshes = workload_meshes(w)
+    tris = mesh_triangles(meshes)
+    ao = DynamicAO(tris)
+    pos, nrm, mask = d["pos"].reshape(-1, 3), d["nrm"].reshape(-1, 3), d["mask"].reshape(-1)
+    E, L = outs[0].reshape(-1, 3).clone(), outs[1].reshape(-1, 3).clone()
+    vis = ao.apply(pos, nrm, AO_RAYS, AO_RADIUS, AO_EPS, 23, mask=mask)
+    tt, tp = time_steps(lambda: ao.apply(pos, nrm, AO_RAYS, AO_RADIUS, AO_EPS, 23, mask=mask, E=E, L=L,
+                                         vis=vis), args.steps, args.warmup)
+    v = vis.cpu().numpy()
+    P, N, M = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3), g["mask"].reshape(-1)
+    near = np.zeros(len(P), bool)
+    for m in meshes:
+        near |= np.linalg.norm(P - m["center"][None, :], axis=1) <= m["radius"] + AO_RADIUS + 0.1
+    near = np.flatnonzero(near & (M > 0))
+    rng = np.random.default_rng(s_near_seed)
+    sel = np.sort(rng.choice(near, min(256, len(near)), replace=False))
+    ref = O.dynamic_ao(tris, P[sel], N[sel], AO_RAYS, AO_RADIUS, AO_EPS, 23, point_id=sel)
+    dh = np.abs(np.rint((1 - v[sel].astype(np.float64)) * AO_RAYS) - np.rint((1 - ref) * AO_RAYS))
+    nodes, depth = ao.info()
+    log(f"[bench] dynamic AO room_4k_6d: {tt:.4f} ms/frame ({AO_RAYS} rays, radius {AO_RADIUS} m, "
+        f"{len(near) / len(P):.3f} of the pixels within reach, {np.mean(v < 1):.3f} occluded; "
+        f"sampled pixels differing from the oracle {np.mean(dh > 0):.4f}, max |dhits| {dh.max():.0f})")
+    return {**stats(tt, tp), "rays": AO_RAYS, "radius_m": AO_RADIUS, "triangles": int(len(tris)),
+            "bvh_nodes": nodes, "bvh_depth": depth, "pixels_within_reach": float(len(near) / len(P)),
+            "occluded_fraction": float(np.mean(v < 1)), "sampled_pixels_differing": float(np.mean(dh > 0)),
+            "sampled_max_hit_difference": int(dh.max())}
 
 
 def bench_table1(args, dev):
@@ -659,9 +702,15 @@ def profile_case(case, steps, tune=None):
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         pm = m.prepare(t(params), "bf16")
         d = [t(g["pos"]), t(g["nrm"]), t(g["albedo"]), t(g["mask"])]
-        f, _ = m.frame(d[0], d[1], pm, albedo=d[2], mask=d[3], extra=(0.37,))
+        f, outs = m.frame(d[0], d[1], pm, albedo=d[2], mask=d[3], extra=(0.37,))
         for _ in range(2 * steps):
             m.query_frames([f], "bf16")
+        # then the dynamic ambient occlusion pass over the same frame
+        from niv_synth import workload_meshes, mesh_triangles
+        from paper_2602_12949_amd.niv import DynamicAO
+        ao = DynamicAO(mesh_triangles(workload_meshes(w)))
+        for _ in range(2 * steps):
+            ao.apply(d[0], d[1], AO_RAYS, AO_RADIUS, AO_EPS, 23, mask=d[3], E=outs[0], L=outs[1])
         torch.cuda.synchronize()
         log(f"[profile] {case}: done")
         return

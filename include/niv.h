@@ -388,6 +388,47 @@ niv_status mc_sample_points_t(const mc_scene *s, const double *lo, const double 
                               int64_t n_surface, uint64_t seed, float *out_x, float *out_n,
                               float *out_t, hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Dynamic ambient occlusion (Sec. 4.4).  A model trained on the static
+ * scene does not see geometry placed at render time; the shaded irradiance
+ * is multiplied by the visibility V of the hemisphere at each pixel against
+ * that dynamic geometry only: one minus the cosine-weighted share of
+ * directions whose ray from pos + eps n meets a dynamic triangle (either
+ * side) at a distance in (0, radius].  V is estimated from `rays` cosine-
+ * distributed directions: direction k of pixel i uses dimensions 0 and 1 of
+ * Philox4x64-10 with counter (i, k, 0, 2) and key (seed, 0), the directions
+ * mapped as mc_irradiance's first direction.  Ray tests in FP32.
+ * ------------------------------------------------------------------- */
+typedef struct niv_ao niv_ao;
+
+typedef struct {
+    int32_t rays;        /* 1..4096 directions per pixel */
+    float radius;        /* > 0: farther triangles do not occlude */
+    float eps;           /* >= 0: ray origin offset along the unit normal */
+    uint64_t seed;
+} niv_ao_params;
+
+/* Builds a bounding-volume hierarchy over `n_tris` (0..2^26) triangles
+ * `tris` [n_tris][3 vertices][3] float (host memory, finite) on the host and
+ * copies it to the device (owned by the returned object, released by
+ * niv_ao_destroy).  A new set of dynamic objects (or new placements) needs
+ * a new object. */
+niv_status niv_ao_create(const float *tris, int64_t n_tris, niv_ao **out);
+void niv_ao_destroy(niv_ao *ao);
+/* Inner nodes of the hierarchy (each record holds its two children's
+ * boxes) and its depth (root 0). */
+niv_status niv_ao_info(const niv_ao *ao, int32_t *n_nodes, int32_t *depth);
+
+/* For pixels i < count (device buffers): pos, nrm [count][3] float; mask
+ * [count] uint8 or NULL (0: pixel left alone, V = 1).  Outputs, each may be
+ * NULL: vis [count] float receives V; E and L [count][3] float are
+ * multiplied by V in place (the query's outputs of the same pixels).
+ * Pixels with a non-finite position or a zero normal get V = 1.  Enqueued
+ * on `stream`; nothing is allocated. */
+niv_status niv_ao_apply(const niv_ao *ao, const niv_ao_params *p, int64_t count, const float *pos,
+                        const float *nrm, const uint8_t *mask, float *E, float *L, float *vis,
+                        hipStream_t stream);
+
 const char *niv_status_string(niv_status s);
 
 #ifdef __cplusplus

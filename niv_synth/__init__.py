@@ -13,7 +13,7 @@ from .scene import (PRIM_DTYPE, PRIM_BOX, PRIM_RECT, PRIM_DISK, make_room,
                     room_prims, enclosure_prims, disk_prim, rect_prim, box_prim,
                     scene_bounds, room_motion)
 from .gbuffer import (Camera, default_camera, cast_gbuffer, make_room_gbuffer,
-                      make_workload_gbuffer)
+                      make_workload_gbuffer, workload_meshes, mesh_triangles)
 from .mesh import icosphere, displaced_sphere
 from .points import unit_cube_queries, uniform_unit_normals
 from .batch import make_room_gbuffers
@@ -25,4 +25,5 @@ __all__ = [
     "Camera", "default_camera", "cast_gbuffer", "make_room_gbuffer",
     "unit_cube_queries", "uniform_unit_normals", "make_room_gbuffers",
     "make_workload_gbuffer", "icosphere", "displaced_sphere", "room_motion",
+    "workload_meshes", "mesh_triangles",
 ]

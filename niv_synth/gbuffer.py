@@ -267,9 +267,22 @@ def make_room_gbuffer(seed: int, width: int, height: int, n_boxes: int = 32,
     return room, g
 
 
-def make_workload_gbuffer(w, frame: int = 0):
-    """Room + G-buffer of a workload's frame, with its dynamic meshes."""
+def workload_meshes(w):
+    """The dynamic meshes of a workload (displaced icospheres)."""
     from .mesh import displaced_sphere
-    meshes = [displaced_sphere(seed, centre) for seed, centre in w.meshes] or None
-    W, H = w.frames[frame]
+    return [displaced_sphere(seed, centre) for seed, centre in w.meshes]
+
+
+def mesh_triangles(meshes):
+    """All triangles of the meshes as one float32 array [m, 3, 3]."""
+    if not meshes:
+        return np.zeros((0, 3, 3), np.float32)
+    return np.concatenate([np.stack([m["v0"], m["v1"], m["v2"]], axis=1) for m in meshes]).astype(np.float32)
+
+
+def make_workload_gbuffer(w, frame: int = 0, size=None):
+    """Room + G-buffer of a workload's frame (or of `size` = (W, H) pixels of
+    the same scene and camera), with its dynamic meshes."""
+    meshes = workload_meshes(w) or None
+    W, H = size if size is not None else w.frames[frame]
     return make_room_gbuffer(w.scene_seeds[frame], W, H, meshes=meshes)

@@ -54,6 +54,10 @@ class UpsampleParams(C.Structure):
     _fields_ = [("sigma_px", C.c_float), ("sigma_pos", C.c_float), ("normal_power", C.c_int32)]
 
 
+class AoParams(C.Structure):
+    _fields_ = [("rays", C.c_int32), ("radius", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
 class Fallback(C.Structure):
     _fields_ = [("flag_mask", C.c_uint32), ("spp", C.c_int32), ("bounces", C.c_int32),
                 ("mc_flags", C.c_int32), ("seed", C.c_uint64)]
@@ -133,6 +137,11 @@ def lib():
         L.mc_irradiance_at.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                        C.c_uint64, vp, vp, vp, vp, vp, vp]
         L.mc_sample_points.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, C.c_uint64, vp, vp, vp]
+        L.niv_ao_create.argtypes = [vp, C.c_int64, C.POINTER(vp)]
+        L.niv_ao_destroy.argtypes = [vp]
+        L.niv_ao_destroy.restype = None
+        L.niv_ao_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.niv_ao_apply.argtypes = [vp, C.POINTER(AoParams), C.c_int64, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -371,6 +380,44 @@ class NIV:
                              want_flags=want_flags, out_inputs=inputs)
         self.query_frames([f], prec)
         return outs + (inputs,) if want_inputs else outs
+
+
+class DynamicAO:
+    """Dynamic ambient occlusion (Sec. 4.4): a hierarchy over the dynamic
+    triangles `tris` [m,3,3] (host array; niv_ao_create) and its pass over a
+    frame's pixels (niv_ao_apply)."""
+
+    def __init__(self, tris):
+        import numpy as np
+        t = np.ascontiguousarray(tris, dtype=np.float32).reshape(-1, 9)
+        h = C.c_void_p()
+        _check(lib().niv_ao_create(t.ctypes.data if t.size else None, t.shape[0], C.byref(h)),
+               "niv_ao_create")
+        self._h = h
+        self.n_tris = t.shape[0]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.niv_ao_destroy(h)
+            self._h = None
+
+    def info(self):
+        """(nodes, depth) of the hierarchy."""
+        n, d = C.c_int32(), C.c_int32()
+        _check(lib().niv_ao_info(self._h, C.byref(n), C.byref(d)), "niv_ao_info")
+        return n.value, d.value
+
+    def apply(self, pos, nrm, rays, radius, eps, seed, mask=None, E=None, L=None, vis=None):
+        """Visibility V of each pixel (returned, [n] float) and, in place, E and
+        L times V."""
+        n = pos.numel() // 3
+        if vis is None:
+            vis = torch.empty(n, dtype=torch.float32, device=pos.device)
+        p = AoParams(int(rays), float(radius), float(eps), int(seed))
+        _check(lib().niv_ao_apply(self._h, C.byref(p), n, _ptr(pos), _ptr(nrm), _ptr(mask), _ptr(E),
+                                  _ptr(L), _ptr(vis), _stream()), "niv_ao_apply")
+        return vis
 
 
 class McScene:

@@ -120,3 +120,28 @@ def test_grid_free_configs(niv):
     with pytest.raises(niv.NivError) as e:
         niv.NIV(dict(base, pos_bands=0))
     assert e.value.status == niv.NIV_ERR_INVALID_ARG
+
+
+def test_dynamic_ao_argument_checks(niv):
+    """niv_ao_create / niv_ao_apply reject bad input before touching the
+    device; an empty triangle set and an empty frame need no device work."""
+    lib = niv.lib()
+    h = C.c_void_p()
+    bad = np.zeros((1, 9), np.float32)
+    bad[0, 4] = np.nan
+    assert lib.niv_ao_create(bad.ctypes.data, 1, C.byref(h)) == niv.NIV_ERR_INVALID_ARG
+    assert lib.niv_ao_create(None, 3, C.byref(h)) == niv.NIV_ERR_INVALID_ARG
+    assert lib.niv_ao_create(None, -1, C.byref(h)) == niv.NIV_ERR_INVALID_ARG
+    assert lib.niv_ao_create(None, 0, C.byref(h)) == niv.NIV_OK and h.value
+    n, d = C.c_int32(-1), C.c_int32(-1)
+    assert lib.niv_ao_info(h, C.byref(n), C.byref(d)) == niv.NIV_OK and n.value == 0 and d.value == 0
+    for rays, radius, eps in [(0, 1.0, 0.0), (4097, 1.0, 0.0), (8, 0.0, 0.0), (8, float("inf"), 0.0),
+                              (8, 1.0, -1.0), (8, 1.0, float("nan"))]:
+        p = niv.AoParams(rays, radius, eps, 1)
+        assert lib.niv_ao_apply(h, C.byref(p), 1, None, None, None, None, None, None, None) == \
+            niv.NIV_ERR_INVALID_ARG, (rays, radius, eps)
+    p = niv.AoParams(8, 1.0, 0.0, 1)
+    assert lib.niv_ao_apply(h, C.byref(p), 0, None, None, None, None, None, None, None) == niv.NIV_OK
+    assert lib.niv_ao_apply(h, C.byref(p), 5, None, None, None, None, None, None, None) == \
+        niv.NIV_ERR_INVALID_ARG
+    lib.niv_ao_destroy(h)
