@@ -408,7 +408,7 @@ typedef struct {
     uint64_t seed;
 } niv_ao_params;
 
-/* Builds a bounding-volume hierarchy over `n_tris` (0..2^26) triangles
+/* Builds a bounding-volume hierarchy over `n_tris` (0..2^22) triangles
  * `tris` [n_tris][3 vertices][3] float (host memory, finite) on the host and
  * copies it to the device (owned by the returned object, released by
  * niv_ao_destroy).  A new set of dynamic objects (or new placements) needs
