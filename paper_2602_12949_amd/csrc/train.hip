@@ -31,6 +31,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "niv_internal.h"
 #include "niv_device.h"
 #include "query_kernel.h"
@@ -857,7 +859,10 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n)
     const int64_t records = n * S::L * 8;
     L.vals_off = L.keys_off + align256(records * 2);
     L.dw_off = L.vals_off + align256(records * 8);
-    L.total = L.dw_off + align256((int64_t)kBwdMaxBlocks * 4 * Bwd<P, S>::NMLP * 4);
+    // one weight-gradient row per backward wave: 4 per workgroup, at most
+    // one workgroup per 4 chunks and kBwdMaxBlocks in all
+    const int64_t bwd_blocks = std::min<int64_t>(kBwdMaxBlocks, std::max<int64_t>(1, (nc + 3) / 4));
+    L.total = L.dw_off + align256(bwd_blocks * 4 * Bwd<P, S>::NMLP * 4);
     return L;
 }
 
@@ -973,7 +978,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
         // weight gradient: the workgroups' rows summed in two passes
         const unsigned cols = (unsigned)((B::NMLP + 255) / 256);
         const int rows = (int)blocks * 4;   // one per wave
-        const int fold = 32;
+        const int fold = rows < 32 ? rows : 32;   // the first pass writes rows 0 .. fold-1
         hipLaunchKernelGGL(k_dw_sum, dim3(cols, (unsigned)fold), dim3(256), 0, stream, ba.dw_part,
                            (int64_t)B::NMLP, rows, (float *)nullptr, 1.0f);
         hipLaunchKernelGGL(k_dw_sum, dim3(cols, 1u), dim3(256), 0, stream, ba.dw_part, (int64_t)B::NMLP,
