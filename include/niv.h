@@ -35,7 +35,8 @@ typedef enum {
     NIV_ERR_UNSUPPORTED = 2,  /* valid model shape the kernels do not cover */
     NIV_ERR_HIP = 3,          /* a HIP runtime call failed */
     NIV_ERR_WORKSPACE = 4,    /* caller-provided scratch too small */
-    NIV_ERR_STATE = 5         /* call out of order (e.g. no prepared model) */
+    NIV_ERR_STATE = 5,        /* call out of order (e.g. no prepared model) */
+    NIV_ERR_NONFINITE = 6     /* a training step's loss or gradient was not finite */
 } niv_status;
 
 typedef enum { NIV_FP32 = 0, NIV_FP16 = 1, NIV_BF16 = 2 } niv_precision;
@@ -290,7 +291,13 @@ niv_status niv_train_sizes(const niv_handle *h, niv_precision prec, int64_t max_
  * channels of (E - y)^2 / (E^2 + 0.01), the denominator held constant; the
  * gradient of every parameter is written to st->grads (overwritten), the
  * loss to st->loss.  The forward pass uses st->model at `prec` (matrix
- * products on the matrix cores with FP32 accumulation); gradients are FP32. */
+ * products on the matrix cores with FP32 accumulation); gradients are FP32.
+ * The gradient does not depend on scheduling: weight gradients are summed
+ * in a fixed order, and each grid value is the sum of its contributions
+ * (the 8 trilinear corners of every level, Sec. 4.1) in 64-bit fixed point,
+ * converted to FP32 once.  A sample whose output or target gives a
+ * non-finite d loss / dE marks the step non-finite (niv_train_status) and
+ * contributes nothing to the grid. */
 niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state *st,
                         niv_precision prec, hipStream_t stream);
 
@@ -298,9 +305,35 @@ niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state
 niv_status niv_adam_update(niv_handle *h, const niv_train_state *st, const niv_adam *ad,
                            hipStream_t stream);
 
-/* niv_backward, niv_adam_update, then niv_prepare of st->model. */
+/* niv_backward, niv_adam_update, then niv_prepare of st->model.  When the
+ * step's loss or gradient is not finite the update is skipped on the device
+ * (parameters and moments unchanged) and niv_train_status reports it; the
+ * call itself stays asynchronous. */
 niv_status niv_train_step(niv_handle *h, const niv_batch *b, const niv_train_state *st,
                           const niv_adam *ad, niv_precision prec, hipStream_t stream);
+
+/* Waits for `stream`, then NIV_ERR_NONFINITE if the last niv_backward or
+ * niv_train_step on this scratch (st->workspace) met a non-finite loss or
+ * gradient (a diverged output or a non-finite target), else NIV_OK. */
+niv_status niv_train_status(const niv_train_state *st, hipStream_t stream);
+
+/* Learning rate of step `step` (1-based) of the schedule of Sec. 4.5: lr0
+ * for the first hold_steps steps, then exponential decay reaching lr1 at
+ * step total_steps (and lr1 after it).  The paper holds 1e-2 for 10k of its
+ * iterations and decays to 1e-4; the bake takes hold_steps = total / 5,
+ * that ratio at its own step budget.  Host only. */
+niv_status niv_lr_schedule(int64_t step, int64_t hold_steps, int64_t total_steps, double lr0,
+                           double lr1, double *lr);
+
+/* Seeded initial parameters (device, n_params floats, the layout of
+ * niv_sizes): grid values uniform on [grid_lo, grid_hi), weights of each
+ * matrix Xavier-uniform on [-a, a), a = sqrt(6 / (fan_in + fan_out)) (the
+ * paper does not state its initialisation; the cited hash encoding starts
+ * its table near zero).  Parameter k draws uniform number 0 of generator
+ * stream (seed, k, 0, 3) (Philox4x64-10 as in mc_irradiance), the value is
+ * formed in FP64 and rounded once to FP32.  Enqueued on `stream`. */
+niv_status niv_init_params(niv_handle *h, float *params, uint64_t seed, float grid_lo,
+                           float grid_hi, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Monte Carlo irradiance (training targets and reference)              */

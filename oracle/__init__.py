@@ -97,6 +97,8 @@ def lib():
                                      C.POINTER(C.c_uint64)]
         L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
         L.orc_uniform.restype = C.c_double
+        L.orc_init_params.argtypes = [cp, C.c_uint64, C.c_double, C.c_double, fp]
+        L.orc_init_params.restype = None
         L.orc_mc_irradiance.argtypes = [C.c_void_p, C.c_int, fp, fp, C.c_void_p, C.c_int64, C.c_int,
                                         C.c_int, C.c_int, C.c_uint64, dp, dp,
                                         C.POINTER(C.c_int32), u8p, fp, fp]
@@ -264,6 +266,14 @@ def adam(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_adam(params.size, _P(params, C.c_double), _P(grads, C.c_double),
                    _P(m, C.c_double), _P(v, C.c_double), lr, beta1, beta2, eps, step)
+
+
+def init_params(cfg: Config, seed, lo, hi):
+    """Seeded initial parameters: grid uniform on [lo, hi), weights
+    Xavier-uniform; parameter k from generator stream (seed, k, 0, 3)."""
+    out = np.empty(n_params(cfg), dtype=np.float32)
+    lib().orc_init_params(C.byref(cfg), int(seed), float(lo), float(hi), _P(out, C.c_float))
+    return out
 
 
 def lr_at(step, s1, s_end, lr0=1e-2, lr1=1e-4):

@@ -648,6 +648,36 @@ double orc_uniform(uint64_t seed, uint64_t a, uint64_t b, uint64_t stream, int d
     return (double)(u >> 8) * 0x1p-24;
 }
 
+/* Seeded initial parameters.  The paper does not state its initialisation;
+ * reading: grid values uniform on [lo, hi) (the cited hash encoding starts
+ * its table near zero), weights Xavier-uniform (Glorot and Bengio, 2010):
+ * uniform on [-a, a) with a = sqrt(6 / (fan_in + fan_out)) per matrix.
+ * Parameter k draws uniform number 0 of generator stream (seed, k, 0, 3);
+ * the value is formed in double precision and rounded once to float. */
+void orc_init_params(const orc_config *c, uint64_t seed, double lo, double hi, float *out)
+{
+    int64_t n_grid = orc_n_grid_values(c);
+    int64_t n = orc_n_params(c);
+    int n_mats = c->n_hidden + 1;
+    int64_t k = 0;
+    for (; k < n_grid; ++k) {
+        double u = orc_uniform(seed, (uint64_t)k, 0, 3, 0);
+        out[k] = (float)fma(hi - lo, u, lo);
+    }
+    for (int m = 0; m < n_mats; ++m) {
+        int64_t fan_in = m == 0 ? orc_input_dim(c) : c->width;
+        int64_t fan_out = m == n_mats - 1 ? c->n_out : c->width;
+        double a = sqrt(6.0 / (double)(fan_in + fan_out));
+        for (int64_t e = 0; e < fan_in * fan_out; ++e, ++k) {
+            double u = orc_uniform(seed, (uint64_t)k, 0, 3, 0);
+            double t = 2.0 * u;
+            t = t - 1.0;
+            out[k] = (float)(a * t);
+        }
+    }
+    (void)n;
+}
+
 /* ------------------------------------------------------------------ */
 /* Scenes and ray casting                                                */
 /* ------------------------------------------------------------------ */

@@ -11,21 +11,16 @@ random; its target is estimated in the scene at that t and t is the
 network's extra input.  This module only sequences library calls;
 every step runs in the library's kernels.
 """
-import math
-
 import torch
 
-from .niv import McScene, Trainer, MC_NEE
+from .niv import McScene, Trainer, MC_NEE, lr_schedule
 
 
-def lr_at(step, total, lr0=1e-2, lr1=1e-4, hold=0.2):
-    """lr0 for the first `hold` fraction of the steps, then exponential decay
-    reaching lr1 at the last step."""
-    s1 = int(hold * total)
-    if step <= s1 or total <= s1:
-        return lr0
-    t = min(1.0, (step - s1) / (total - s1))
-    return lr0 * (lr1 / lr0) ** t
+def lr_at(step, total, lr0=1e-2, lr1=1e-4):
+    """The library's Sec. 4.5 schedule (niv_lr_schedule): lr0 held for the
+    first fifth of the steps (the paper's 10k of its 50k iterations), then
+    exponential decay reaching lr1 at the last step."""
+    return lr_schedule(step, total // 5, total, lr0, lr1)
 
 
 class Baker:

@@ -1,7 +1,8 @@
 // C interface of libniv: argument checking, model tables, launches.
 #include <math.h>
-#include <new>
 #include <string.h>
+
+#include <new>
 
 #include "niv_internal.h"
 
@@ -326,22 +327,12 @@ niv_status niv_fallback_sizes(const niv_handle *h, int64_t max_flagged, int64_t 
     return NIV_OK;
 }
 
-niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_frames,
-                              niv_precision prec, const niv_fallback *fb, void *workspace,
-                              int64_t workspace_bytes, hipStream_t stream)
+// niv_query_fallback with its scratch given as the counter and the list of
+// `cap` entries.
+static niv_status query_fallback_into(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                                      niv_precision prec, const niv_fallback *fb, uint32_t *cnt,
+                                      uint32_t *list, uint32_t cap, hipStream_t stream)
 {
-    niv_status s = check_frames(h, frames, n_frames, prec);
-    if (s != NIV_OK) return s;
-    if (n_frames > kMaxFrames) return NIV_ERR_INVALID_ARG;
-    if (!fb || !workspace || !aligned(workspace, 256)) return NIV_ERR_INVALID_ARG;
-    if (workspace_bytes < 256 + 4) return NIV_ERR_WORKSPACE;
-    if (fb->spp < 1 || fb->bounces < 0 || fb->bounces > 16 || (fb->mc_flags & ~15) ||
-        ((fb->mc_flags & 1) && (fb->mc_flags & 2)) || (fb->flag_mask & ~21u))
-        return NIV_ERR_INVALID_ARG;
-    uint32_t *cnt = static_cast<uint32_t *>(workspace);
-    uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(workspace) + 256);
-    const int64_t cap64 = (workspace_bytes - 256) / 4;
-    const uint32_t cap = (uint32_t)(cap64 < 0x7fffffff ? cap64 : 0x7fffffff);
     // the counter is cleared by a kernel so that the whole call can be captured in a graph
     if (launch_zero_u32(cnt, 1, stream) != hipSuccess) return NIV_ERR_HIP;
     QueryArgs a;
@@ -375,6 +366,33 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
         d.t = fr.extra_values[0];
     }
     return launch_mc_fallback(b, stream) == hipSuccess ? NIV_OK : NIV_ERR_HIP;
+}
+
+static niv_status check_fallback(const niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                                 niv_precision prec, const niv_fallback *fb)
+{
+    niv_status s = check_frames(h, frames, n_frames, prec);
+    if (s != NIV_OK) return s;
+    if (n_frames > kMaxFrames || !fb) return NIV_ERR_INVALID_ARG;
+    if (fb->spp < 1 || fb->bounces < 0 || fb->bounces > 16 || (fb->mc_flags & ~15) ||
+        ((fb->mc_flags & 1) && (fb->mc_flags & 2)) || (fb->flag_mask & ~21u))
+        return NIV_ERR_INVALID_ARG;
+    return NIV_OK;
+}
+
+niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                              niv_precision prec, const niv_fallback *fb, void *workspace,
+                              int64_t workspace_bytes, hipStream_t stream)
+{
+    niv_status s = check_fallback(h, frames, n_frames, prec, fb);
+    if (s != NIV_OK) return s;
+    if (!workspace || !aligned(workspace, 256)) return NIV_ERR_INVALID_ARG;
+    if (workspace_bytes < 256 + 4) return NIV_ERR_WORKSPACE;
+    uint32_t *cnt = static_cast<uint32_t *>(workspace);
+    uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(workspace) + 256);
+    const int64_t cap64 = (workspace_bytes - 256) / 4;
+    const uint32_t cap = (uint32_t)(cap64 < 0x7fffffff ? cap64 : 0x7fffffff);
+    return query_fallback_into(h, frames, n_frames, prec, fb, cnt, list, cap, stream);
 }
 
 niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames,
@@ -520,6 +538,7 @@ const char *niv_status_string(niv_status s)
     case NIV_ERR_HIP: return "HIP runtime error";
     case NIV_ERR_WORKSPACE: return "workspace too small";
     case NIV_ERR_STATE: return "call out of order";
+    case NIV_ERR_NONFINITE: return "the training step's loss or gradient was not finite (update skipped)";
     }
     return "unknown status";
 }

@@ -74,6 +74,7 @@ struct QueryArgs {
     uint32_t *mask_save;      // ReLU masks, per chunk, layer, dword, lane
     float *dE;                // [count][3] d(loss)/dE without the 1/(3n) factor
     float *loss;              // device scalar, accumulates the Eq. 3 loss
+    uint32_t *train_status;   // step words of the training scratch; [2] set by a non-finite dE
     float loss_eps;           // 0.01 (Eq. 3)
     int32_t xcd_order;        // tile order, see LaunchTune
     FrameArgs f[kMaxFrames];

@@ -722,6 +722,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         if constexpr (TRAIN) {
             // Eq. 3: (E - y)^2 / (sg(E^2) + eps); d/dE = 2 (E - y) / (E^2 + eps)
             float lsum = 0.0f;
+            bool nonfinite = false;
             if (live) {
                 const float Ev[3] = {acc_out.x, acc_out.y, acc_out.z};
 #pragma unroll
@@ -732,10 +733,13 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                         const float den = Ev[c] * Ev[c] + a.loss_eps;
                         d = 2.0f * r / den;
                         lsum += r * r / den;
+                        nonfinite |= !__builtin_isfinite(d);
                     }
                     a.dE[3 * q + c] = d;
                 }
             }
+            // a diverged output or a non-finite target marks the whole step
+            if (__ballot(nonfinite) != 0ull && lane == 0) atomicOr(a.train_status + 2, 1u);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off);
             if (lane == 0) atomicAdd(a.loss, lsum * a.loss_scale);

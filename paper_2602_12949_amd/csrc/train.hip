@@ -20,9 +20,11 @@
 //      memory side of this part, ~22 G/s): the contributions are counted
 //      per bin of 4096 grid entries and workgroup (k_grid_count), the
 //      counts are scanned (k_grid_scan_bins, k_grid_scan_totals), the
-//      contributions are written bin by bin (k_grid_write), and one
-//      workgroup per bin sums its contributions in LDS and stores the bin's
-//      gradient (k_grid_accum);
+//      contributions are written bin by bin (k_grid_write), and one or more
+//      workgroups per bin sum their contributions in LDS in 64-bit fixed
+//      point (k_grid_accum); a bin split over several workgroups has its
+//      integer partial sums added in a fixed order (k_grid_merge), so the
+//      whole grid gradient is independent of scheduling;
 //   4. k_adam over all parameters, then the prepared model is rebuilt.
 // Gradients are carried unscaled through the network and multiplied by
 // 1/(3n) when they are added to the gradient buffer, so FP16 operands do not
@@ -35,9 +37,12 @@
 
 #include "niv_internal.h"
 #include "niv_device.h"
+#include "mc_device.h"
 #include "query_kernel.h"
 
 namespace niv {
+
+constexpr int kMaxMats = 12;   // weight matrices of a model (n_hidden + 1) niv_init_params takes
 
 // ---------------------------------------------------------------- layouts
 template <int P, class S> struct Bwd {
@@ -413,7 +418,11 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            bool scatter = live && (dEl[0] != 0.f || dEl[1] != 0.f || dEl[2] != 0.f);
+            // a sample scatters when its dE is finite and not zero (a non-finite
+            // dE marks the step non-finite in the forward and never reaches the grid)
+            bool scatter = live && (dEl[0] != 0.f || dEl[1] != 0.f || dEl[2] != 0.f) &&
+                           __builtin_isfinite(dEl[0]) && __builtin_isfinite(dEl[1]) &&
+                           __builtin_isfinite(dEl[2]);
             if (scatter) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) scatter &= __builtin_isfinite(a.x[3 * q + c]);
@@ -493,6 +502,12 @@ constexpr int kScatterBlocks = 256;           // workgroups of the count and wri
 constexpr int kAccumRecords = 98304;          // records one accumulating workgroup takes (1.5x a
                                               // hashed level's bin at 2^18 samples: those stay whole)
 
+// The first 256 bytes of the training scratch hold the step's words: [0]
+// largest |grid contribution| (float bits), [1] records of the fullest bin,
+// [2] non-zero when the step's loss or gradient was not finite (set by the
+// forward pass; the Adam update of niv_train_step then does nothing).
+constexpr int kStatusWords = 4;
+
 struct ScatterArgs {
     const float *x;            // [n][3] sample positions
     const float *dx0;          // [n][2L]
@@ -501,7 +516,9 @@ struct ScatterArgs {
     uint32_t *counts;          // [bins][kScatterBlocks] per workgroup, then their offsets
     uint32_t *bin_start;       // [bins + 1]
     uint32_t *work_start;      // [bins + 1] first accumulating workgroup of each bin
-    uint32_t *vmax;            // bits of the largest |contribution| of the step (>= 0 floats order as integers)
+    uint32_t *vmax;            // [0] bits of the largest |contribution| of the step (>= 0 floats
+                               // order as integers), [1] records of the fullest bin
+    long long *parts;          // [accumulating workgroup][2 kBinEntries] fixed-point partial sums
     uint16_t *keys;            // [records] entry index within its bin
     float2 *vals;              // [records] contributions of the two features
     float *grads;              // grid part of the gradient: [entries][2]
@@ -743,18 +760,39 @@ __global__ __launch_bounds__(1024) void k_grid_scan_totals(const ScatterArgs a)
         __syncthreads();
     }
     for (int b = t; b <= a.n_bins; b += 1024) a.work_start[b] = b > 0 ? v[b - 1] : 0u;
+    // records of the fullest bin: they bound the fixed-point sums
+    __shared__ uint32_t smax;
+    if (t == 0) smax = 0u;
+    __syncthreads();
+    uint32_t mx = 0u;
+#pragma unroll
+    for (int k = 0; k < kMaxBins / 1024; ++k) mx = tot[k] > mx ? tot[k] : mx;
+    atomicMax(&smax, mx);
+    __syncthreads();
+    if (t == 0) a.vmax[1] = smax;
+}
+
+// Scale of the step's fixed-point sums: with M the largest |contribution| <
+// 2^e and at most 2^c records in any bin, a value v becomes round(v 2^s),
+// s = 62 - c - e, so every term is at most 2^(62-c) and every sum over a bin
+// (whole, or any part of it) at most 2^62: no overflow in 64 bits, and each
+// term is resolved to 2^(-62+c) M.
+__device__ inline int fixed_shift(const uint32_t *vmax)
+{
+    int e;
+    (void)frexpf(u2f(vmax[0]), &e);            // M < 2^e (M = 0 gives e = 0: all terms are zero)
+    const uint32_t n = vmax[1];
+    const int c = n > 1u ? 32 - __builtin_clz(n - 1u) : 0;   // n <= 2^c
+    return 62 - c - e;
 }
 
 // Accumulation: the records of bin b are split over work_start[b+1] -
 // work_start[b] workgroups of at most kAccumRecords records.  Each sums its
-// share in LDS in 64-bit fixed point (LDS integer atomics run far faster than
-// LDS float atomics here, and integer sums do not depend on the order): with
-// M the step's largest |contribution| < 2^e, a value v becomes round(v 2^s),
-// s = 62 - 17 - e, so kAccumRecords < 2^17 terms cannot overflow and each
-// term is resolved to 2^-45 M.  A bin taken by one workgroup is stored as is
-// (every entry, zeros included); the partial sums of a shared bin are added
-// with atomics to the zero-filled gradient (few: hot bins are the coarse
-// dense levels).
+// share in LDS in 64-bit fixed point at the step's scale (fixed_shift; LDS
+// integer atomics run far faster than LDS float atomics here, and integer
+// sums do not depend on the order).  A bin taken by one workgroup is stored
+// as is (every entry, zeros included); a shared bin (the coarse dense
+// levels) stores each part's integer sums, which k_grid_merge adds.
 __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
 {
     __shared__ unsigned long long acc[2 * kBinEntries];
@@ -777,9 +815,7 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     const uint32_t b0 = a.bin_start[b], b1 = a.bin_start[b + 1];
     const uint32_t r0 = b0 + part * (uint32_t)kAccumRecords;
     const uint32_t r1 = parts == 1 ? b1 : (r0 + kAccumRecords < b1 ? r0 + kAccumRecords : b1);
-    int e;
-    (void)frexpf(u2f(*a.vmax), &e);            // M < 2^e (M = 0 gives e = 0: all terms are zero)
-    const int sh = 62 - 17 - e;
+    const int sh = fixed_shift(a.vmax);
     const double up = ldexp(1.0, sh), down = ldexp(1.0, -sh);
     auto fx = [&](float v) { return (unsigned long long)(long long)__builtin_rint((double)v * up); };
     uint32_t r = r0 + threadIdx.x;
@@ -806,22 +842,46 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     }
     __syncthreads();
     const int64_t e0 = (int64_t)b << kBinShift;
+    if (parts > 1) {
+        long long *dst = a.parts + (int64_t)w * (2 * kBinEntries);
+        for (int k = threadIdx.x; k < 2 * kBinEntries; k += 1024) dst[k] = (long long)acc[k];
+        return;
+    }
     for (int k = threadIdx.x; k < 2 * kBinEntries; k += 1024) {
         const int64_t en = e0 + (k >> 1);
         if (en >= a.n_entries) continue;
-        const float g = (float)((double)(long long)acc[k] * down);
-        if (parts == 1) a.grads[2 * en + (k & 1)] = g;
-        else if (g != 0.f) atomicAdd(&a.grads[2 * en + (k & 1)], g);
+        a.grads[2 * en + (k & 1)] = (float)((double)(long long)acc[k] * down);
     }
+}
+
+// Bins split over several workgroups: their parts' integer sums added in
+// part order, then scaled once.  Workgroup (b, s) takes values 256 s .. 256 s
+// + 255 of bin b; the workgroups of whole bins return at once.
+constexpr int kMergeSlices = 2 * kBinEntries / 256;
+__global__ __launch_bounds__(256) void k_grid_merge(const ScatterArgs a)
+{
+    const int b = blockIdx.x / kMergeSlices;
+    const int k = (blockIdx.x % kMergeSlices) * 256 + threadIdx.x;
+    const uint32_t w0 = a.work_start[b], parts = a.work_start[b + 1] - w0;
+    if (parts <= 1u) return;
+    const int64_t en = ((int64_t)b << kBinShift) + (k >> 1);
+    if (en >= a.n_entries) return;
+    const long long *src = a.parts + (int64_t)w0 * (2 * kBinEntries) + k;
+    long long s = 0;
+    for (uint32_t p = 0; p < parts; ++p) s += src[(int64_t)p * (2 * kBinEntries)];
+    a.grads[2 * en + (k & 1)] = (float)((double)s * ldexp(1.0, -fixed_shift(a.vmax)));
 }
 
 // ---------------------------------------------------------------- Adam
 // Kingma & Ba, Algorithm 1, applied to every parameter; bc1 = 1 - beta1^t,
 // bc2 = 1 - beta2^t.
+// With `status` given (a training step), nothing is updated when the step's
+// loss or gradient was not finite (status[2] set by the forward pass).
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
                        float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                       float bc1, float bc2)
+                       float bc1, float bc2, const uint32_t *status)
 {
+    if (status && status[2] != 0u) return;
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; k < n; k += stride) {
@@ -834,19 +894,71 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, floa
     }
 }
 
+// ---------------------------------------------------------------- initial parameters
+// Seeded start of training: grid values uniform on [lo, hi), weights of
+// matrix m uniform on [-a_m, a_m), a_m = sqrt(6 / (fan_in + fan_out))
+// (Xavier-uniform).  Parameter k takes uniform number 0 of the generator
+// stream (seed, k, 0, 3): Philox4x64-10, counter (k, 0, 0, 3), key (seed, 0),
+// the low 32 bits of word 0 cut to 24.  FP64 arithmetic, one rounding to FP32.
+struct InitArgs {
+    float *params;
+    int64_t n_grid, n;
+    int32_t n_mats;
+    int64_t mat_end[kMaxMats];
+    double scale[kMaxMats];
+    double lo, width;
+    uint64_t seed;
+};
+
+__global__ void k_init_params(const InitArgs a)
+{
+#pragma clang fp contract(off)
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; k < a.n; k += stride) {
+        uint64_t w[4] = {(uint64_t)k, 0ull, 0ull, 3ull};
+        philox4x64_10(w, a.seed, 0);
+        const double u = (double)((uint32_t)w[0] >> 8) * 0x1p-24;
+        double v;
+        if (k < a.n_grid) {
+            v = __builtin_fma(a.width, u, a.lo);
+        } else {
+            int m = 0;
+            while (m + 1 < a.n_mats && k >= a.mat_end[m]) ++m;
+            v = a.scale[m] * (2.0 * u - 1.0);
+        }
+        a.params[k] = (float)v;
+    }
+}
+
 // ---------------------------------------------------------------- host side
 struct TrainLayout {
     int64_t bwd_off, x_off, mask_off, dE_off, dx0_off, sflag_off, counts_off, start_off, work_off,
-        vmax_off, keys_off, vals_off, dw_off, total;
+        vmax_off, keys_off, vals_off, dw_off, parts_off, total;
 };
 
-template <int P, class S> TrainLayout train_layout_t(int64_t n)
+// Accumulating workgroups of a step: at most one per bin plus one per
+// kAccumRecords records (the launch takes this many; the excess ones return
+// at once).
+static int64_t acc_group_bound(int64_t n, int n_levels, int64_t n_bins)
+{
+    const int64_t records = n * (int64_t)n_levels * 8;
+    return n_bins + (records + kAccumRecords - 1) / kAccumRecords;
+}
+
+static int64_t grid_bins(const Model &m)
+{
+    return (m.n_grid_values / 2 + kBinEntries - 1) >> kBinShift;
+}
+
+template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
 {
     using B = Bwd<P, S>;
     const int64_t nc = (n + 63) / 64;
     TrainLayout L;
-    L.bwd_off = 0;
-    L.x_off = align256(B::BYTES);
+    L.vmax_off = 0;   // step words first, at a fixed place (see kStatusWords)
+    L.bwd_off = 256;
+    L.x_off = L.bwd_off + align256(B::BYTES);
     L.mask_off = L.x_off + align256(nc * B::CHUNK_BYTES);
     L.dE_off = L.mask_off + align256(nc * S::H * (S::W / 32) * 64 * 4);
     L.dx0_off = L.dE_off + align256(n * 3 * 4);
@@ -854,15 +966,16 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n)
     L.counts_off = L.sflag_off + align256(n);
     L.start_off = L.counts_off + align256((int64_t)kMaxBins * kScatterBlocks * 4);
     L.work_off = L.start_off + align256((kMaxBins + 1) * 4);
-    L.vmax_off = L.work_off + align256((kMaxBins + 1) * 4);
-    L.keys_off = L.vmax_off + 256;
+    L.keys_off = L.work_off + align256((kMaxBins + 1) * 4);
     const int64_t records = n * S::L * 8;
     L.vals_off = L.keys_off + align256(records * 2);
     L.dw_off = L.vals_off + align256(records * 8);
     // one weight-gradient row per backward wave: 4 per workgroup, at most
     // one workgroup per 4 chunks and kBwdMaxBlocks in all
     const int64_t bwd_blocks = std::min<int64_t>(kBwdMaxBlocks, std::max<int64_t>(1, (nc + 3) / 4));
-    L.total = L.dw_off + align256(bwd_blocks * 4 * Bwd<P, S>::NMLP * 4);
+    L.parts_off = L.dw_off + align256(bwd_blocks * 4 * Bwd<P, S>::NMLP * 4);
+    // fixed-point partial sums: one row per accumulating workgroup
+    L.total = L.parts_off + align256(acc_group_bound(n, S::L, n_bins) * 2 * kBinEntries * 8);
     return L;
 }
 
@@ -872,18 +985,20 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
 {
     using B = Bwd<P, S>;
     using O = Ops<P, S>;
-    TrainLayout L = train_layout_t<P, S>(b.count);
+    TrainLayout L = train_layout_t<P, S>(b.count, grid_bins(m));
     uint8_t *ws = static_cast<uint8_t *>(st.workspace);
     if (m.n_params - m.n_grid_values != B::NMLP) return hipErrorInvalidValue;   // shape mismatch
-    // zero the grid part of the gradient (the MLP part is stored whole by
-    // k_dw_sum) and the loss, with kernels, so the step can be captured
-    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, stream, st.grads, m.n_grid_values);
+    // the loss and the step's words are cleared by kernels, so the step can be
+    // captured; every gradient value is stored whole (the grid by the
+    // accumulating and merging passes, the MLP by k_dw_sum)
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.vmax_off);
     hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, stream, st.loss, (int64_t)1);
+    hipError_t e = launch_zero_u32(status, kStatusWords, stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_prepare_bwd<P, S>), dim3((B::N_OPS * 64 + 255) / 256), dim3(256), 0,
                        stream, st.params, ws + L.bwd_off, m.n_grid_values);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // 1. forward with saves, loss and d loss / dE
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 1. forward with saves, loss and d loss / dE (non-finite ones mark the step)
     QueryArgs a;
     memset(&a, 0, sizeof(a));
     a.n_frames = 1;
@@ -906,6 +1021,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     a.mask_save = reinterpret_cast<uint32_t *>(ws + L.mask_off);
     a.dE = reinterpret_cast<float *>(ws + L.dE_off);
     a.loss = st.loss;
+    a.train_status = status;
     a.loss_scale = (float)(1.0 / (3.0 * (double)b.count));  // used by the forward's loss sum
     a.loss_eps = 0.01f;
     {
@@ -995,7 +1111,8 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.counts = reinterpret_cast<uint32_t *>(ws + L.counts_off);
     sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
     sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
-    sa.vmax = reinterpret_cast<uint32_t *>(ws + L.vmax_off);
+    sa.vmax = status;
+    sa.parts = reinterpret_cast<long long *>(ws + L.parts_off);
     sa.keys = reinterpret_cast<uint16_t *>(ws + L.keys_off);
     sa.vals = reinterpret_cast<float2 *>(ws + L.vals_off);
     sa.grads = st.grads;
@@ -1011,7 +1128,6 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
-    if ((e = launch_zero_u32(sa.vmax, 1, stream)) != hipSuccess) return e;
     const int write_lds = kScatterWaves * write_wave_bytes(sa.n_levels);
     static bool write_lds_set = false;   // dynamic LDS beyond 64 KB must be allowed per kernel
     if (!write_lds_set) {
@@ -1023,24 +1139,22 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     }
     hipLaunchKernelGGL(k_grid_write, dim3(kScatterBlocks), dim3(kScatterThreads), (size_t)write_lds,
                        stream, sa);
-    // an upper bound of the accumulating workgroups: one per bin plus one per
-    // kAccumRecords records; the excess ones return at once
-    const int64_t records = b.count * (int64_t)m.cfg.n_levels * 8;
-    const int64_t acc_groups = sa.n_bins + (records + kAccumRecords - 1) / kAccumRecords;
+    const int64_t acc_groups = acc_group_bound(b.count, m.cfg.n_levels, sa.n_bins);
     hipLaunchKernelGGL(k_grid_accum, dim3((unsigned)acc_groups), dim3(1024), 0, stream, sa);
+    hipLaunchKernelGGL(k_grid_merge, dim3((unsigned)(sa.n_bins * kMergeSlices)), dim3(256), 0, stream, sa);
     return hipGetLastError();
 }
 
 static int64_t train_bytes(const Model &m, niv_precision prec, int64_t n)
 {
     if (m.kind == kUnitCube)
-        return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeUnitCube>(n).total
-                                : train_layout_t<NIV_FP16, ShapeUnitCube>(n).total;
+        return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeUnitCube>(n, grid_bins(m)).total
+                                : train_layout_t<NIV_FP16, ShapeUnitCube>(n, grid_bins(m)).total;
     if (m.kind == kRoom6D)
-        return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom6D>(n).total
-                                : train_layout_t<NIV_FP16, ShapeRoom6D>(n).total;
-    return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom>(n).total
-                            : train_layout_t<NIV_FP16, ShapeRoom>(n).total;
+        return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom6D>(n, grid_bins(m)).total
+                                : train_layout_t<NIV_FP16, ShapeRoom6D>(n, grid_bins(m)).total;
+    return prec == NIV_FP32 ? train_layout_t<NIV_FP32, ShapeRoom>(n, grid_bins(m)).total
+                            : train_layout_t<NIV_FP16, ShapeRoom>(n, grid_bins(m)).total;
 }
 
 }  // namespace niv
@@ -1092,30 +1206,104 @@ niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state
     return hst(e);
 }
 
-niv_status niv_adam_update(niv_handle *h, const niv_train_state *st, const niv_adam *ad,
-                           hipStream_t stream)
+static niv_status check_adam(const niv_train_state *st, const niv_adam *ad)
 {
-    if (!h || !st || !ad || !st->params || !st->grads || !st->adam_m || !st->adam_v)
+    if (!st || !ad || !st->params || !st->grads || !st->adam_m || !st->adam_v)
         return NIV_ERR_INVALID_ARG;
     if (ad->step < 1 || !(ad->lr >= 0.f) || !(ad->beta1 >= 0.f && ad->beta1 < 1.f) ||
         !(ad->beta2 >= 0.f && ad->beta2 < 1.f) || !(ad->eps > 0.f))
         return NIV_ERR_INVALID_ARG;
+    return NIV_OK;
+}
+
+static niv_status adam_launch(const Model &m, const niv_train_state *st, const niv_adam *ad,
+                              const uint32_t *status, hipStream_t stream)
+{
     const double bc1 = 1.0 - pow((double)ad->beta1, (double)ad->step);
     const double bc2 = 1.0 - pow((double)ad->beta2, (double)ad->step);
     hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, stream, st->params, st->grads, st->adam_m,
-                       st->adam_v, h->m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps, (float)bc1,
-                       (float)bc2);
+                       st->adam_v, m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps, (float)bc1,
+                       (float)bc2, status);
     return hst(hipGetLastError());
+}
+
+niv_status niv_adam_update(niv_handle *h, const niv_train_state *st, const niv_adam *ad,
+                           hipStream_t stream)
+{
+    if (!h) return NIV_ERR_INVALID_ARG;
+    niv_status s = check_adam(st, ad);
+    if (s != NIV_OK) return s;
+    return adam_launch(h->m, st, ad, nullptr, stream);
 }
 
 niv_status niv_train_step(niv_handle *h, const niv_batch *b, const niv_train_state *st,
                           const niv_adam *ad, niv_precision prec, hipStream_t stream)
 {
-    niv_status s = niv_backward(h, b, st, prec, stream);
+    if (!h) return NIV_ERR_INVALID_ARG;
+    niv_status s = check_adam(st, ad);
     if (s != NIV_OK) return s;
-    s = niv_adam_update(h, st, ad, stream);
+    s = niv_backward(h, b, st, prec, stream);
+    if (s != NIV_OK) return s;
+    // the update reads the step's non-finite word and does nothing when it is set
+    s = adam_launch(h->m, st, ad, static_cast<const uint32_t *>(st->workspace), stream);
     if (s != NIV_OK) return s;
     return niv_prepare(h, st->params, st->model, prec, stream);
+}
+
+niv_status niv_train_status(const niv_train_state *st, hipStream_t stream)
+{
+    if (!st || !st->workspace || !al(st->workspace, 256)) return NIV_ERR_INVALID_ARG;
+    uint32_t words[kStatusWords] = {0u, 0u, 0u, 0u};
+    if (hipMemcpyAsync(words, st->workspace, sizeof(words), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return NIV_ERR_HIP;
+    return words[2] ? NIV_ERR_NONFINITE : NIV_OK;
+}
+
+niv_status niv_lr_schedule(int64_t step, int64_t hold_steps, int64_t total_steps, double lr0,
+                           double lr1, double *lr)
+{
+    if (!lr || step < 1 || hold_steps < 0 || total_steps < 1 || !(lr0 > 0.0) || !(lr1 > 0.0) ||
+        !isfinite(lr0) || !isfinite(lr1))
+        return NIV_ERR_INVALID_ARG;
+    if (step <= hold_steps || total_steps <= hold_steps) {
+        *lr = lr0;
+        return NIV_OK;
+    }
+    double t = (double)(step - hold_steps) / (double)(total_steps - hold_steps);
+    t = t < 1.0 ? t : 1.0;
+    *lr = lr0 * pow(lr1 / lr0, t);
+    return NIV_OK;
+}
+
+niv_status niv_init_params(niv_handle *h, float *params, uint64_t seed, float grid_lo, float grid_hi,
+                           hipStream_t stream)
+{
+    if (!h || !params || !al(params, 4) || !isfinite(grid_lo) || !isfinite(grid_hi) ||
+        !(grid_hi >= grid_lo))
+        return NIV_ERR_INVALID_ARG;
+    const niv_config &c = h->m.cfg;
+    const int n_mats = c.n_hidden + 1;
+    if (n_mats > kMaxMats) return NIV_ERR_UNSUPPORTED;
+    InitArgs a;
+    memset(&a, 0, sizeof(a));
+    a.params = params;
+    a.n_grid = h->m.n_grid_values;
+    a.n = h->m.n_params;
+    a.n_mats = n_mats;
+    int64_t end = a.n_grid;
+    for (int k = 0; k < n_mats; ++k) {
+        const int64_t fan_in = k == 0 ? h->m.din : c.width;
+        const int64_t fan_out = k == n_mats - 1 ? c.n_out : c.width;
+        end += fan_in * fan_out;
+        a.mat_end[k] = end;
+        a.scale[k] = sqrt(6.0 / (double)(fan_in + fan_out));
+    }
+    a.lo = (double)grid_lo;
+    a.width = (double)grid_hi - (double)grid_lo;
+    a.seed = seed;
+    hipLaunchKernelGGL(k_init_params, dim3(1024), dim3(256), 0, stream, a);
+    return hst(hipGetLastError());
 }
 
 }  // extern "C"

@@ -13,7 +13,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libniv.so")
 
-NIV_OK, NIV_ERR_INVALID_ARG, NIV_ERR_UNSUPPORTED, NIV_ERR_HIP, NIV_ERR_WORKSPACE, NIV_ERR_STATE = range(6)
+(NIV_OK, NIV_ERR_INVALID_ARG, NIV_ERR_UNSUPPORTED, NIV_ERR_HIP, NIV_ERR_WORKSPACE, NIV_ERR_STATE,
+ NIV_ERR_NONFINITE) = range(7)
 FP32, FP16, BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
 FLAG_OUTSIDE, FLAG_BAD_INPUT, FLAG_BAD_OUTPUT, FLAG_FALLBACK, FLAG_NEG_OUTPUT = 1, 2, 4, 8, 16
@@ -127,6 +128,10 @@ def lib():
         L.niv_adam_update.argtypes = [vp, C.POINTER(TrainState), C.POINTER(Adam), vp]
         L.niv_train_step.argtypes = [vp, C.POINTER(Batch), C.POINTER(TrainState), C.POINTER(Adam),
                                      C.c_int, vp]
+        L.niv_train_status.argtypes = [C.POINTER(TrainState), vp]
+        L.niv_lr_schedule.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                      C.POINTER(C.c_double)]
+        L.niv_init_params.argtypes = [vp, vp, C.c_uint64, C.c_float, C.c_float, vp]
         L.mc_scene_create.argtypes = [vp, C.c_int32, C.POINTER(vp)]
         L.mc_scene_destroy.argtypes = [vp]
         L.mc_scene_destroy.restype = None
@@ -161,6 +166,14 @@ def _stream():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def lr_schedule(step, hold_steps, total_steps, lr0=1e-2, lr1=1e-4):
+    """niv_lr_schedule: the Sec. 4.5 learning rate of a 1-based step."""
+    out = C.c_double()
+    _check(lib().niv_lr_schedule(int(step), int(hold_steps), int(total_steps), float(lr0),
+                                 float(lr1), C.byref(out)), "niv_lr_schedule")
+    return out.value
 
 
 def make_config(d) -> Config:
@@ -221,6 +234,16 @@ class NIV:
         c = self.cfg
         W = c["width"]
         return [(W, self.input_dim)] + [(W, W)] * (c["n_hidden"] - 1) + [(c["n_out"], W)]
+
+    def init_params(self, seed, grid_lo=-1e-4, grid_hi=1e-4, out=None, device="cuda"):
+        """niv_init_params: seeded FP32 master parameters on the device (grid
+        uniform on [grid_lo, grid_hi), weights Xavier-uniform)."""
+        if out is None:
+            out = torch.empty(self.n_params, dtype=torch.float32, device=device)
+        assert out.is_cuda and out.dtype == torch.float32 and out.numel() == self.n_params
+        _check(lib().niv_init_params(self._h, _ptr(out), C.c_uint64(int(seed)), float(grid_lo),
+                                     float(grid_hi), _stream()), "niv_init_params")
+        return out
 
     def level_info(self):
         import numpy as np
@@ -567,6 +590,15 @@ class Trainer:
         _check(lib().niv_backward(self.niv._h, C.byref(b), C.byref(self._st), self.prec, _stream()),
                "niv_backward")
         return self.loss
+
+    def status(self):
+        """niv_train_status: waits for the stream; False if the last step's loss
+        or gradient was not finite (its update was skipped), else True."""
+        st = lib().niv_train_status(C.byref(self._st), _stream())
+        if st == NIV_ERR_NONFINITE:
+            return False
+        _check(st, "niv_train_status")
+        return True
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=None):
         self.step_count = step if step is not None else self.step_count + 1

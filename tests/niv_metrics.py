@@ -59,3 +59,21 @@ def sign_margin(prec, E_ref, scale):
         return 1e-5 * np.maximum(np.abs(E_ref), scale)
     rms = np.sqrt(np.mean(E_ref ** 2))
     return 2e-2 * np.maximum(scale, rms)
+
+
+def relu_margin(mats, x0):
+    """Per sample, the smallest |z| / (|W| |h|) over the hidden units, z the
+    pre-activation and |W| |h| the magnitude of its terms, in the FP64 pass.
+    Where it is below the FP32 rounding of z (~1e-7), an FP32 evaluation may
+    take the other ReLU decision; the gradient then gates a different unit.
+    Both decisions are correct to the precision, so gradient comparisons
+    leave such samples out (on both sides)."""
+    h = x0.T
+    m = np.full(x0.shape[0], np.inf)
+    for Wm in mats[:-1]:
+        z = Wm @ h
+        sc = np.abs(Wm) @ np.abs(h)
+        r = np.abs(z) / np.maximum(sc, 1e-300)
+        m = np.minimum(m, r.min(axis=0))
+        h = np.maximum(z, 0.0)
+    return m

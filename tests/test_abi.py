@@ -145,3 +145,22 @@ def test_dynamic_ao_argument_checks(niv):
     assert lib.niv_ao_apply(h, C.byref(p), 5, None, None, None, None, None, None, None) == \
         niv.NIV_ERR_INVALID_ARG
     lib.niv_ao_destroy(h)
+
+
+def test_lr_schedule_matches_oracle(niv):
+    """The library's Sec. 4.5 schedule (host-only call) equals the oracle's
+    over holds, decays and the steps past the end."""
+    for hold, total in ((800, 4000), (10000, 50000), (0, 7), (5, 5)):
+        for step in sorted({1, 2, hold, hold + 1, (hold + total) // 2, total - 1, total,
+                            total + 3, 3 * total}):
+            if step < 1:
+                continue
+            got = niv.lr_schedule(step, hold, total, 1e-2, 1e-4)
+            want = O.lr_at(step, hold, total, 1e-2, 1e-4)
+            assert got == pytest.approx(want, rel=1e-14, abs=0), (hold, total, step)
+    from paper_2602_12949_amd.bake import lr_at
+    assert lr_at(1, 4000) == 1e-2 and lr_at(4000, 4000) == pytest.approx(1e-4, rel=1e-12)
+    for bad in ((0, 10, 100, 1e-2, 1e-4), (1, -1, 100, 1e-2, 1e-4), (1, 10, 100, 0.0, 1e-4),
+                (1, 10, 100, 1e-2, float("nan"))):
+        with pytest.raises(niv.NivError):
+            niv.lr_schedule(*bad)

@@ -253,7 +253,7 @@ def test_fallback_pixels_get_monte_carlo_estimates(small_rooms):
         close = (np.abs(E[idx] - Eo) / scale).max(1) <= 1e-4
         print(f"  frame {fi}: {idx.size} fallback pixels, {close.mean():.3f} agree to 1e-4",
               flush=True)
-        assert close.mean() >= 0.9
+        assert close.mean() >= 0.99
         d = ~close
         if d.any():
             z = (E[idx][d] - Eo[d]) / np.sqrt(2 * varo[d] + 1e-30)
@@ -491,4 +491,4 @@ def test_fallback_in_a_scene_that_moves(small_rooms):
         close = (np.abs(E[idx] - Eo) / scale).max(1) <= 1e-4
         print(f"  frame {fi} (t = {ts[fi]}): {idx.size} fallback pixels, {close.mean():.3f} agree",
               flush=True)
-        assert close.mean() >= 0.9
+        assert close.mean() >= 0.99

@@ -103,7 +103,7 @@ def test_room_parity_with_oracle(room_points, flags, bounces):
     close = (np.abs(E - Eo) / scale).max(1) <= 1e-4
     print(f"points agreeing to 1e-4: {close.mean():.4f}; back-face counts equal: "
           f"{(bf == bfo).mean():.4f}; validity equal: {(vd == vdo).mean():.4f}", flush=True)
-    assert close.mean() >= 0.9
+    assert close.mean() >= 0.99
     assert (bf == bfo).mean() >= 0.97 and (vd == vdo).mean() >= 0.97
     # points that differ still agree statistically
     d = ~close
@@ -145,7 +145,7 @@ def test_moving_scene_parity_with_oracle(room_points, flags, bounces):
     close = (np.abs(E - Eo) / scale).max(1) <= 1e-4
     print(f"points agreeing to 1e-4: {close.mean():.4f}; back faces equal {(bf == bfo).mean():.4f}",
           flush=True)
-    assert close.mean() >= 0.9
+    assert close.mean() >= 0.99
     assert (bf == bfo).mean() >= 0.97 and (vd == vdo).mean() >= 0.97
     d = ~close
     if d.any():

@@ -147,6 +147,118 @@ def test_trilinear_reproduces_affine_latents():
         np.testing.assert_allclose(x0[:, 2 * l + 1], s @ (-a) - 1.0, atol=1e-12)
 
 
+def test_trilinear_reproduces_affine_latents_in_world_coordinates_on_a_box():
+    """The room's 10 x 4 x 10 m box (non-cubic, offset from the origin):
+    latents that are an affine function of each vertex's WORLD position,
+    lo + i (hi - lo) / N per axis, are reproduced exactly at any world
+    point.  An axis mapped with another axis' extent, a missing offset or a
+    transposed cell index breaks this."""
+    lo, hi = np.array([-2.0, 0.5, 3.0]), np.array([8.0, 4.5, 13.0])
+    c = _cfg(n_levels=3, log2_T=14, base_res=3.0, per_level_scale=2.0,
+             aabb_min=tuple(lo), aabb_max=tuple(hi))
+    tab = O.level_table(c)
+    assert tab["dense"].all()
+    params = np.zeros(O.n_params(c))
+    grid = O.split_params(c, params)[0]
+    a = np.array([0.3, -1.1, 0.7])
+    for l in range(c.n_levels):
+        N = int(tab["res"][l])
+        side = N + 1
+        zz, yy, xx = np.meshgrid(np.arange(side), np.arange(side), np.arange(side), indexing="ij")
+        v = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1).astype(np.float64)   # x fastest
+        world = lo + v * (hi - lo) / N
+        grid[tab["offset"][l]:tab["offset"][l] + side ** 3, 0] = world @ a + 0.25
+        grid[tab["offset"][l]:tab["offset"][l] + side ** 3, 1] = world @ (-a) - 1.0
+    rng = np.random.default_rng(31)
+    pos = rng.uniform(lo, hi, size=(400, 3)).astype(np.float32)
+    nrm = np.tile(np.float32([0, 1, 0]), (400, 1))
+    _, _, _, x0 = O.query(c, params, pos, nrm, want_x0=True)
+    p64 = pos.astype(np.float64)
+    for l in range(c.n_levels):
+        np.testing.assert_allclose(x0[:, 2 * l], p64 @ a + 0.25, atol=1e-11)
+        np.testing.assert_allclose(x0[:, 2 * l + 1], p64 @ (-a) - 1.0, atol=1e-11)
+
+
+def test_fp32_error_bar_reading_on_the_room_network():
+    """The reading of the FP32 bar (max relative error 1e-5): relative to
+    the output, or under cancellation to the magnitude of the terms summed
+    into it.  A plain numpy FP32 evaluation of the room_1080p network (same
+    FP64 encoded inputs rounded to FP32, sequential FP32 matrix products)
+    meets 1e-5 on that scale, while the error relative to a floor of 1e-3
+    of the largest output exceeds 1e-5: that floored form is not a bar any
+    FP32 evaluation of this network can meet."""
+    from niv_metrics import term_scale, max_rel_floored
+    w = get_workload("room_1080p")
+    c = O.config_from_workload(w)
+    params = make_params(O.n_grid_values(c), O.mat_shapes(c), w.param_seed, *w.grid_init)
+    p64 = params.astype(np.float64)
+    rng = np.random.default_rng(5)
+    n = 1 << 16
+    pos = rng.uniform(w.aabb_min, w.aabb_max, size=(n, 3)).astype(np.float32)
+    v = rng.standard_normal((n, 3))
+    nrm = (v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    E, _, _, x0 = O.query(c, p64, pos, nrm, want_x0=True)
+    mats = O.split_params(c, p64)[1:]
+    h = x0.astype(np.float32)
+    for k, Wm in enumerate(mats):
+        h = h @ Wm.astype(np.float32).T
+        if k < len(mats) - 1:
+            h = np.maximum(h, np.float32(0))
+    scale = term_scale(mats, x0)
+    err = np.abs(h.astype(np.float64) - E)
+    term = float(np.max(err / np.maximum(np.abs(E), scale)))
+    floored = max_rel_floored(h.astype(np.float64), E)
+    print(f"numpy FP32 on {n} points: term-scale {term:.2e}, floored {floored:.2e}")
+    assert term <= 1e-5
+    assert floored > 1e-5
+
+
+def test_init_params_follow_their_stream_and_xavier_bounds():
+    """Seeded start: value k is lo + (hi - lo) u_k on the grid and a (2 u_k
+    - 1) in weight matrix m, a = sqrt(6 / (fan_in + fan_out)), where u_k is
+    the low 32 bits of the first word of Philox4x64-10 at counter (k, 0, 0,
+    3), key (seed, 0), cut to 24 bits (recomputed here with numpy's Philox).
+    The moments follow: grid mean (lo + hi) / 2; weight variance
+    2 / (fan_in + fan_out) (Xavier)."""
+    w = get_workload("room_1080p")
+    c = O.config_from_workload(w)
+    seed, lo, hi = 4242, -1e-4, 1e-4
+    p = O.init_params(c, seed, lo, hi)
+    assert p.dtype == np.float32 and p.size == O.n_params(c)
+    n_grid = O.n_grid_values(c)
+
+    def u_k(k):   # numpy increments its counter before a block: start one below (k, 0, 0, 3)
+        bg = np.random.Philox(counter=np.array([k - 1, 0, 0, 3], dtype=np.uint64),
+                              key=np.array([seed, 0], dtype=np.uint64))
+        return (int(bg.random_raw(1)[0]) & 0xFFFFFFFF) >> 8
+
+    from fractions import Fraction
+    rng = np.random.default_rng(8)
+    ks = list(rng.integers(1, n_grid, 40)) + list(rng.integers(n_grid, p.size, 40)) + [1, n_grid]
+    shapes = O.mat_shapes(c)
+    ends = np.cumsum([o * i for o, i in shapes]) + n_grid
+    for k in ks:
+        u = u_k(int(k)) * 2.0 ** -24
+        if k < n_grid:   # one rounding of the exact lo + (hi - lo) u to double, then to float
+            want = np.float32(float(Fraction(hi - lo) * Fraction(u) + Fraction(lo)))
+        else:
+            m = int(np.searchsorted(ends, k, side="right"))
+            o, i = shapes[m]
+            want = np.float32(math.sqrt(6.0 / (o + i)) * (2.0 * u - 1.0))
+        assert p[k] == want, (k, p[k], want)
+    g = p[:n_grid].astype(np.float64)
+    assert g.min() >= lo and g.max() < hi
+    assert abs(g.mean()) < 1e-6
+    k = n_grid
+    for (o, i) in shapes:
+        wm = p[k:k + o * i].astype(np.float64)
+        a = math.sqrt(6.0 / (o + i))
+        assert wm.min() >= -a and wm.max() < a
+        assert wm.var() == pytest.approx(2.0 / (o + i), rel=0.35 if o * i < 500 else 0.06)
+        k += o * i
+    assert not np.array_equal(p, O.init_params(c, seed + 1, lo, hi))
+
+
 def test_weights_partition_of_unity_and_corner_range():
     c = O.config_from_workload(get_workload("room_1080p"))
     tab = O.level_table(c)
