@@ -161,6 +161,24 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
                               niv_precision prec, const niv_fallback *fb, void *workspace,
                               int64_t workspace_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * niv_query_fallback with the counter and the list of flagged pixels in a
+ * fixed scratch array inside the library instead of a workspace argument.
+ * Computes exactly what niv_query_fallback computes with a list of
+ * max_flagged entries.  1 <= max_flagged <= NIV_NOALLOC_MAX_FLAGGED
+ * (4 MiB of scratch); a larger value gives NIV_ERR_WORKSPACE, a smaller one
+ * NIV_ERR_INVALID_ARG, and nothing is enqueued.  The scratch is held on
+ * each device the library runs on until the process ends (its device
+ * address is looked up on the first call on a device); every call on one
+ * device shares it, so calls that overlap on one device, on different
+ * streams or from different threads, race and must be serialised by the
+ * caller.  The counter is cleared by each call.  Allocates nothing. */
+#define NIV_NOALLOC_MAX_FLAGGED (1 << 20)
+niv_status niv_query_fallback_noalloc(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                                      niv_precision prec, const niv_fallback *fb,
+                                      int64_t max_flagged, hipStream_t stream);
+
 /* Half-resolution rendering (Sec. 4.4): the network runs at a quarter of
  * the pixels and the full-resolution albedo shades the result.  The
  * half-resolution samples are the G-buffer pixels (2x, 2y), x < ceil(W/2),

@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "niv_internal.h"
@@ -393,6 +394,56 @@ niv_status niv_query_fallback(niv_handle *h, const niv_frame *frames, int32_t n_
     const int64_t cap64 = (workspace_bytes - 256) / 4;
     const uint32_t cap = (uint32_t)(cap64 < 0x7fffffff ? cap64 : 0x7fffffff);
     return query_fallback_into(h, frames, n_frames, prec, fb, cnt, list, cap, stream);
+}
+
+}  // extern "C"
+
+// Fallback scratch that needs no allocation: the counter (first 256 bytes)
+// and a list of up to NIV_NOALLOC_MAX_FLAGGED entries, resident on every
+// device the library runs on until the process ends.  Host code never uses
+// this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_ptr.
+static __device__ __align__(256) uint8_t scratch[256 + 4 * (size_t)NIV_NOALLOC_MAX_FLAGGED];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device.
+niv_status scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return NIV_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return NIV_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NIV_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NIV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+niv_status niv_query_fallback_noalloc(niv_handle *h, const niv_frame *frames, int32_t n_frames,
+                                      niv_precision prec, const niv_fallback *fb,
+                                      int64_t max_flagged, hipStream_t stream)
+{
+    niv_status s = check_fallback(h, frames, n_frames, prec, fb);
+    if (s != NIV_OK) return s;
+    if (max_flagged < 1) return NIV_ERR_INVALID_ARG;
+    if (max_flagged > NIV_NOALLOC_MAX_FLAGGED) return NIV_ERR_WORKSPACE;
+    void *base = nullptr;
+    s = scratch_address(&base);
+    if (s != NIV_OK) return s;
+    uint32_t *cnt = static_cast<uint32_t *>(base);
+    uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(base) + 256);
+    return query_fallback_into(h, frames, n_frames, prec, fb, cnt, list, (uint32_t)max_flagged,
+                               stream);
 }
 
 niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames,

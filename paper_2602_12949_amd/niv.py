@@ -88,6 +88,7 @@ class Adam(C.Structure):
 
 
 _lib = None
+NOALLOC_MAX_FLAGGED = 1 << 20   # NIV_NOALLOC_MAX_FLAGGED
 MC_NEE, MC_EMIT_ON_HIT, MC_INCLUDE_DIRECT, MC_DIRECT_AT_ORIGIN = 1, 2, 4, 8
 
 
@@ -115,6 +116,8 @@ def lib():
         L.niv_fallback_sizes.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
         L.niv_query_fallback.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
                                          C.POINTER(Fallback), vp, C.c_int64, vp]
+        L.niv_query_fallback_noalloc.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
+                                                 C.POINTER(Fallback), C.c_int64, vp]
         L.niv_autotune.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int, vp,
                                    C.POINTER(TuneResult)]
         L.niv_set_tune.argtypes = [vp, C.c_int, C.c_int32, C.c_int32, C.c_int32]
@@ -363,6 +366,14 @@ class NIV:
         _check(lib().niv_query_fallback(self._h, arr, len(frames), _prec(prec), C.byref(fb),
                                         _ptr(workspace), workspace.numel(), _stream()),
                "niv_query_fallback")
+
+    def query_fallback_noalloc(self, frames, prec, fb, max_flagged):
+        """niv_query_fallback_noalloc: as query_fallback, with the list in the
+        library's fixed scratch (at most NOALLOC_MAX_FLAGGED entries)."""
+        arr = (Frame * len(frames))(*frames)
+        _check(lib().niv_query_fallback_noalloc(self._h, arr, len(frames), _prec(prec), C.byref(fb),
+                                                int(max_flagged), _stream()),
+               "niv_query_fallback_noalloc")
 
     def autotune(self, frames, prec):
         """Times the launch shapes on these frames, keeps the fastest."""
