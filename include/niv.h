@@ -138,6 +138,21 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
  * shape and precision; up to 16 frames go into one persistent launch whose
  * workgroups walk the frames' pixel tiles in order. */
 
+/* Inspection of the encoding (Sec. 4.1): for points i < count (pos, device
+ * [count][3] float) the grid entries that the query's encoding at `prec`
+ * reads, out (device) [count][n_levels][8] uint32: the level's first entry
+ * plus the corner's index within the level, corner c = cx + 2 cy + 4 cz of
+ * the cell, dense x + (N+1)(y + (N+1) z) or the spatial hash.  The entries
+ * come from the same device encoding function that niv_query (training != 0:
+ * the forward pass of niv_backward) runs for this model and precision, with
+ * positions clamped to the box: FP64 cell coordinates, except the FP16
+ * query, which takes FP32 coordinates (at a cell face it may choose the
+ * neighbouring cell).  `model` is a prepared model of `prec` (its level
+ * table is read).  Non-finite positions give 0xFFFFFFFF.  count < 2^28;
+ * grid-free models give NIV_ERR_UNSUPPORTED. */
+niv_status niv_corner_indices(niv_handle *h, niv_precision prec, int32_t training, const void *model,
+                              const float *pos, int64_t count, uint32_t *out, hipStream_t stream);
+
 /* Monte Carlo fallback for pixels the network should not answer: after the
  * query, pixels whose flags intersect `flag_mask` (bits 0, 2 and 4 of
  * out_flags) or whose in_flags are set are appended to a list, and

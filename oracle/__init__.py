@@ -85,6 +85,7 @@ def lib():
         L.orc_freq.argtypes = [C.c_int, C.c_double, dp]
         L.orc_query.argtypes = [cp, dp, C.c_int64, fp, fp, fp, fp, u8p, dp, dp, u8p, dp]
         L.orc_corners.argtypes = [cp, fp, i64p, dp]
+        L.orc_corners_n.argtypes = [cp, fp, C.c_int64, i64p]
         L.orc_loss_grad.argtypes = [cp, dp, C.c_int64, fp, fp, fp, fp, u8p, C.c_double, dp]
         L.orc_loss_grad.restype = C.c_double
         L.orc_loss.argtypes = [cp, dp, C.c_int64, fp, fp, fp, fp, u8p, C.c_double]
@@ -228,6 +229,15 @@ def corners(cfg: Config, p):
     w = np.zeros((cfg.n_levels, 8))
     lib().orc_corners(C.byref(cfg), _P(p, C.c_float), _P(idx, C.c_int64), _P(w, C.c_double))
     return idx, w
+
+
+def corners_many(cfg: Config, pos):
+    """Within-level corner indices [n, L, 8] of n points (corners() per point)."""
+    pos = _f32(pos).reshape(-1, 3)
+    n = len(pos)
+    idx = np.zeros((n, cfg.n_levels, 8), np.int64)
+    lib().orc_corners_n(C.byref(cfg), _P(pos, C.c_float), n, _P(idx, C.c_int64))
+    return idx
 
 
 # ---------------------------------------------------------------- training

@@ -444,6 +444,19 @@ void orc_corners(const orc_config *c, const float *pos, int64_t *idx, double *w)
     }
 }
 
+/* orc_corners for n points: idx [n][L][8] within-level indices. */
+void orc_corners_n(const orc_config *c, const float *pos, int64_t n, int64_t *idx)
+{
+#pragma omp parallel
+    {
+        double *w = (double *)malloc(sizeof(double) * 8 * (size_t)(c->n_levels > 0 ? c->n_levels : 1));
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < n; ++q)
+            orc_corners(c, pos + 3 * q, idx + q * c->n_levels * 8, w);
+        free(w);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Training: Eq. 3 loss, exact backpropagation, Adam                     */
 /* ------------------------------------------------------------------ */

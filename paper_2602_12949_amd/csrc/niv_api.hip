@@ -321,6 +321,19 @@ niv_status niv_query_half(niv_handle *h, const niv_half_frame *f, const niv_upsa
     return hip_status(upsample_launch(h, f, p, stream));
 }
 
+niv_status niv_corner_indices(niv_handle *h, niv_precision prec, int32_t training, const void *model,
+                              const float *pos, int64_t count, uint32_t *out, hipStream_t stream)
+{
+    if (!h || (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16)) return NIV_ERR_INVALID_ARG;
+    if (h->m.kind < 0) return NIV_ERR_UNSUPPORTED;
+    if (h->m.cfg.n_levels == 0) return NIV_ERR_UNSUPPORTED;
+    if (count < 0 || count >= (int64_t(1) << 28)) return NIV_ERR_INVALID_ARG;
+    if (count == 0) return NIV_OK;
+    if (!model || !pos || !out || !aligned(model, 256) || !aligned(pos, 4) || !aligned(out, 4))
+        return NIV_ERR_INVALID_ARG;
+    return hip_status(launch_trace_corners(h->m, prec, training != 0, model, pos, count, out, stream));
+}
+
 niv_status niv_fallback_sizes(const niv_handle *h, int64_t max_flagged, int64_t *workspace_bytes)
 {
     if (!h || !workspace_bytes || max_flagged < 0 || max_flagged > 0x7fffffff) return NIV_ERR_INVALID_ARG;

@@ -411,9 +411,12 @@ __device__ inline void level_corners(const LV &lv, const double p[3], uint32_t h
 // ~2900 cells is off by ~2e-4 of a cell, below the operand rounding, and
 // trilinear interpolation is continuous across cell faces, so a cell chosen
 // differently at a face gives the same features); else in FP64.
-template <int P, bool F32C = false, class LV>
+// TRACE (inspection only): also stores the grid entry of each corner, in
+// corner order, to trace[0..7].
+template <int P, bool F32C = false, bool TRACE = false, class LV>
 __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t hmask,
-                                      __amdgpu_buffer_rsrc_t rsrc, const float *pf = nullptr)
+                                      __amdgpu_buffer_rsrc_t rsrc, const float *pf = nullptr,
+                                      uint32_t *trace = nullptr)
 {
     constexpr int SH = (P == NIV_FP32) ? 3 : 2;   // log2 of the entry size in bytes
     constexpr uint32_t EB = 1u << SH;
@@ -436,7 +439,9 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
         }
     }
     f2 v[8];
+    [[maybe_unused]] int nt = 0;
     auto ld = [&](uint32_t voff, uint32_t soff) -> f2 {
+        if constexpr (TRACE) trace[nt++] = (voff + soff) >> SH;
         if constexpr (P == NIV_FP32) {
             u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
             return (f2){u2f(w.x), u2f(w.y)};
@@ -505,9 +510,9 @@ __device__ inline LevelRegs load_level(const LevelConst *lp)
     return r;
 }
 
-template <int P>
+template <int P, bool TRACE = false>
 __device__ inline f2 encode_level_vec(const LevelRegs &lv, const double p[3], uint32_t hmask,
-                                      __amdgpu_buffer_rsrc_t rsrc)
+                                      __amdgpu_buffer_rsrc_t rsrc, uint32_t *trace = nullptr)
 {
     constexpr int SH = (P == NIV_FP32) ? 3 : 2;
     constexpr uint32_t EB = 1u << SH;
@@ -521,7 +526,9 @@ __device__ inline f2 encode_level_vec(const LevelRegs &lv, const double p[3], ui
         ci[a] = c;
         fr[a] = (float)(s - (double)c);
     }
+    [[maybe_unused]] int nt = 0;
     auto ld = [&](uint32_t voff) -> f2 {
+        if constexpr (TRACE) trace[nt++] = voff >> SH;
         if constexpr (P == NIV_FP32) {
             u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, 0, 0);
             return (f2){u2f(w.x), u2f(w.y)};

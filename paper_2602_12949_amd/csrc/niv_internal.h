@@ -120,6 +120,11 @@ LaunchTune default_tune(int kind, niv_precision prec);
 hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
                         hipStream_t stream);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t stream);
+struct Box6 {
+    double v[6];  // lo x, y, z, hi x, y, z
+};
+hipError_t launch_trace_corners(const Model &m, niv_precision prec, bool train, const void *model,
+                                const float *pos, int64_t count, uint32_t *out, hipStream_t stream);
 
 // Joint bilateral upsampling (upsample.hip).
 struct UpsampleArgs {

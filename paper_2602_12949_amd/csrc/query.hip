@@ -228,6 +228,81 @@ hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const 
     }
 }
 
+// Grid entries the query's encoding reads (inspection): one lane per point,
+// the position clamped to the box as in k_query, then the same encoding
+// function the fused kernel runs for this model and precision, which
+// records each corner's entry.  Non-finite positions give 0xFFFFFFFF.
+template <int P, bool F32C, bool SLICED>
+__global__ __launch_bounds__(256) void k_trace_corners(const uint8_t *__restrict__ model,
+                                                       uint64_t grid_off, uint32_t grid_bytes,
+                                                       uint32_t hmask, const Box6 box,
+                                                       const float *__restrict__ pos, int64_t count,
+                                                       int n_levels, uint32_t *__restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(model + grid_off), (short)0, (int)grid_bytes, 0x00020000);
+    const LevelConst *lvs = reinterpret_cast<const LevelConst *>(model);
+    const float px = pos[3 * q], py = pos[3 * q + 1], pz = pos[3 * q + 2];
+    uint32_t *o = out + q * n_levels * 8;
+    if (!(__builtin_isfinite(px) && __builtin_isfinite(py) && __builtin_isfinite(pz))) {
+        for (int k = 0; k < n_levels * 8; ++k) o[k] = 0xFFFFFFFFu;
+        return;
+    }
+    double p[3] = {px, py, pz};
+    for (int c = 0; c < 3; ++c)
+        p[c] = p[c] < box.v[c] ? box.v[c] : (p[c] > box.v[3 + c] ? box.v[3 + c] : p[c]);
+    const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
+    for (int l = 0; l < n_levels; ++l) {
+        f2 f;
+        if constexpr (SLICED) {
+            const LevelRegs lc = load_level(lvs + l);
+            f = encode_level_vec<P, true>(lc, p, hmask, rsrc, o + 8 * l);
+        } else {
+            f = encode_level_buf<P, F32C, true>(lvs[l], p, hmask, rsrc, pf, o + 8 * l);
+        }
+        (void)f;
+    }
+}
+
+hipError_t launch_trace_corners(const Model &m, niv_precision prec, bool train, const void *model,
+                                const float *pos, int64_t count, uint32_t *out, hipStream_t st)
+{
+    Box6 box;
+    for (int c = 0; c < 3; ++c) {
+        box.v[c] = m.cfg.aabb_min[c];
+        box.v[3 + c] = m.cfg.aabb_max[c];
+    }
+    const OpLayout L = op_layout(m.kind, prec);
+    const uint64_t goff = (uint64_t)L.grid_off;
+    const uint32_t gbytes = (uint32_t)(m.n_grid_values * (prec == NIV_FP32 ? 4 : 2));
+    const uint32_t hmask = (uint32_t)((int64_t(1) << m.cfg.log2_T) - 1);
+    const uint8_t *md = static_cast<const uint8_t *>(model);
+    const dim3 grid((unsigned)((count + 255) / 256)), blk(256);
+    const int nl = m.cfg.n_levels;
+    const bool sliced = m.kind == kWide6D && prec != NIV_FP32;
+    if (prec == NIV_FP32)
+        hipLaunchKernelGGL((k_trace_corners<NIV_FP32, false, false>), grid, blk, 0, st, md, goff, gbytes,
+                           hmask, box, pos, count, nl, out);
+    else if (sliced && prec == NIV_FP16)
+        hipLaunchKernelGGL((k_trace_corners<NIV_FP16, false, true>), grid, blk, 0, st, md, goff, gbytes,
+                           hmask, box, pos, count, nl, out);
+    else if (sliced)
+        hipLaunchKernelGGL((k_trace_corners<NIV_BF16, false, true>), grid, blk, 0, st, md, goff, gbytes,
+                           hmask, box, pos, count, nl, out);
+    else if (prec == NIV_FP16 && !train)
+        hipLaunchKernelGGL((k_trace_corners<NIV_FP16, true, false>), grid, blk, 0, st, md, goff, gbytes,
+                           hmask, box, pos, count, nl, out);
+    else if (prec == NIV_FP16)
+        hipLaunchKernelGGL((k_trace_corners<NIV_FP16, false, false>), grid, blk, 0, st, md, goff, gbytes,
+                           hmask, box, pos, count, nl, out);
+    else
+        hipLaunchKernelGGL((k_trace_corners<NIV_BF16, false, false>), grid, blk, 0, st, md, goff, gbytes,
+                           hmask, box, pos, count, nl, out);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ p, int n)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;

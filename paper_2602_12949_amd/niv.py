@@ -114,6 +114,7 @@ def lib():
         L.niv_upsample.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), vp]
         L.niv_query_half.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), C.c_int, vp]
         L.niv_fallback_sizes.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.niv_corner_indices.argtypes = [vp, C.c_int, C.c_int32, vp, vp, C.c_int64, vp, vp]
         L.niv_query_fallback.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
                                          C.POINTER(Fallback), vp, C.c_int64, vp]
         L.niv_query_fallback_noalloc.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
@@ -349,6 +350,15 @@ class NIV:
         p = params or self.upsample_params()
         _check(lib().niv_query_half(self._h, C.byref(f), C.byref(p), _prec(prec), _stream()),
                "niv_query_half")
+
+    def corner_indices(self, pos, model, prec="fp32", training=False):
+        """niv_corner_indices: grid entries [n, L, 8] (int32 tensor) read by the
+        query's encoding at `prec` for each position."""
+        n = pos.numel() // 3
+        out = torch.empty((n, self.cfg["n_levels"], 8), dtype=torch.int32, device=pos.device)
+        _check(lib().niv_corner_indices(self._h, _prec(prec), int(bool(training)), _ptr(model), _ptr(pos),
+                                        n, _ptr(out), _stream()), "niv_corner_indices")
+        return out
 
     def fallback_workspace(self, max_flagged, device="cuda"):
         nb = C.c_int64()

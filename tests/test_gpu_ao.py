@@ -126,11 +126,11 @@ def test_no_triangles_and_empty_frames():
 
 
 @pytest.mark.parametrize("rays", [16])
-def test_room_4k_6d_full_size(rays):
+def test_room_4k_6d_full_size(rays, workload_gbuffer):
     """The 3840x2160 frame of the field workload: sampled pixels near the
     meshes against the oracle, at the bench's settings."""
     w = get_workload("room_4k_6d")
-    _, g = make_workload_gbuffer(w)
+    _, g = workload_gbuffer("room_4k_6d")
     meshes = workload_meshes(w)
     tris = mesh_triangles(meshes)
     pos = g["pos"].reshape(-1, 3).astype(np.float32)

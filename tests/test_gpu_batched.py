@@ -419,10 +419,8 @@ def test_batched_8_rooms_full_size(eight_rooms):
 
 # ------------------------------------------------------------ 4K scene-variable field
 @pytest.fixture(scope="module")
-def room_4k():
-    from niv_synth import make_workload_gbuffer
-    w = get_workload("room_4k_6d")
-    return w, make_workload_gbuffer(w)
+def room_4k(workload_gbuffer):
+    return get_workload("room_4k_6d"), workload_gbuffer("room_4k_6d")
 
 
 def test_room_4k_6d_full_size(room_4k):

@@ -182,11 +182,10 @@ def test_invalid_arguments_rejected(unit_cube):
 
 
 @pytest.fixture(scope="module")
-def room():
+def room(workload_gbuffer):
     w = get_workload("room_1080p")
     oc = O.config_from_workload(w)
-    W, H = w.frames[0]
-    scene, g = make_room_gbuffer(w.scene_seeds[0], W, H)
+    scene, g = workload_gbuffer("room_1080p")
     params = make_params(O.n_grid_values(oc), O.mat_shapes(oc), w.param_seed, *w.grid_init)
     return w, oc, g, params
 

@@ -634,3 +634,36 @@ def test_grid_free_mlp_matches_numpy():
     for W in mats[:-1]:
         h = np.maximum(h @ W.T, 0.0)
     np.testing.assert_allclose(E, h @ mats[-1].T, rtol=1e-12, atol=1e-14)
+
+
+def test_corners_many_equals_brute_force():
+    """The batched corner indices (used for the GPU's bit-exact index check)
+    against the per-point routine and a brute-force Python formula: cell
+    floor((p - lo) N / (hi - lo)) clamped to N - 1, dense x + (N+1)(y +
+    (N+1) z) or the 32-bit XOR hash of the primes 1, 2654435761, 805459861
+    masked to T - 1; room box (dense and hashed levels) and T = 2^19."""
+    for name in ("room_1080p", "room_4k_6d"):
+        c = O.config_from_workload(get_workload(name))
+        tab = O.level_table(c)
+        lo = np.array(c.aabb_min[:3]); hi = np.array(c.aabb_max[:3])
+        rng = np.random.default_rng(17)
+        pts = rng.uniform(lo - 0.5, hi + 0.5, size=(300, 3)).astype(np.float32)
+        pts[:4] = [lo, hi, [hi[0], lo[1], hi[2]], (lo + hi) / 2]
+        many = O.corners_many(c, pts)
+        T = 1 << c.log2_T
+        for q, p in enumerate(pts):
+            idx, _ = O.corners(c, p)
+            np.testing.assert_array_equal(many[q], idx)
+            pc = np.clip(p.astype(np.float64), lo, hi)
+            for l in (0, 3, 4, 9, 15):
+                N = int(tab["res"][l])
+                s = (pc - lo) * N / (hi - lo)
+                i = np.minimum(np.floor(s).astype(np.int64), N - 1)
+                for k in range(8):
+                    v = [int(i[a]) + ((k >> a) & 1) for a in range(3)]
+                    if tab["dense"][l]:
+                        want = v[0] + (N + 1) * (v[1] + (N + 1) * v[2])
+                    else:
+                        h = ((v[0] * 1) ^ (v[1] * 2654435761) ^ (v[2] * 805459861)) & 0xFFFFFFFF
+                        want = h & (T - 1)
+                    assert many[q, l, k] == want, (name, q, l, k)
