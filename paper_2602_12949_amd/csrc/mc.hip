@@ -89,6 +89,26 @@ struct Motion4 {
 };
 typedef const __attribute__((address_space(4))) Motion4 *ConstMotion;
 
+// Trace list of a static scene (built by mc_scene_create): the boxes, then
+// the rectangles grouped by axis, then the disks, each list in primitive
+// order and each record 32 bytes with the primitive's index, so that the
+// closest-hit loop runs one kind at a time without a branch on the kind.
+struct TraceRec {
+    float a[3];      // box: min corner; rectangle: centre (plane coordinate on its axis)
+    int32_t idx;     // primitive index
+    float b[3];      // box: max corner; rectangle: half extents u, v, then the facing sign
+    int32_t pad;
+};
+static_assert(sizeof(TraceRec) == 32, "trace record is 32 bytes");
+typedef const __attribute__((address_space(4))) TraceRec *ConstRecs;
+
+struct SceneRefs {
+    ConstPrims prims;
+    int32_t n_prims;
+    ConstRecs recs;        // null: test every primitive in order (moving scenes)
+    int32_t nb, nr[3], nd;
+};
+
 // the ray origin moved by -shift (a primitive translated by shift is tested
 // with the translated ray: same distance, side and normal)
 __device__ inline Ray shifted(const Ray &r, float sx, float sy, float sz)
@@ -138,59 +158,87 @@ __device__ inline void prim_hit(ConstPrims prims, int k, const Ray &r, float &be
     }
 }
 
+// Static scenes: closest hit over the trace list.  Boxes come first in
+// primitive order with a strict comparison; rectangles and disks then take a
+// hit at the same distance only from a lower primitive index, so ties go to
+// the lowest index exactly as in one scan over the primitives.
+__device__ inline void trace_list(const SceneRefs &sc, const Ray &r, float &best, int &bp, bool &bback)
+{
+    ConstRecs rb = sc.recs;
+#pragma unroll 2
+    for (int k = 0; k < sc.nb; ++k) {
+        const float x1 = slab(rb[k].a[0], r, 0), x2 = slab(rb[k].b[0], r, 0);
+        const float y1 = slab(rb[k].a[1], r, 1), y2 = slab(rb[k].b[1], r, 1);
+        const float z1 = slab(rb[k].a[2], r, 2), z2 = slab(rb[k].b[2], r, 2);
+        const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
+        const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
+        const bool front = tn > 0.0f;
+        const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
+        const bool take = (tn <= tf) && (t > 0.0f) && (t < best);
+        best = take ? t : best;
+        bp = take ? rb[k].idx : bp;
+        bback = take ? !front : bback;
+    }
+    rb += sc.nb;
+    auto rects = [&](auto axis, int n) {
+        constexpr int A = decltype(axis)::value;
+        constexpr int U = A == 2 ? 0 : A + 1, V = A == 0 ? 2 : A - 1;
+        for (int k = 0; k < n; ++k) {
+            const float t = slab(rb[k].a[A], r, A);
+            const float hu = __builtin_fmaf(t, r.d[U], r.o[U]), hv = __builtin_fmaf(t, r.d[V], r.o[V]);
+            const int id = rb[k].idx;
+            const bool take = (t > 0.0f) && ((t < best) || ((t == best) && (id < bp))) &&
+                              (fabsf(hu - rb[k].a[U]) <= rb[k].b[0]) && (fabsf(hv - rb[k].a[V]) <= rb[k].b[1]);
+            best = take ? t : best;
+            bp = take ? id : bp;
+            bback = take ? (r.d[A] * rb[k].b[2] > 0.0f) : bback;
+        }
+        rb += n;
+    };
+    rects(std::integral_constant<int, 0>(), sc.nr[0]);
+    rects(std::integral_constant<int, 1>(), sc.nr[1]);
+    rects(std::integral_constant<int, 2>(), sc.nr[2]);
+    for (int k = 0; k < sc.nd; ++k) {
+        const int id = rb[k].idx;
+        ConstPrims pd = sc.prims + id;
+        const float nx = pd->q[0], ny = pd->q[1], nz = pd->q[2];
+        const float den = r.d[0] * nx + r.d[1] * ny + r.d[2] * nz;
+        const float t = ((pd->p[0] - r.o[0]) * nx + (pd->p[1] - r.o[1]) * ny + (pd->p[2] - r.o[2]) * nz) / den;
+        float r2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float e = __builtin_fmaf(t, r.d[c], r.o[c]) - pd->p[c];
+            r2 = __builtin_fmaf(e, e, r2);
+        }
+        const bool take = (den != 0.0f) && (t > 0.0f) && ((t < best) || ((t == best) && (id < bp))) &&
+                          (r2 <= pd->radius * pd->radius);
+        best = take ? t : best;
+        bp = take ? id : bp;
+        bback = take ? (den > 0.0f) : bback;
+    }
+}
+
 // MOVING: the scene changes with the point's scene variable tv (uniform over
 // the wave): primitive k is translated by tv * motion[k] (motion[k].w != 0
 // marks a moving primitive).
 template <bool MOVING>
-__device__ inline bool trace(ConstPrims prims, int n_prims, const float o[3], const float d[3],
+__device__ inline bool trace(const SceneRefs &sc, const float o[3], const float d[3],
                              Hit &h, ConstMotion motion = nullptr, float tv = 0.0f)
 {
+    ConstPrims prims = sc.prims;
     const Ray r = make_ray(o, d);
     float best = INFINITY;
     int bp = -1;
     bool bback = false;
-    for (int k = 0; k < n_prims; ++k) {
-        if constexpr (MOVING) {
-            if (motion[k].w != 0.0f)
+    if (!MOVING && sc.recs) {
+        trace_list(sc, r, best, bp, bback);
+    } else {
+        for (int k = 0; k < sc.n_prims; ++k) {
+            if (MOVING && motion[k].w != 0.0f)
                 prim_hit(prims, k, shifted(r, tv * motion[k].x, tv * motion[k].y, tv * motion[k].z),
                          best, bp, bback);
             else
                 prim_hit(prims, k, r, best, bp, bback);
-            continue;
-        }
-        // static scenes: the primitive tests written out in the loop
-        const int kind = prims[k].kind;
-        if (kind == 0) {
-            const float x1 = slab(prims[k].p[0], r, 0), x2 = slab(prims[k].q[0], r, 0);
-            const float y1 = slab(prims[k].p[1], r, 1), y2 = slab(prims[k].q[1], r, 1);
-            const float z1 = slab(prims[k].p[2], r, 2), z2 = slab(prims[k].q[2], r, 2);
-            const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
-            const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
-            if (!(tn <= tf)) continue;
-            const bool front = tn > 0.0f;
-            const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
-            if (t > 0.0f && t < best) { best = t; bp = k; bback = !front; }
-        } else if (kind == 1) {
-            const int a = prims[k].axis;
-            if (a == 0) rect_hit<0>(prims, k, r, best, bp, bback);
-            else if (a == 1) rect_hit<1>(prims, k, r, best, bp, bback);
-            else rect_hit<2>(prims, k, r, best, bp, bback);
-        } else {
-            const float nx = prims[k].q[0], ny = prims[k].q[1], nz = prims[k].q[2];
-            const float den = r.d[0] * nx + r.d[1] * ny + r.d[2] * nz;
-            if (den == 0.0f) continue;
-            const float t = ((prims[k].p[0] - r.o[0]) * nx + (prims[k].p[1] - r.o[1]) * ny +
-                             (prims[k].p[2] - r.o[2]) * nz) / den;
-            if (!(t > 0.0f) || !(t < best)) continue;
-            float r2 = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float e = __builtin_fmaf(t, r.d[c], r.o[c]) - prims[k].p[c];
-                r2 = __builtin_fmaf(e, e, r2);
-            }
-            if (r2 > prims[k].radius * prims[k].radius) continue;
-            best = t; bp = k;
-            bback = den > 0.0f;
         }
     }
     h.t = best;
@@ -260,6 +308,8 @@ __device__ inline float light_point(ConstPrims prims, int k, float u1, float u2,
 
 struct McArgs {
     const Prim *prims;
+    const TraceRec *recs;     // trace list of the static scene
+    int32_t nb, nr[3], nd;
     const int32_t *lights;
     const Motion4 *motion;    // [n_prims] (x, y, z, moving) or null
     const float *t;           // [count] scene variable per point or null (0)
@@ -277,12 +327,12 @@ struct McArgs {
 
 // Next-event estimate at y with normal ny toward light j: L cos cos / d^2 A.
 template <bool MOVING>
-__device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy[3],
+__device__ inline bool nee(const SceneRefs &sc, int lk, const float oy[3],
                            const float ny[3], float u1, float u2, float &G, ConstMotion motion,
                            float tv)
 {
     float q[3], nq[3];
-    float A = light_point(prims, lk, u1, u2, q, nq);
+    float A = light_point(sc.prims, lk, u1, u2, q, nq);
     if constexpr (MOVING) {
         q[0] += tv * motion[lk].x; q[1] += tv * motion[lk].y; q[2] += tv * motion[lk].z;
     }
@@ -294,7 +344,7 @@ __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy
     float cq = -(nq[0] * w[0] + nq[1] * w[1] + nq[2] * w[2]);
     if (cy <= 0.0f || cq <= 0.0f) return false;
     Hit hh;
-    if (!trace<MOVING>(prims, n_prims, oy, w, hh, motion, tv) || hh.prim != lk) return false;
+    if (!trace<MOVING>(sc, oy, w, hh, motion, tv) || hh.prim != lk) return false;
     G = cy * cq / d2 * A;
     return true;
 }
@@ -303,11 +353,12 @@ __device__ inline bool nee(ConstPrims prims, int n_prims, int lk, const float oy
 // ...; returns (in every lane) the FP64 sums of the sample values and of
 // their squares, and the back-face count.
 template <bool MOVING>
-__device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int J, float eps,
+__device__ inline void mc_point(const SceneRefs &sc, ConstInts lights, int J, float eps,
                                 const float px[3], const float pn_in[3], int spp, int bounces,
                                 int flags, uint64_t seed, uint64_t point, int lane, double s1[3],
                                 double s2[3], int &backs, ConstMotion motion, float tv)
 {
+    ConstPrims prims = sc.prims;
     const int stride = 2 * J + 2;
     float pn[3] = {pn_in[0], pn_in[1], pn_in[2]};
     const float ln = sqrtf(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
@@ -325,14 +376,14 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
             for (int j = 0; j < J; ++j) {
                 int lk = lights[j];
                 float G;
-                if (nee<MOVING>(prims, np, lk, o, pn, rng.u(2 * j), rng.u(2 * j + 1), G, motion, tv))
+                if (nee<MOVING>(sc, lk, o, pn, rng.u(2 * j), rng.u(2 * j + 1), G, motion, tv))
                     for (int c = 0; c < 3; ++c) val[c] += prims[lk].emission[c] * G;
             }
         } else {
             float d[3];
             cosine_dir(pn, rng.u(0), rng.u(1), d);
             Hit h;
-            bool ok = trace<MOVING>(prims, np, o, d, h, motion, tv);
+            bool ok = trace<MOVING>(sc, o, d, h, motion, tv);
             if (ok && h.back) { backs++; ok = false; }
             if (ok) {
                 float rad[3] = {0.f, 0.f, 0.f};
@@ -351,7 +402,7 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
                         for (int j = 0; j < J; ++j) {
                             int lk = lights[j];
                             float G;
-                            if (nee<MOVING>(prims, np, lk, oy, ny, rng.u(base + 2 * j), rng.u(base + 2 * j + 1), G,
+                            if (nee<MOVING>(sc, lk, oy, ny, rng.u(base + 2 * j), rng.u(base + 2 * j + 1), G,
                                             motion, tv))
                                 for (int c = 0; c < 3; ++c)
                                     rad[c] += beta[c] * rho[c] * 0.318309886183790672f * prims[lk].emission[c] * G;
@@ -362,7 +413,7 @@ __device__ inline void mc_point(ConstPrims prims, int np, ConstInts lights, int 
                     for (int c = 0; c < 3; ++c) beta[c] *= rho[c];
                     if (beta[0] == 0.f && beta[1] == 0.f && beta[2] == 0.f) break;
                     cosine_dir(ny, rng.u(base + 2 * J), rng.u(base + 2 * J + 1), d);
-                    if (!trace<MOVING>(prims, np, oy, d, h, motion, tv) || h.back) break;
+                    if (!trace<MOVING>(sc, oy, d, h, motion, tv) || h.back) break;
                     if (flags & 2)
                         for (int c = 0; c < 3; ++c) rad[c] += beta[c] * prims[h.prim].emission[c];
                     for (int c = 0; c < 3; ++c) { y[c] = oy[c] + h.t * d[c]; ny[c] = h.n[c]; }
@@ -393,14 +444,20 @@ __global__ __launch_bounds__(256) void k_mc_irradiance(const McArgs a)
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= a.count) return;  // whole wave leaves together
-    ConstPrims prims = (ConstPrims)a.prims;
+    SceneRefs sc;
+    sc.prims = (ConstPrims)a.prims;
+    sc.n_prims = a.n_prims;
+    sc.recs = (ConstRecs)a.recs;
+    sc.nb = a.nb;
+    sc.nr[0] = a.nr[0]; sc.nr[1] = a.nr[1]; sc.nr[2] = a.nr[2];
+    sc.nd = a.nd;
     ConstInts lights = (ConstInts)a.lights;
     const float px[3] = {a.x[3 * i], a.x[3 * i + 1], a.x[3 * i + 2]};
     const float pn[3] = {a.nrm[3 * i], a.nrm[3 * i + 1], a.nrm[3 * i + 2]};
     double s1[3], s2[3];
     int backs;
     const float tv = (MOVING && a.t) ? a.t[i] : 0.0f;
-    mc_point<MOVING>(prims, a.n_prims, lights, a.n_lights, a.eps, px, pn, a.spp, a.bounces, a.flags,
+    mc_point<MOVING>(sc, lights, a.n_lights, a.eps, px, pn, a.spp, a.bounces, a.flags,
                      a.seed, (uint64_t)i, lane, s1, s2, backs, (ConstMotion)a.motion, tv);
     if (lane == 0) {
         const double S = (double)a.spp;
@@ -433,7 +490,13 @@ __global__ __launch_bounds__(256) void k_mc_fallback(const FbArgs a)
         const int fi = (int)(code >> 28);
         const int64_t q = code & 0x0fffffffu;
         if (!ka->f[fi].prims) continue;
-        ConstPrims prims = (ConstPrims)ka->f[fi].prims;
+        SceneRefs sc;
+        sc.prims = (ConstPrims)ka->f[fi].prims;
+        sc.n_prims = ka->f[fi].n_prims;
+        sc.recs = (ConstRecs)ka->f[fi].recs;
+        sc.nb = ka->f[fi].nk[0];
+        sc.nr[0] = ka->f[fi].nk[1]; sc.nr[1] = ka->f[fi].nk[2]; sc.nr[2] = ka->f[fi].nk[3];
+        sc.nd = ka->f[fi].nk[4];
         ConstInts lights = (ConstInts)ka->f[fi].lights;
         const float *pos = ka->f[fi].pos, *nrm = ka->f[fi].nrm;
         const float px[3] = {pos[3 * q], pos[3 * q + 1], pos[3 * q + 2]};
@@ -444,11 +507,11 @@ __global__ __launch_bounds__(256) void k_mc_fallback(const FbArgs a)
         // a static scene in such a launch has no motion table and reads none
         const bool moving = MOVING && ka->f[fi].motion != nullptr;
         if (moving)
-            mc_point<MOVING>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
+            mc_point<MOVING>(sc, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
                              a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
                              (ConstMotion)ka->f[fi].motion, ka->f[fi].t);
         else
-            mc_point<false>(prims, ka->f[fi].n_prims, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
+            mc_point<false>(sc, lights, ka->f[fi].n_lights, ka->f[fi].eps, px, pn,
                             a.spp, a.bounces, a.flags, a.seed, (uint64_t)code, lane, s1, s2, backs,
                             nullptr, 0.0f);
         if (lane == 0) {
@@ -540,6 +603,8 @@ struct mc_scene {
     int32_t *d_face_prim = nullptr, *d_face_id = nullptr;
     double *d_cdf = nullptr;
     Motion4 *d_motion = nullptr;   // per primitive (x, y, z, moving), or null: static scene
+    TraceRec *d_recs = nullptr;    // trace list: boxes, rectangles by axis, disks
+    int32_t nk[5] = {0, 0, 0, 0, 0};  // their counts (boxes, rectangles x/y/z, disks)
     int32_t n_prims = 0, n_lights = 0, n_faces = 0;
     double total_area = 0.0;
     float eps = 0.0f;
@@ -556,6 +621,12 @@ void mc_scene_device_view(const struct mc_scene *s, const void **prims, const in
     *n_lights = s ? s->n_lights : 0;
     *eps = s ? s->eps : 0.0f;
     *motion = s ? s->d_motion : nullptr;
+}
+
+void mc_scene_trace_view(const struct mc_scene *s, const void **recs, int32_t nk[5])
+{
+    *recs = s ? s->d_recs : nullptr;
+    for (int k = 0; k < 5; ++k) nk[k] = s ? s->nk[k] : 0;
 }
 
 hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream)
@@ -590,7 +661,42 @@ void release(mc_scene *s)
     (void)hipFree(s->d_face_id);
     (void)hipFree(s->d_cdf);
     (void)hipFree(s->d_motion);
+    (void)hipFree(s->d_recs);
     delete s;
+}
+
+// Trace list of the static scene: boxes, rectangles perpendicular to x, y
+// and z, disks; each list in primitive order.
+niv_status upload_trace_list(mc_scene *s)
+{
+    std::vector<TraceRec> lists[5];
+    for (int k = 0; k < s->n_prims; ++k) {
+        const Prim &p = s->prims[k];
+        TraceRec r;
+        memset(&r, 0, sizeof(r));
+        r.idx = k;
+        if (p.kind == 0) {
+            for (int c = 0; c < 3; ++c) { r.a[c] = p.p[c]; r.b[c] = p.q[c]; }
+            lists[0].push_back(r);
+        } else if (p.kind == 1) {
+            for (int c = 0; c < 3; ++c) r.a[c] = p.p[c];
+            r.b[0] = p.q[0];
+            r.b[1] = p.q[1];
+            r.b[2] = p.sign;
+            lists[1 + p.axis].push_back(r);
+        } else {
+            lists[4].push_back(r);
+        }
+    }
+    std::vector<TraceRec> all;
+    for (int l = 0; l < 5; ++l) {
+        s->nk[l] = (int32_t)lists[l].size();
+        all.insert(all.end(), lists[l].begin(), lists[l].end());
+    }
+    niv_status st = hs(hipMalloc(&s->d_recs, sizeof(TraceRec) * all.size()));
+    if (st == NIV_OK)
+        st = hs(hipMemcpy(s->d_recs, all.data(), sizeof(TraceRec) * all.size(), hipMemcpyHostToDevice));
+    return st;
 }
 // Cumulative-area table of the sampler's surfaces: every rectangle and box
 // face that does not emit and does not move.
@@ -685,6 +791,7 @@ niv_status mc_scene_create(const niv_mc_prim *prims, int32_t n_prims, mc_scene *
         if (st == NIV_OK) st = hs(hipMemcpy(s->d_prims, P, sizeof(Prim) * n_prims, hipMemcpyHostToDevice));
         if (st == NIV_OK) st = hs(hipMemcpy(s->d_lights, lights, sizeof(int32_t) * kMaxLights, hipMemcpyHostToDevice));
         if (st == NIV_OK) st = upload_faces(s, nullptr);
+        if (st == NIV_OK) st = upload_trace_list(s);
     }
     if (st != NIV_OK) {
         release(s);
@@ -734,6 +841,10 @@ niv_status mc_irradiance_at(const mc_scene *s, const float *x, const float *nrm,
     McArgs a;
     memset(&a, 0, sizeof(a));
     a.prims = s->d_prims;
+    a.recs = s->d_recs;
+    a.nb = s->nk[0];
+    for (int c = 0; c < 3; ++c) a.nr[c] = s->nk[1 + c];
+    a.nd = s->nk[4];
     a.lights = s->d_lights;
     a.motion = s->d_motion;
     a.t = t;

@@ -377,6 +377,7 @@ static niv_status query_fallback_into(niv_handle *h, const niv_frame *frames, in
         d.out_L = fr.out_L;
         d.out_flags = fr.out_flags;
         mc_scene_device_view(fr.scene, &d.prims, &d.lights, &d.n_prims, &d.n_lights, &d.eps, &d.motion);
+        mc_scene_trace_view(fr.scene, &d.recs, d.nk);
         d.t = fr.extra_values[0];
     }
     return launch_mc_fallback(b, stream) == hipSuccess ? NIV_OK : NIV_ERR_HIP;

@@ -148,6 +148,8 @@ struct FbFrame {
     const void *prims;        // device primitives of the frame's scene, or null
     const int32_t *lights;
     const void *motion;       // float4 per primitive (scene variable), or null
+    const void *recs;         // trace list of the static scene
+    int32_t nk[5];            // its counts: boxes, rectangles by axis, disks
     int32_t n_prims, n_lights;
     float eps;
     float t;                  // the frame's scene variable (extra value 0)
@@ -163,6 +165,7 @@ struct FbArgs {
 hipError_t launch_mc_fallback(const FbArgs &a, hipStream_t stream);
 void mc_scene_device_view(const struct mc_scene *s, const void **prims, const int32_t **lights,
                           int32_t *n_prims, int32_t *n_lights, float *eps, const void **motion);
+void mc_scene_trace_view(const struct mc_scene *s, const void **recs, int32_t nk[5]);
 
 }  // namespace niv
 
