@@ -411,8 +411,104 @@ __device__ inline void level_corners(const LV &lv, const double p[3], uint32_t h
 // ~2900 cells is off by ~2e-4 of a cell, below the operand rounding, and
 // trilinear interpolation is continuous across cell faces, so a cell chosen
 // differently at a face gives the same features); else in FP64.
+// A level's eight latents in flight: the raw loaded words (FP16/BF16 pairs,
+// or FP32 pairs) and the cell fractions.
+template <int P> struct LevelFetch {
+    typename std::conditional<P == NIV_FP32, u2, uint32_t>::type v[8];
+    float fr[3];
+};
+
+// Issue phase: cell, corner offsets and the eight buffer loads of one level.
+// F32C: cell coordinates in FP32 (the FP16 query: an FP32 coordinate of
+// ~2900 cells is off by ~2e-4 of a cell, below the operand rounding, and
+// trilinear interpolation is continuous across cell faces, so a cell chosen
+// differently at a face gives the same features); else in FP64.
 // TRACE (inspection only): also stores the grid entry of each corner, in
 // corner order, to trace[0..7].
+template <int P, bool F32C = false, bool TRACE = false, class LV>
+__device__ inline void level_issue(const LV &lv, const double p[3], uint32_t hmask,
+                                   __amdgpu_buffer_rsrc_t rsrc, const float *pf, LevelFetch<P> &out,
+                                   uint32_t *trace = nullptr)
+{
+    constexpr int SH = (P == NIV_FP32) ? 3 : 2;   // log2 of the entry size in bytes
+    constexpr uint32_t EB = 1u << SH;
+    int32_t ci[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (F32C) {
+            const float s = __builtin_fmaf(pf[a], lv.kf[a], lv.of[a]);
+            int32_t c = (int32_t)s;            // s > -1: truncation = floor clamped at 0
+            c = c < lv.nm1 ? c : lv.nm1;
+            ci[a] = c;
+            out.fr[a] = s - (float)c;          // exact (Sterbenz)
+        } else {
+            double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+            int32_t c = (int32_t)s;
+            c = c < lv.nm1 ? c : lv.nm1;
+            ci[a] = c;
+            out.fr[a] = (float)(s - (double)c);
+        }
+    }
+    [[maybe_unused]] int nt = 0;
+    auto ld = [&](int c, uint32_t voff, uint32_t soff) {
+        if constexpr (TRACE) trace[nt++] = (voff + soff) >> SH;
+        if constexpr (P == NIV_FP32) out.v[c] = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
+        else out.v[c] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0);
+    };
+    // One set of loads for both storage kinds, with no branch, so that the
+    // loads of consecutive levels can overlap.  Corner c = cx + 2cy + 4cz
+    // reads (xb + cx EB) ^ t_c at scalar offset o_c: a hashed level has
+    // xb = x << SH, t_c = the masked y/z hash terms and o_c its first entry;
+    // a dense level has xb = (x + (N+1)(y + (N+1) z)) << SH, t_c = 0 (mask 0)
+    // and o_c its first entry plus the y/z steps of the corner.
+    const bool dn = lv.dense != 0;
+    const uint32_t bd = ((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH;
+    const uint32_t xb = dn ? bd : ((uint32_t)ci[0] << SH);
+    const uint32_t m = dn ? 0u : (hmask << SH);
+    const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH;
+    const uint32_t y0 = (uint32_t)ci[1] * p1, y1 = y0 + p1;
+    const uint32_t z0 = (uint32_t)ci[2] * p2, z1 = z0 + p2;
+    const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
+    const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
+    const uint32_t o = lv.off << SH;
+    const uint32_t o10 = dn ? (lv.off + lv.s1) << SH : o, o01 = dn ? (lv.off + lv.s2) << SH : o;
+    const uint32_t o11 = dn ? (lv.off + lv.s2 + lv.s1) << SH : o;
+    const uint32_t x0 = xb, x1 = xb + EB;
+    ld(0, x0 ^ t00, o);   ld(1, x1 ^ t00, o);
+    ld(2, x0 ^ t10, o10); ld(3, x1 ^ t10, o10);
+    ld(4, x0 ^ t01, o01); ld(5, x1 ^ t01, o01);
+    ld(6, x0 ^ t11, o11); ld(7, x1 ^ t11, o11);
+}
+
+// Blend phase: the trilinear weights and the FP32 sum of the eight latents.
+template <int P>
+__device__ inline f2 level_blend(const LevelFetch<P> &f)
+{
+    const float wx1 = f.fr[0], wx0 = 1.0f - f.fr[0];
+    const float wy1 = f.fr[1], wy0 = 1.0f - f.fr[1];
+    const float wz1 = f.fr[2], wz0 = 1.0f - f.fr[2];
+    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+    const float w[8] = {wx0 * w00, wx1 * w00, wx0 * w10, wx1 * w10,
+                        wx0 * w01, wx1 * w01, wx0 * w11, wx1 * w11};
+    f2 acc = {0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        f2 v;
+        if constexpr (P == NIV_FP32) v = (f2){u2f(f.v[c].x), u2f(f.v[c].y)};
+        else v = Prec<P>::unpack(f.v[c]);
+        acc.x = __builtin_fmaf(w[c], v.x, acc.x);
+        acc.y = __builtin_fmaf(w[c], v.y, acc.y);
+    }
+    return acc;
+}
+
+// One level fetched and blended in one go, with the storage kind as a branch:
+// the per-level table offset rides in the scalar offset of the load, the
+// hash primes are pre-scaled by the entry size, and dense corners differ
+// only by scalar or immediate offsets (the compiler pairs a dense level's
+// x-neighbours into 8-byte loads).  The FP16 query uses it level by level:
+// there the paired loads (fewer gather instructions) pay more than
+// overlapping the levels' loads (level_issue), measured.
 template <int P, bool F32C = false, bool TRACE = false, class LV>
 __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t hmask,
                                       __amdgpu_buffer_rsrc_t rsrc, const float *pf = nullptr,
@@ -438,25 +534,21 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
             fr[a] = (float)(s - (double)c);
         }
     }
-    f2 v[8];
+    LevelFetch<P> f;
     [[maybe_unused]] int nt = 0;
-    auto ld = [&](uint32_t voff, uint32_t soff) -> f2 {
+    auto ld = [&](int c, uint32_t voff, uint32_t soff) {
         if constexpr (TRACE) trace[nt++] = (voff + soff) >> SH;
-        if constexpr (P == NIV_FP32) {
-            u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
-            return (f2){u2f(w.x), u2f(w.y)};
-        } else {
-            return Prec<P>::unpack(__builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0));
-        }
+        if constexpr (P == NIV_FP32) f.v[c] = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
+        else f.v[c] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0);
     };
     if (lv.dense) {
         const uint32_t b = ((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH;
         const uint32_t o00 = lv.off << SH, o10 = (lv.off + lv.s1) << SH;
         const uint32_t o01 = (lv.off + lv.s2) << SH, o11 = (lv.off + lv.s2 + lv.s1) << SH;
-        v[0] = ld(b, o00); v[1] = ld(b + EB, o00);
-        v[2] = ld(b, o10); v[3] = ld(b + EB, o10);
-        v[4] = ld(b, o01); v[5] = ld(b + EB, o01);
-        v[6] = ld(b, o11); v[7] = ld(b + EB, o11);
+        ld(0, b, o00); ld(1, b + EB, o00);
+        ld(2, b, o10); ld(3, b + EB, o10);
+        ld(4, b, o01); ld(5, b + EB, o01);
+        ld(6, b, o11); ld(7, b + EB, o11);
     } else {
         const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH, m = hmask << SH;
         const uint32_t x0 = (uint32_t)ci[0] << SH, x1 = x0 + EB;
@@ -465,24 +557,13 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
         const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
         const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
         const uint32_t o = lv.off << SH;
-        v[0] = ld(x0 ^ t00, o); v[1] = ld(x1 ^ t00, o);
-        v[2] = ld(x0 ^ t10, o); v[3] = ld(x1 ^ t10, o);
-        v[4] = ld(x0 ^ t01, o); v[5] = ld(x1 ^ t01, o);
-        v[6] = ld(x0 ^ t11, o); v[7] = ld(x1 ^ t11, o);
+        ld(0, x0 ^ t00, o); ld(1, x1 ^ t00, o);
+        ld(2, x0 ^ t10, o); ld(3, x1 ^ t10, o);
+        ld(4, x0 ^ t01, o); ld(5, x1 ^ t01, o);
+        ld(6, x0 ^ t11, o); ld(7, x1 ^ t11, o);
     }
-    const float wx1 = fr[0], wx0 = 1.0f - fr[0];
-    const float wy1 = fr[1], wy0 = 1.0f - fr[1];
-    const float wz1 = fr[2], wz0 = 1.0f - fr[2];
-    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
-    const float w[8] = {wx0 * w00, wx1 * w00, wx0 * w10, wx1 * w10,
-                        wx0 * w01, wx1 * w01, wx0 * w11, wx1 * w11};
-    f2 acc = {0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
-        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
-    }
-    return acc;
+    f.fr[0] = fr[0]; f.fr[1] = fr[1]; f.fr[2] = fr[2];
+    return level_blend<P>(f);
 }
 
 // The same blend for a level that differs between lanes (lane-sliced

@@ -307,23 +307,44 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         if (work && outside) flags |= 1u;
 
         uint32_t *row = stage + lane * O::ROW_DW;
-        if (work) {
-            if constexpr (P == NIV_FP32) {
+        // the FP16 query takes its cell coordinates in FP32
+        constexpr bool F32C = (P == NIV_FP16) && !TRAIN;
+        if constexpr (S::L > 0 && !F32C) {
+            // grid levels for every lane (lanes without work encode the box
+            // corner and store zeros), so that the gathers are not inside a
+            // divergent branch and the next level's loads are in flight while
+            // a level is blended
 #pragma unroll
-                for (int l = 0; l < S::L; ++l) {
-                    f2 f = encode_level_buf<P>(lvs[l], p, a.hash_mask, grid_rsrc);
+            for (int c = 0; c < 3; ++c) p[c] = work ? p[c] : a.lo[c];
+            const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
+            LevelFetch<P> cur, nxt;
+            level_issue<P, F32C>(lvs[0], p, a.hash_mask, grid_rsrc, pf, cur);
+#pragma unroll
+            for (int l = 0; l < S::L; ++l) {
+                if (l + 1 < S::L) level_issue<P, F32C>(lvs[l + 1], p, a.hash_mask, grid_rsrc, pf, nxt);
+                f2 f = level_blend<P>(cur);
+                f.x = work ? f.x : 0.0f;
+                f.y = work ? f.y : 0.0f;
+                if constexpr (P == NIV_FP32) {
                     row[2 * l] = f2u(f.x);
                     row[2 * l + 1] = f2u(f.y);
+                } else if constexpr (O::NS == 2) {
+                    Prec<P>::split(f.x, f.y, row[l], row[O::PART_DW + l]);
+                } else {
+                    row[l] = Prec<P>::pack(f.x, f.y);
                 }
-            } else {
-                // the FP16 query takes its cell coordinates in FP32
-                constexpr bool F32C = (P == NIV_FP16) && !TRAIN;
+                cur = nxt;
+            }
+        }
+        if (work) {
+            if constexpr (S::L > 0 && F32C) {
+                // level by level, the storage kind as a branch (paired 8-byte
+                // loads on dense levels)
                 const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
-                    f2 f = encode_level_buf<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
-                    if constexpr (O::NS == 2) Prec<P>::split(f.x, f.y, row[l], row[O::PART_DW + l]);
-                    else row[l] = Prec<P>::pack(f.x, f.y);
+                    const f2 f = encode_level_buf<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
+                    row[l] = Prec<P>::pack(f.x, f.y);
                 }
             }
             if constexpr (S::PB > 0) {
@@ -398,9 +419,12 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     for (int sp = 0; sp < O::NS; ++sp) row[sp * O::PART_DW + k] = 0u;
             }
         } else {
-            // no bias anywhere: an all-zero input gives E = 0
+            // no bias anywhere: an all-zero input gives E = 0 (the
+            // pipelined grid columns are already zero)
+            constexpr int done = F32C ? 0 : (P == NIV_FP32 ? 2 * S::L : S::L);
 #pragma unroll
-            for (int k = 0; k < O::NS * O::PART_DW; ++k) row[k] = 0u;
+            for (int k = 0; k < O::NS * O::PART_DW; ++k)
+                if (k % O::PART_DW >= done) row[k] = 0u;
         }
         if (f_inputs && live) {
             // in the order of the parameters of W_0
