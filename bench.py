@@ -158,7 +158,19 @@ def setup_1080p(dev):
     w = get_workload("room_1080p")
     Wd, Ht = w.frames[0]
     log(f"[bench] G-buffer {Wd}x{Ht} seed {w.scene_seeds[0]}")
-    _, g = make_room_gbuffer(w.scene_seeds[0], Wd, Ht)
+    # profiling runs start many processes: the G-buffer is kept in /tmp for them
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                         f"niv_bench_room_1080p_{w.scene_seeds[0]}_{Wd}x{Ht}.npz")
+    if os.path.exists(cache):
+        with np.load(cache) as z:
+            g = {k: z[k] for k in z.files}
+    else:
+        _, g = make_room_gbuffer(w.scene_seeds[0], Wd, Ht)
+        try:
+            np.savez(cache + ".tmp.npz", **{k: g[k] for k in ("pos", "nrm", "albedo", "mask")})
+            os.replace(cache + ".tmp.npz", cache)
+        except OSError:
+            pass
     m = NIV(w.model_dict())
     params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -197,6 +209,12 @@ def bench_1080p(args, dev, precs):
         log(f"[bench] room_1080p {prec}: {ms:.4f} ms/frame (launch p50 {np.median(per):.4f}, "
             f"graph p50 {np.median(gper):.4f}), {n_valid / (ms * 1e-3) / 1e9:.3f} G queries/s")
         del graph
+        # the encoding stage alone at the same launch shape: a floor for the query
+        pframe, pouts = m.frame(d["pos"], d["nrm"], prepared, albedo=d["alb"], mask=d["mask"])
+        etotal, eper = time_steps(lambda: m.probe_encode(pframe, prec), args.steps, args.warmup)
+        results[prec]["encode_only"] = {**stats(etotal, eper), "frac_of_query": etotal / ms}
+        log(f"[bench] room_1080p {prec}: encoding stage alone {etotal:.4f} ms ({etotal / ms:.2f} of the query)")
+        del pframe, pouts
     return w, g, params, results, outputs, n_valid, Q
 
 
@@ -232,6 +250,23 @@ def errors_1080p(w, g, params, outputs):
     return errors
 
 
+def host_cpu():
+    """Model and topology of the host CPU (lscpu), for the CPU baseline."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "CPU(s)", "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    info["os_cpu_count"] = os.cpu_count()
+    return info
+
+
 def cpu_baseline_1080p(w, g, params):
     import oracle as O
     oc = O.config_from_workload(w)
@@ -254,6 +289,7 @@ def cpu_baseline_1080p(w, g, params):
     one = (time.perf_counter() - t0) * 16
     O.set_threads(cores)
     return {"value": med * 1e3, "unit": "ms/frame", "cores": cores, "kind": "oracle",
+            "host_cpu": host_cpu(),
             "sample": "three full 1920x1080 frames of room_1080p (FP64 forward, OpenMP over "
                       "pixels), median; plus 1/16 of the frame on one thread, scaled",
             "queries_per_s": n_valid / med, "one_thread_ms_per_frame": one * 1e3,
@@ -322,10 +358,12 @@ def bench_train(args, dev):
     return res
 
 
-def bench_trained(args, dev, steps=2000, batch=1 << 16, spp=64):
+def bench_trained(args, dev, steps=4000, batch=1 << 18, spp=256, checkpoints=(500, 1000, 2000)):
     """The on-GPU-trained model judged by the estimator: bake room_train for
-    `steps` steps, then held-out relative L2 against 4096-spp Monte Carlo on
-    2^16 points, next to Monte Carlo at 1 sample per point."""
+    `steps` steps of `batch` points at `spp` samples (the workload's stated
+    configuration), then held-out relative L2 against 4096-spp Monte Carlo on
+    2^16 points (also at the checkpoints), next to Monte Carlo at 1 sample
+    per point at a similar cost."""
     import torch
     from niv_synth import get_workload, make_params, make_room
     from paper_2602_12949_amd import NIV
@@ -341,12 +379,19 @@ def bench_trained(args, dev, steps=2000, batch=1 << 16, spp=64):
     Eh, _, _, vh = bk.scene.irradiance(hx, hn, 4096, 3, 1, 199)
     Eh = Eh.float()
     err0 = held_out_error(m, bk.trainer.model, "fp16", hx, hn, Eh, vh)
+    curve = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bk.run(steps)
+    for s in range(1, steps + 1):
+        bk.step(s, steps)
+        if s in checkpoints:
+            e = held_out_error(m, bk.trainer.model, "fp16", hx, hn, Eh, vh)
+            curve.append({"step": s, "held_out_rel_l2": e[0]})
+            log(f"[bench] bake step {s}: held-out rel-L2 {e[0]:.3f} ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     err1 = held_out_error(m, bk.trainer.model, "fp16", hx, hn, Eh, vh)
+    curve.append({"step": steps, "held_out_rel_l2": err1[0]})
     qt, _ = time_steps(lambda: m.query(hx, hn, bk.trainer.model, "fp16"), 20, 3)
     mt, _ = time_steps(lambda: bk.scene.irradiance(hx, hn, 1, 3, 1, 777), 5, 1)
     E1, _, _, _ = bk.scene.irradiance(hx, hn, 1, 3, 1, 778)
@@ -355,10 +400,12 @@ def bench_trained(args, dev, steps=2000, batch=1 << 16, spp=64):
     log(f"[bench] trained model: {steps} steps x {batch} at {spp} spp in {dt:.1f} s; held-out "
         f"rel-L2 {err0[0]:.3f} -> {err1[0]:.3f}; query {qt:.3f} ms vs 1-spp MC {mt:.3f} ms "
         f"(rel-L2 {mc1:.3f})")
-    return {"workload": f"room_train baked {steps} steps x {batch} points at {spp} spp (FP16), "
-                        "judged on 2^16 held-out points against 4096-spp Monte Carlo",
-            "bake_s": dt, "held_out_rel_l2_before": err0[0], "held_out_rel_l2": err1[0],
-            "held_out_relmse": err1[1], "valid_fraction": float(vh.float().mean().item()),
+    return {"workload": f"room_train baked {steps} steps x {batch} points at {spp} spp, 3 bounces "
+                        "(FP16), judged on 2^16 held-out points against 4096-spp Monte Carlo",
+            "bake_s": dt, "samples_per_s": steps * batch / dt,
+            "held_out_rel_l2_before": err0[0], "held_out_rel_l2": err1[0],
+            "held_out_relmse": err1[1], "curve": curve,
+            "valid_fraction": float(vh.float().mean().item()),
             "query_ms": qt, "mc_1spp_ms": mt, "mc_1spp_rel_l2": mc1}
 
 
@@ -627,10 +674,15 @@ def profile_case(case, steps, tune=None):
         for _ in range(steps):   # warm-up: clocks and caches as in the timed loop of the bench
             m.query_frames([f], prec)
         torch.cuda.synchronize()
-        for _ in range(steps):
-            m.query_frames([f], prec)
+        # the traced launches, timed in this process with HIP events on the launch stream
+        total, per = time_steps(lambda: m.query_frames([f], prec), steps, 0)
+        log(f"[profile] {case}: {steps} launches, HIP events in this process: mean {total:.4f} ms, "
+            f"p50 {np.median(per):.4f} ms per launch")
+        # then the encoding stage alone at the same launch shape
+        pf, _ = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"])
+        total, per = time_steps(lambda: m.probe_encode(pf, prec), steps, steps)
+        log(f"[profile] {case}: encoding stage alone, HIP events: mean {total:.4f} ms per launch")
         torch.cuda.synchronize()
-        log(f"[profile] {case}: {steps} launches")
         return
     if case in ("train_step", "mc"):
         from niv_synth import get_workload, make_params, make_room
@@ -644,17 +696,16 @@ def profile_case(case, steps, tune=None):
                                    device=dev)
         E = torch.empty((B, 3), dtype=torch.float32, device=dev)
         valid = torch.empty(B, dtype=torch.uint8, device=dev)
-        reps = steps if case == "train_step" else max(1, steps // 10)
-        for k in range(reps):
-            scene.targets(x, n, 256, 3, seed=2 + k, out=(E, valid))
-            if case == "mc" and k == 0:
-                torch.cuda.synchronize()
-        if case == "train_step":
-            tr = Trainer(m, torch.from_numpy(params).to(dev), "fp16", max_batch=B)
-            for _ in range(steps):
-                tr.step(x, n, E, 1e-3, valid=valid)
-        torch.cuda.synchronize()
-        log(f"[profile] {case}: done")
+        if case == "mc":
+            total, per = time_steps(lambda: scene.targets(x, n, 256, 3, seed=2, out=(E, valid)),
+                                    max(1, steps // 10), 1)
+            log(f"[profile] mc: HIP events in this process: mean {total:.3f} ms per launch")
+            return
+        scene.targets(x, n, 256, 3, seed=2, out=(E, valid))
+        tr = Trainer(m, torch.from_numpy(params).to(dev), "fp16", max_batch=B)
+        total, per = time_steps(lambda: tr.step(x, n, E, 1e-3, valid=valid), steps, steps)
+        log(f"[profile] train_step: HIP events in this process: mean {total:.4f} ms, p50 "
+            f"{np.median(per):.4f} ms per step")
         return
     if case.startswith("pe") and case[2:].isdigit():
         from niv_synth import get_workload, make_params, make_room_gbuffer
@@ -726,6 +777,8 @@ def main():
     ap.add_argument("--precisions", default="fp16,fp32,bf16")
     ap.add_argument("--only", default="query,train,batched,field_4k,table1,half",
                     help="comma list of parts to run")
+    ap.add_argument("--bake-steps", type=int, default=4000,
+                    help="steps of the stated room_train bake (2^18 points x 256 spp each)")
     ap.add_argument("--profile", default=None, help="run one kernel case for rocprofv3")
     ap.add_argument("--tune", default=None,
                     help="launch shape for --profile: block,blocks_per_cu,xcd_order")
@@ -763,6 +816,13 @@ def main():
     }
     for b in bounds.values():
         b["frac"] = b["achieved"] / b["peak"]
+    enc = results[head]["encode_only"]["ms"]
+    bounds["encode"] = {"achieved": n_valid / (ms * 1e-3) / 1e9, "peak": n_valid / (enc * 1e-3) / 1e9,
+                        "unit": "G queries/s", "per_query": "128 latent gathers + blends",
+                        "peak_kind": "measured: the query's encoding stage alone (niv_probe_encode), "
+                                     "same frame and launch shape"}
+    for b in bounds.values():
+        b["frac"] = b["achieved"] / b["peak"]
     bound = max(bounds, key=lambda k: bounds[k]["frac"])
     traffic = measured_traffic(f"k_query {head} room_1080p")
     roof = {"bound": bound, "achieved": bounds[bound]["achieved"], "peak": bounds[bound]["peak"],
@@ -776,7 +836,10 @@ def main():
     extra = {}
     if "train" in parts:
         extra["train"] = bench_train(args, dev)
-        extra["trained_model"] = bench_trained(args, dev)
+        extra["trained_model"] = bench_trained(args, dev, steps=args.bake_steps)
+        # a short bake of a quarter of the points at a quarter of the samples
+        extra["trained_model_reduced"] = bench_trained(args, dev, steps=2000, batch=1 << 16, spp=64,
+                                                       checkpoints=())
     if "batched" in parts:
         extra["batched"] = bench_batched(args, dev)
     if "field_4k" in parts:

@@ -153,6 +153,16 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames,
 niv_status niv_corner_indices(niv_handle *h, niv_precision prec, int32_t training, const void *model,
                               const float *pos, int64_t count, uint32_t *out, hipStream_t stream);
 
+/* Measurement: the encoding stage of niv_query alone (grid gathers and
+ * trilinear blends, spherical harmonics), with the query's launch shape,
+ * pixel order and encoding functions, for one frame of a 16-level room model
+ * (other shapes: NIV_ERR_UNSUPPORTED).  Instead of running the network it
+ * writes one word per pixel, the XOR of the encoded input, to out_E[3 q]
+ * (the rest of out_E, out_L and out_flags are not written).  Its time is a
+ * floor for the fused query's time on the same frame. */
+niv_status niv_probe_encode(niv_handle *h, const niv_frame *frame, niv_precision prec,
+                            hipStream_t stream);
+
 /* Monte Carlo fallback for pixels the network should not answer: after the
  * query, pixels whose flags intersect `flag_mask` (bits 0, 2 and 4 of
  * out_flags) or whose in_flags are set are appended to a list, and

@@ -236,6 +236,19 @@ niv_status niv_query(niv_handle *h, const niv_frame *frames, int32_t n_frames, n
     return NIV_OK;
 }
 
+niv_status niv_probe_encode(niv_handle *h, const niv_frame *frame, niv_precision prec,
+                            hipStream_t stream)
+{
+    niv_status s = check_frames(h, frame, 1, prec);
+    if (s != NIV_OK) return s;
+    if (h->m.kind != kRoom) return NIV_ERR_UNSUPPORTED;
+    const LaunchTune tu = tune_of(h, prec);
+    QueryArgs a;
+    fill_args(h, frame, 1, prec, a);
+    a.xcd_order = tu.xcd_order;
+    return hip_status(launch_query_probe(h->m, a, prec, tu, stream));
+}
+
 // ---------------------------------------------------------------- half resolution
 static niv_status check_half(const niv_handle *h, const niv_half_frame *f,
                              const niv_upsample_params *p)

@@ -116,10 +116,15 @@ struct Model {
 OpLayout op_layout(int kind, niv_precision prec);
 hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
                           niv_precision prec, hipStream_t stream);
+// The weight operands of a prepared model only (trainable shapes, FP32/FP16).
+hipError_t launch_prepare_operands(const Model &m, const float *params, void *prepared,
+                                   niv_precision prec, hipStream_t stream);
 LaunchTune default_tune(int kind, niv_precision prec);
 hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
                         hipStream_t stream);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t stream);
+hipError_t launch_query_probe(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
+                              hipStream_t stream);
 struct Box6 {
     double v[6];  // lo x, y, z, hi x, y, z
 };

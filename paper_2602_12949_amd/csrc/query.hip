@@ -103,6 +103,33 @@ static hipError_t prepare_t(const Model &m, const float *params, void *prepared,
     return hipGetLastError();
 }
 
+template <int P, class S>
+static hipError_t prepare_operands_t(const Model &m, const float *params, void *prepared, hipStream_t st)
+{
+    using O = Ops<P, S>;
+    int threads = O::N_OPS * 64;
+    hipLaunchKernelGGL((k_prepare_operands<P, S>), dim3((threads + 255) / 256), dim3(256), 0, st,
+                       params, static_cast<uint8_t *>(prepared) + kLevelBytes, m.n_grid_values,
+                       m.cfg.n_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_operands(const Model &m, const float *params, void *prepared,
+                                   niv_precision prec, hipStream_t st)
+{
+#define NIV_PREPO(P)                                                                          \
+    switch (m.kind) {                                                                         \
+    case kUnitCube: return prepare_operands_t<P, ShapeUnitCube>(m, params, prepared, st);    \
+    case kRoom: return prepare_operands_t<P, ShapeRoom>(m, params, prepared, st);            \
+    case kRoom6D: return prepare_operands_t<P, ShapeRoom6D>(m, params, prepared, st);        \
+    default: return hipErrorInvalidValue;                                                     \
+    }
+    if (prec == NIV_FP32) { NIV_PREPO(NIV_FP32) }
+    if (prec == NIV_FP16) { NIV_PREPO(NIV_FP16) }
+    return hipErrorInvalidValue;
+#undef NIV_PREPO
+}
+
 hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
                           niv_precision prec, hipStream_t st)
 {
@@ -132,11 +159,11 @@ template <int P, class S, bool WLDS, int BLOCK> constexpr size_t query_lds()
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
 
-template <int P, class S, bool WLDS, int TB, int BLOCK>
+template <int P, class S, bool WLDS, int TB, int BLOCK, bool PROBE = false>
 static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
 {
     constexpr int kWavesPerBlock = BLOCK / 64;
-    auto kern = k_query<P, S, WLDS, TB, false, BLOCK>;
+    auto kern = k_query<P, S, WLDS, TB, false, BLOCK, PROBE>;
     constexpr size_t lds = query_lds<P, S, WLDS, BLOCK>();
     static_assert(lds <= kLdsPerCu, "workgroup LDS");
     static int max_blocks = -1;  // resident workgroups per CU for this instantiation
@@ -181,6 +208,27 @@ static hipError_t query_b(QueryArgs &a, const LaunchTune &tu, hipStream_t st)
         if (tu.block == 256) return query_t<P, S, WLDS, TB, 256>(a, tu.blocks_per_cu, st);
         return query_t<P, S, WLDS, TB, 512>(a, tu.blocks_per_cu, st);
     }
+}
+
+// The encoding stage alone (measurement), room model, at the query's launch shape.
+template <int P>
+static hipError_t probe_b(QueryArgs &a, const LaunchTune &tu, hipStream_t st)
+{
+    if constexpr (query_lds<P, ShapeRoom, true, 512>() > kLdsPerCu) {
+        return query_t<P, ShapeRoom, true, 4, 256, true>(a, tu.blocks_per_cu, st);
+    } else {
+        if (tu.block == 256) return query_t<P, ShapeRoom, true, 4, 256, true>(a, tu.blocks_per_cu, st);
+        return query_t<P, ShapeRoom, true, 4, 512, true>(a, tu.blocks_per_cu, st);
+    }
+}
+
+hipError_t launch_query_probe(const Model &m, QueryArgs &a, niv_precision prec, const LaunchTune &tu,
+                              hipStream_t st)
+{
+    if (m.kind != kRoom) return hipErrorInvalidValue;
+    if (prec == NIV_FP32) return probe_b<NIV_FP32>(a, tu, st);
+    if (prec == NIV_FP16) return probe_b<NIV_FP16>(a, tu, st);
+    return probe_b<NIV_BF16>(a, tu, st);
 }
 
 LaunchTune default_tune(int kind, niv_precision prec)

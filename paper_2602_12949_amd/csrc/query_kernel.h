@@ -30,10 +30,23 @@
 
 namespace niv {
 
+// LDS accesses of one wave complete in order; the fences keep the compiler
+// from moving LDS reads and writes of the wave across this point.
+__device__ inline void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- fused query
-template <int P, class S, bool WLDS, int TB, bool TRAIN, int BLOCK>
+// PROBE (measurement only): the encoding stage alone, with the launch shape,
+// pixel order and encoding functions of the query, writing one word per
+// pixel (E[3q]) instead of running the network.
+template <int P, class S, bool WLDS, int TB, bool TRAIN, int BLOCK, bool PROBE = false>
 __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
 {
+    static_assert(!PROBE || (!TRAIN && !S::SL), "probe: staged query encoding");
     constexpr int kWavesPerBlock = BLOCK / 64;
     using O = Ops<P, S>;
     static_assert(!TRAIN || (TB == 4 && P != NIV_BF16), "training: four tiles, FP32 or FP16");
@@ -309,7 +322,11 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         uint32_t *row = stage + lane * O::ROW_DW;
         // the FP16 query takes its cell coordinates in FP32
         constexpr bool F32C = (P == NIV_FP16) && !TRAIN;
-        if constexpr (S::L > 0 && !F32C) {
+        // the FP32 and BF16 queries overlap the levels' gathers; the FP16
+        // query and the training forward go level by level (measured faster:
+        // paired dense loads, and the training kernel's registers)
+        constexpr bool PIPE = !F32C && !TRAIN;
+        if constexpr (S::L > 0 && PIPE) {
             // grid levels for every lane (lanes without work encode the box
             // corner and store zeros), so that the gathers are not inside a
             // divergent branch and the next level's loads are in flight while
@@ -337,14 +354,21 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             }
         }
         if (work) {
-            if constexpr (S::L > 0 && F32C) {
+            if constexpr (S::L > 0 && !PIPE) {
                 // level by level, the storage kind as a branch (paired 8-byte
                 // loads on dense levels)
                 const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
                     const f2 f = encode_level_buf<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
-                    row[l] = Prec<P>::pack(f.x, f.y);
+                    if constexpr (P == NIV_FP32) {
+                        row[2 * l] = f2u(f.x);
+                        row[2 * l + 1] = f2u(f.y);
+                    } else if constexpr (O::NS == 2) {
+                        Prec<P>::split(f.x, f.y, row[l], row[O::PART_DW + l]);
+                    } else {
+                        row[l] = Prec<P>::pack(f.x, f.y);
+                    }
                 }
             }
             if constexpr (S::PB > 0) {
@@ -421,7 +445,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         } else {
             // no bias anywhere: an all-zero input gives E = 0 (the
             // pipelined grid columns are already zero)
-            constexpr int done = F32C ? 0 : (P == NIV_FP32 ? 2 * S::L : S::L);
+            constexpr int done = !PIPE ? 0 : (P == NIV_FP32 ? 2 * S::L : S::L);
 #pragma unroll
             for (int k = 0; k < O::NS * O::PART_DW; ++k)
                 if (k % O::PART_DW >= done) row[k] = 0u;
@@ -460,6 +484,13 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                     reinterpret_cast<uint16_t *>(xs)[(2 * k + 1) * 64 + lane] = (uint16_t)(row[k] >> 16);
                 }
             }
+        }
+        if constexpr (PROBE) {
+            uint32_t xo = 0u;
+#pragma unroll
+            for (int k = 0; k < O::NS * O::PART_DW; ++k) xo ^= row[k];
+            if (live) ka->f[fi].out_E[3 * q] = u2f(xo);
+            continue;
         }
         }  // staged encoding
         // LDS accesses of one wave complete in order; the fence keeps the
@@ -637,23 +668,43 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                             }
                         }
                     if constexpr (TRAIN) {
-                        uint16_t *xs = reinterpret_cast<uint16_t *>(a.x_save + chunk * CHUNK_BYTES) +
-                                       (S::DIN + (layer - 1) * S::W) * 64;
+                        // the layer's input, [neuron][64 samples], through this
+                        // wave's staging block (free once layer 0 has read it)
+                        // in halves of 32 neurons: 2-byte LDS writes, then
+                        // coalesced 16-byte stores
+                        uint8_t *xs = a.x_save + chunk * CHUNK_BYTES + (S::DIN + (layer - 1) * S::W) * 64 * 2;
+                        constexpr int RS = 68;   // halves per staged row (64 samples + padding)
+                        static_assert(32 * RS * 2 <= 64 * O::ROW_DW * 4, "half a layer fits the staging block");
+                        uint16_t *tb16 = reinterpret_cast<uint16_t *>(stage);
                         uint32_t mk[S::W / 32];
 #pragma unroll
                         for (int d = 0; d < S::W / 32; ++d) mk[d] = 0u;
 #pragma unroll
-                        for (int t = 0; t < TB; ++t)
+                        for (int hf = 0; hf < 2; ++hf) {
+                            wave_lds_fence();
 #pragma unroll
-                            for (int ob = 0; ob < S::NOB; ++ob)
+                            for (int t = 0; t < TB; ++t)
 #pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    const uint32_t w2 = bh[0][t][2 * ob + (r >> 1)];
-                                    const uint16_t hv = (uint16_t)((r & 1) ? (w2 >> 16) : (w2 & 0xffffu));
-                                    xs[(16 * ob + 4 * g + r) * 64 + 16 * t + j] = hv;
-                                    const int bit = (t * S::NOB + ob) * 4 + r;
-                                    mk[bit >> 5] |= (hv != 0 ? 1u : 0u) << (bit & 31);
-                                }
+                                for (int ob = 2 * hf; ob < 2 * hf + 2; ++ob)
+#pragma unroll
+                                    for (int r = 0; r < 4; ++r) {
+                                        const uint32_t w2 = bh[0][t][2 * ob + (r >> 1)];
+                                        const uint16_t hv = (uint16_t)((r & 1) ? (w2 >> 16) : (w2 & 0xffffu));
+                                        tb16[(16 * (ob - 2 * hf) + 4 * g + r) * RS + 16 * t + j] = hv;
+                                        const int bit = (t * S::NOB + ob) * 4 + r;
+                                        mk[bit >> 5] |= (hv != 0 ? 1u : 0u) << (bit & 31);
+                                    }
+                            wave_lds_fence();
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const int ci = lane + 64 * i, row = ci >> 3, c = ci & 7;
+                                const u2 lo = *reinterpret_cast<const u2 *>(tb16 + row * RS + 8 * c);
+                                const u2 hi = *reinterpret_cast<const u2 *>(tb16 + row * RS + 8 * c + 4);
+                                *reinterpret_cast<u4 *>(xs + ((32 * hf + row) * 64 + 8 * c) * 2) =
+                                    (u4){lo.x, lo.y, hi.x, hi.y};
+                            }
+                        }
+                        wave_lds_fence();   // the staging block is written again by the next tile
 #pragma unroll
                         for (int d = 0; d < S::W / 32; ++d)
                             a.mask_save[((chunk * S::H + (layer - 1)) * (S::W / 32) + d) * 64 + lane] = mk[d];

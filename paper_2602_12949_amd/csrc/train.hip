@@ -107,12 +107,17 @@ __device__ int64_t bwd_source(int op, int lane, int e, int64_t n_grid)
     return w0 + (int64_t)out_neuron(kb) * S::DIN + 16 * ib + i;
 }
 
+// Also clears the step's words (status, loss) so that a step needs no
+// separate fill launches (and stays capturable).
 template <int P, class S>
 __global__ void k_prepare_bwd(const float *__restrict__ params, uint8_t *__restrict__ out,
-                              int64_t n_grid)
+                              int64_t n_grid, uint32_t *__restrict__ status, int n_status,
+                              float *__restrict__ loss)
 {
     using B = Bwd<P, S>;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < n_status) status[tid] = 0u;
+    if (tid == 0) *loss = 0.0f;
     if (tid >= B::N_OPS * 64) return;
     const int op = tid / 64, lane = tid % 64;
     int64_t off;
@@ -130,13 +135,6 @@ __global__ void k_prepare_bwd(const float *__restrict__ params, uint8_t *__restr
         if constexpr (B::F32) reinterpret_cast<float *>(out + off)[lane * ne + e] = v;
         else reinterpret_cast<_Float16 *>(out + off)[lane * ne + e] = (_Float16)v;
     }
-}
-
-__global__ void k_fill_zero(float *__restrict__ p, int64_t n)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; k < n; k += stride) p[k] = 0.0f;
 }
 
 // ---------------------------------------------------------------- backward
@@ -516,6 +514,7 @@ struct ScatterArgs {
     uint32_t *counts;          // [bins][kScatterBlocks] per workgroup, then their offsets
     uint32_t *bin_start;       // [bins + 1]
     uint32_t *work_start;      // [bins + 1] first accumulating workgroup of each bin
+    uint32_t *split;           // [bins + 1] bins split over several workgroups, in order; [bins] count
     uint32_t *vmax;            // [0] bits of the largest |contribution| of the step (>= 0 floats
                                // order as integers), [1] records of the fullest bin
     long long *parts;          // [accumulating workgroup][2 kBinEntries] fixed-point partial sums
@@ -760,6 +759,32 @@ __global__ __launch_bounds__(1024) void k_grid_scan_totals(const ScatterArgs a)
         __syncthreads();
     }
     for (int b = t; b <= a.n_bins; b += 1024) a.work_start[b] = b > 0 ? v[b - 1] : 0u;
+    // the bins split over several workgroups, in bin order (k_grid_merge)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMaxBins / 1024; ++k) {
+        const int b = t + 1024 * k;
+        v[b] = (b < a.n_bins && tot[k] > kAccumRecords) ? 1u : 0u;
+    }
+    __syncthreads();
+    for (int off = 1; off < kMaxBins; off <<= 1) {
+        uint32_t add[kMaxBins / 1024];
+#pragma unroll
+        for (int k = 0; k < kMaxBins / 1024; ++k) {
+            const int b = t + 1024 * k;
+            add[k] = b >= off ? v[b - off] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxBins / 1024; ++k) v[t + 1024 * k] += add[k];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxBins / 1024; ++k) {
+        const int b = t + 1024 * k;
+        if (b < a.n_bins && tot[k] > kAccumRecords) a.split[v[b] - 1] = (uint32_t)b;
+    }
+    if (t == 0) a.split[a.n_bins] = v[kMaxBins - 1];
     // records of the fullest bin: they bound the fixed-point sums
     __shared__ uint32_t smax;
     if (t == 0) smax = 0u;
@@ -855,15 +880,17 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
 }
 
 // Bins split over several workgroups: their parts' integer sums added in
-// part order, then scaled once.  Workgroup (b, s) takes values 256 s .. 256 s
-// + 255 of bin b; the workgroups of whole bins return at once.
+// part order, then scaled once.  Workgroup (i, s) takes values 256 s .. 256 s
+// + 255 of the i-th split bin; the launch is sized by the most bins that can
+// be split, the workgroups beyond the step's count return at once.
 constexpr int kMergeSlices = 2 * kBinEntries / 256;
 __global__ __launch_bounds__(256) void k_grid_merge(const ScatterArgs a)
 {
-    const int b = blockIdx.x / kMergeSlices;
+    const uint32_t i = blockIdx.x / kMergeSlices;
+    if (i >= a.split[a.n_bins]) return;
+    const int b = (int)a.split[i];
     const int k = (blockIdx.x % kMergeSlices) * 256 + threadIdx.x;
     const uint32_t w0 = a.work_start[b], parts = a.work_start[b + 1] - w0;
-    if (parts <= 1u) return;
     const int64_t en = ((int64_t)b << kBinShift) + (k >> 1);
     if (en >= a.n_entries) return;
     const long long *src = a.parts + (int64_t)w0 * (2 * kBinEntries) + k;
@@ -877,9 +904,14 @@ __global__ __launch_bounds__(256) void k_grid_merge(const ScatterArgs a)
 // bc2 = 1 - beta2^t.
 // With `status` given (a training step), nothing is updated when the step's
 // loss or gradient was not finite (status[2] set by the forward pass).
+// With grid_out given, grid values k < n_grid are also stored, rounded to the
+// model's precision (GP), into the prepared model's grid (the training step
+// then rebuilds only the weight operands).
+template <int GP>
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
                        float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                       float bc1, float bc2, const uint32_t *status)
+                       float bc1, float bc2, const uint32_t *status, uint8_t *__restrict__ grid_out,
+                       int64_t n_grid)
 {
     if (status && status[2] != 0u) return;
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -890,7 +922,12 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, floa
         const float vk = b2 * v[k] + (1.0f - b2) * g * g;
         m[k] = mk;
         v[k] = vk;
-        p[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+        const float pk = p[k] - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+        p[k] = pk;
+        if (grid_out && k < n_grid) {
+            if constexpr (GP == NIV_FP32) reinterpret_cast<float *>(grid_out)[k] = pk;
+            else reinterpret_cast<_Float16 *>(grid_out)[k] = (_Float16)pk;
+        }
     }
 }
 
@@ -934,7 +971,7 @@ __global__ void k_init_params(const InitArgs a)
 // ---------------------------------------------------------------- host side
 struct TrainLayout {
     int64_t bwd_off, x_off, mask_off, dE_off, dx0_off, sflag_off, counts_off, start_off, work_off,
-        vmax_off, keys_off, vals_off, dw_off, parts_off, total;
+        split_off, vmax_off, keys_off, vals_off, dw_off, parts_off, total;
 };
 
 // Accumulating workgroups of a step: at most one per bin plus one per
@@ -966,7 +1003,8 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
     L.counts_off = L.sflag_off + align256(n);
     L.start_off = L.counts_off + align256((int64_t)kMaxBins * kScatterBlocks * 4);
     L.work_off = L.start_off + align256((kMaxBins + 1) * 4);
-    L.keys_off = L.work_off + align256((kMaxBins + 1) * 4);
+    L.split_off = L.work_off + align256((kMaxBins + 1) * 4);
+    L.keys_off = L.split_off + align256((kMaxBins + 1) * 4);
     const int64_t records = n * S::L * 8;
     L.vals_off = L.keys_off + align256(records * 2);
     L.dw_off = L.vals_off + align256(records * 8);
@@ -992,12 +1030,11 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     // captured; every gradient value is stored whole (the grid by the
     // accumulating and merging passes, the MLP by k_dw_sum)
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.vmax_off);
-    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, stream, st.loss, (int64_t)1);
-    hipError_t e = launch_zero_u32(status, kStatusWords, stream);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_prepare_bwd<P, S>), dim3((B::N_OPS * 64 + 255) / 256), dim3(256), 0,
-                       stream, st.params, ws + L.bwd_off, m.n_grid_values);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+                       stream, st.params, ws + L.bwd_off, m.n_grid_values, status, kStatusWords,
+                       st.loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     // 1. forward with saves, loss and d loss / dE (non-finite ones mark the step)
     QueryArgs a;
     memset(&a, 0, sizeof(a));
@@ -1111,6 +1148,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.counts = reinterpret_cast<uint32_t *>(ws + L.counts_off);
     sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
     sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
+    sa.split = reinterpret_cast<uint32_t *>(ws + L.split_off);
     sa.vmax = status;
     sa.parts = reinterpret_cast<long long *>(ws + L.parts_off);
     sa.keys = reinterpret_cast<uint16_t *>(ws + L.keys_off);
@@ -1141,7 +1179,11 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
                        stream, sa);
     const int64_t acc_groups = acc_group_bound(b.count, m.cfg.n_levels, sa.n_bins);
     hipLaunchKernelGGL(k_grid_accum, dim3((unsigned)acc_groups), dim3(1024), 0, stream, sa);
-    hipLaunchKernelGGL(k_grid_merge, dim3((unsigned)(sa.n_bins * kMergeSlices)), dim3(256), 0, stream, sa);
+    // a split bin holds more than kAccumRecords records
+    const int64_t records = b.count * (int64_t)m.cfg.n_levels * 8;
+    const int64_t max_split = std::min<int64_t>(sa.n_bins, records / (kAccumRecords + 1));
+    if (max_split > 0)
+        hipLaunchKernelGGL(k_grid_merge, dim3((unsigned)(max_split * kMergeSlices)), dim3(256), 0, stream, sa);
     return hipGetLastError();
 }
 
@@ -1217,13 +1259,19 @@ static niv_status check_adam(const niv_train_state *st, const niv_adam *ad)
 }
 
 static niv_status adam_launch(const Model &m, const niv_train_state *st, const niv_adam *ad,
-                              const uint32_t *status, hipStream_t stream)
+                              const uint32_t *status, uint8_t *grid_out, niv_precision prec,
+                              hipStream_t stream)
 {
     const double bc1 = 1.0 - pow((double)ad->beta1, (double)ad->step);
     const double bc2 = 1.0 - pow((double)ad->beta2, (double)ad->step);
-    hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, stream, st->params, st->grads, st->adam_m,
-                       st->adam_v, m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps, (float)bc1,
-                       (float)bc2, status);
+    if (prec == NIV_FP32)
+        hipLaunchKernelGGL(k_adam<NIV_FP32>, dim3(2048), dim3(256), 0, stream, st->params, st->grads,
+                           st->adam_m, st->adam_v, m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps,
+                           (float)bc1, (float)bc2, status, grid_out, m.n_grid_values);
+    else
+        hipLaunchKernelGGL(k_adam<NIV_FP16>, dim3(2048), dim3(256), 0, stream, st->params, st->grads,
+                           st->adam_m, st->adam_v, m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps,
+                           (float)bc1, (float)bc2, status, grid_out, m.n_grid_values);
     return hst(hipGetLastError());
 }
 
@@ -1233,7 +1281,7 @@ niv_status niv_adam_update(niv_handle *h, const niv_train_state *st, const niv_a
     if (!h) return NIV_ERR_INVALID_ARG;
     niv_status s = check_adam(st, ad);
     if (s != NIV_OK) return s;
-    return adam_launch(h->m, st, ad, nullptr, stream);
+    return adam_launch(h->m, st, ad, nullptr, nullptr, NIV_FP32, stream);
 }
 
 niv_status niv_train_step(niv_handle *h, const niv_batch *b, const niv_train_state *st,
@@ -1244,10 +1292,13 @@ niv_status niv_train_step(niv_handle *h, const niv_batch *b, const niv_train_sta
     if (s != NIV_OK) return s;
     s = niv_backward(h, b, st, prec, stream);
     if (s != NIV_OK) return s;
-    // the update reads the step's non-finite word and does nothing when it is set
-    s = adam_launch(h->m, st, ad, static_cast<const uint32_t *>(st->workspace), stream);
+    // the update reads the step's non-finite word and does nothing when it is
+    // set; it stores the new grid into the prepared model, whose level table
+    // never changes, so only the weight operands are rebuilt
+    uint8_t *grid_out = static_cast<uint8_t *>(st->model) + op_layout(h->m.kind, prec).grid_off;
+    s = adam_launch(h->m, st, ad, static_cast<const uint32_t *>(st->workspace), grid_out, prec, stream);
     if (s != NIV_OK) return s;
-    return niv_prepare(h, st->params, st->model, prec, stream);
+    return hst(launch_prepare_operands(h->m, st->params, st->model, prec, stream));
 }
 
 niv_status niv_train_status(const niv_train_state *st, hipStream_t stream)

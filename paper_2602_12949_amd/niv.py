@@ -114,6 +114,7 @@ def lib():
         L.niv_upsample.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), vp]
         L.niv_query_half.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), C.c_int, vp]
         L.niv_fallback_sizes.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.niv_probe_encode.argtypes = [vp, C.POINTER(Frame), C.c_int, vp]
         L.niv_corner_indices.argtypes = [vp, C.c_int, C.c_int32, vp, vp, C.c_int64, vp, vp]
         L.niv_query_fallback.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
                                          C.POINTER(Fallback), vp, C.c_int64, vp]
@@ -359,6 +360,12 @@ class NIV:
         _check(lib().niv_corner_indices(self._h, _prec(prec), int(bool(training)), _ptr(model), _ptr(pos),
                                         n, _ptr(out), _stream()), "niv_corner_indices")
         return out
+
+    def probe_encode(self, frame, prec="fp16"):
+        """niv_probe_encode: the query's encoding stage alone on one frame
+        (measurement; writes one word per pixel into the frame's out_E)."""
+        _check(lib().niv_probe_encode(self._h, C.byref(frame), _prec(prec), _stream()),
+               "niv_probe_encode")
 
     def fallback_workspace(self, max_flagged, device="cuda"):
         nb = C.c_int64()
