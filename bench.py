@@ -34,7 +34,7 @@ progress goes to stderr.
 
 `--profile CASE` runs only that case's kernel a few times (for rocprofv3
 counter and trace runs): query_fp16, query_fp32, query_bf16, field_4k,
-train_step, mc, pe16, pe32, pe64, half, copy (a 1 GiB device copy that calibrates
+train_step, mc, pe16, pe32, pe64, half, gather (the gather-rate probes), copy (a 1 GiB device copy that calibrates
 the HBM byte counters).
 """
 import argparse
@@ -330,6 +330,20 @@ def bench_train(args, dev):
         tr.step(x, n, E, lr_at(s, 4000), valid=valid)
 
     et, ep = time_steps(whole, 3, 1)
+    # gather rates of the texture path (niv_probe_gather): n x 128 four-byte
+    # gathers per pass; the random pattern is the training forward's ceiling
+    from paper_2602_12949_amd.niv import probe_gather
+    table = torch.ones(1 << 21, dtype=torch.int32, device=dev)       # 8 MiB
+    sink = torch.empty(2048 * 256, dtype=torch.int32, device=dev)
+    gather = {}
+    for mode, what in ((0, "random words over 8 MiB (64 lines per instruction)"),
+                       (1, "consecutive words (2 lines per instruction, L1)"),
+                       (2, "quads share a line (16 lines per instruction, L1)"),
+                       (3, "a line per lane (64 lines per instruction, L1)")):
+        gt, gp = time_steps(lambda: probe_gather(mode, B, table, sink), 10, 3)
+        gather[what] = {"us_per_pass": gt * 1e3, "G_gathers_per_s": B * 128 / (gt * 1e-3) / 1e9}
+    log(f"[bench] gather rates (2^18 x 128 per pass): " +
+        ", ".join(f"{k.split(' (')[0]}: {v['us_per_pass']:.1f} us" for k, v in gather.items()))
     res = {
         "workload": "room_train: B=2^18 points/step (80 % volume, 20 % surface), targets at "
                     "256 spp, 3 bounces, NEE to 2 rect lights; model of room_1080p, FP16",
@@ -340,6 +354,7 @@ def bench_train(args, dev):
                        "spp": 256, "bounces": 3},
         "bake_step": {**stats(et, ep), "samples_per_s": B / (et * 1e-3)},
         "valid_fraction": float(valid.float().mean().item()),
+        "gather_rates": gather,
     }
     if not args.no_cpu:
         # the estimator's oracle on a bounded sample: 512 points x 4096 spp
@@ -684,6 +699,14 @@ def profile_case(case, steps, tune=None):
         log(f"[profile] {case}: encoding stage alone, HIP events: mean {total:.4f} ms per launch")
         torch.cuda.synchronize()
         return
+    if case == "gather":
+        from paper_2602_12949_amd.niv import probe_gather
+        table = torch.ones(1 << 21, dtype=torch.int32, device=dev)
+        sink = torch.empty(2048 * 256, dtype=torch.int32, device=dev)
+        for mode in range(4):
+            total, _ = time_steps(lambda: probe_gather(mode, 1 << 18, table, sink), steps, steps)
+            log(f"[profile] gather mode {mode}: HIP events {total * 1e3:.1f} us per pass")
+        return
     if case in ("train_step", "mc"):
         from niv_synth import get_workload, make_params, make_room
         from paper_2602_12949_amd import NIV, McScene, Trainer
@@ -719,10 +742,8 @@ def profile_case(case, steps, tune=None):
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         pm = m.prepare(t(params), "fp16")
         f, _ = m.frame(t(g["pos"]), t(g["nrm"]), pm, albedo=t(g["albedo"]), mask=t(g["mask"]))
-        for _ in range(2 * steps):
-            m.query_frames([f], "fp16")
-        torch.cuda.synchronize()
-        log(f"[profile] {case}: done")
+        total, _ = time_steps(lambda: m.query_frames([f], "fp16"), steps, steps)
+        log(f"[profile] {case}: HIP events in this process: mean {total:.4f} ms per launch")
         return
     if case == "half":
         from niv_synth import get_workload, make_params, make_room_gbuffer
@@ -736,10 +757,9 @@ def profile_case(case, steps, tune=None):
         pm = m.prepare(t(params), "fp16")
         f, _ = m.half_frame(Wd, Ht, t(g["pos"]), t(g["nrm"]), model=pm, albedo=t(g["albedo"]),
                             mask=t(g["mask"]))
-        for _ in range(2 * steps):
-            m.query_half(f, "fp16")
-        torch.cuda.synchronize()
-        log(f"[profile] {case}: done")
+        total, _ = time_steps(lambda: m.query_half(f, "fp16"), steps, steps)
+        log(f"[profile] {case}: HIP events in this process: mean {total:.4f} ms per frame "
+            f"(query and upsampling)")
         return
     if case == "field_4k":
         from niv_synth import get_workload, make_params, make_workload_gbuffer
@@ -754,16 +774,15 @@ def profile_case(case, steps, tune=None):
         pm = m.prepare(t(params), "bf16")
         d = [t(g["pos"]), t(g["nrm"]), t(g["albedo"]), t(g["mask"])]
         f, outs = m.frame(d[0], d[1], pm, albedo=d[2], mask=d[3], extra=(0.37,))
-        for _ in range(2 * steps):
-            m.query_frames([f], "bf16")
+        total, _ = time_steps(lambda: m.query_frames([f], "bf16"), steps, steps)
+        log(f"[profile] {case}: HIP events in this process: query mean {total:.4f} ms per launch")
         # then the dynamic ambient occlusion pass over the same frame
         from niv_synth import workload_meshes, mesh_triangles
         from paper_2602_12949_amd.niv import DynamicAO
         ao = DynamicAO(mesh_triangles(workload_meshes(w)))
-        for _ in range(2 * steps):
-            ao.apply(d[0], d[1], AO_RAYS, AO_RADIUS, AO_EPS, 23, mask=d[3], E=outs[0], L=outs[1])
-        torch.cuda.synchronize()
-        log(f"[profile] {case}: done")
+        total, _ = time_steps(lambda: ao.apply(d[0], d[1], AO_RAYS, AO_RADIUS, AO_EPS, 23, mask=d[3],
+                                               E=outs[0], L=outs[1]), steps, steps)
+        log(f"[profile] {case}: HIP events in this process: occlusion pass mean {total:.4f} ms per launch")
         return
     raise SystemExit(f"unknown profile case {case}")
 

@@ -163,6 +163,15 @@ niv_status niv_corner_indices(niv_handle *h, niv_precision prec, int32_t trainin
 niv_status niv_probe_encode(niv_handle *h, const niv_frame *frame, niv_precision prec,
                             hipStream_t stream);
 
+/* Measurement: one pass of n x 128 four-byte gathers (8 per level, 16 levels)
+ * in the pattern `mode`: 0 random words over an 8 MiB table (64 cache lines
+ * per instruction, the pattern of the training forward's encoding), 1
+ * consecutive words (2 lines per instruction), 2 quads of lanes sharing a
+ * line (16 lines), 3 a line per lane (64 lines); modes 1-3 read the first
+ * 16 KiB only.  table: device, 8 MiB; out: device, 2048 x 256 words written.
+ * 1 <= n <= 2^24.  The caller times the launch. */
+niv_status niv_probe_gather(int32_t mode, int32_t n, const void *table, void *out, hipStream_t stream);
+
 /* Monte Carlo fallback for pixels the network should not answer: after the
  * query, pixels whose flags intersect `flag_mask` (bits 0, 2 and 4 of
  * out_flags) or whose in_flags are set are appended to a list, and

@@ -114,6 +114,7 @@ def lib():
         L.niv_upsample.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), vp]
         L.niv_query_half.argtypes = [vp, C.POINTER(HalfFrame), C.POINTER(UpsampleParams), C.c_int, vp]
         L.niv_fallback_sizes.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.niv_probe_gather.argtypes = [C.c_int32, C.c_int32, vp, vp, vp]
         L.niv_probe_encode.argtypes = [vp, C.POINTER(Frame), C.c_int, vp]
         L.niv_corner_indices.argtypes = [vp, C.c_int, C.c_int32, vp, vp, C.c_int64, vp, vp]
         L.niv_query_fallback.argtypes = [vp, C.POINTER(Frame), C.c_int32, C.c_int,
@@ -171,6 +172,13 @@ def _stream():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def probe_gather(mode, n, table, out):
+    """niv_probe_gather: one pass of n x 128 gathers in pattern `mode`
+    (measurement); table: 8 MiB device tensor, out: 2048 x 256 words."""
+    _check(lib().niv_probe_gather(int(mode), int(n), _ptr(table), _ptr(out), _stream()),
+           "niv_probe_gather")
 
 
 def lr_schedule(step, hold_steps, total_steps, lr0=1e-2, lr1=1e-4):
