@@ -347,7 +347,9 @@ niv_status niv_train_sizes(const niv_handle *h, niv_precision prec, int64_t max_
  * The gradient does not depend on scheduling: weight gradients are summed
  * in a fixed order, and each grid value is the sum of its contributions
  * (the 8 trilinear corners of every level, Sec. 4.1) in 64-bit fixed point,
- * converted to FP32 once.  A sample whose output or target gives a
+ * converted to FP32 once.  With NIV_FP16 each contribution is first rounded
+ * to FP16 at a per-step power-of-two scale (11 significant bits, the
+ * precision of that path's operands); with NIV_FP32 it is summed as computed.  A sample whose output or target gives a
  * non-finite d loss / dE marks the step non-finite (niv_train_status) and
  * contributes nothing to the grid. */
 niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state *st,

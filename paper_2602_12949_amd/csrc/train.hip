@@ -149,6 +149,8 @@ struct BwdArgs {
     float *dw_part;            // [wave][weights] each wave's weight gradient
     float *dx0;                // [n][2L] gradient of each sample's grid features
     uint8_t *sflag;            // [n] 1: the sample's features scatter into the grid
+    uint32_t *vmax;            // step word [0]: largest |feature gradient| x loss_scale of a
+                               // scattering sample (float bits; bounds every contribution)
     int64_t n, n_grid;
     float loss_scale;
     uint32_t hash_mask;
@@ -180,6 +182,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
 
     const int64_t n_chunks = (a.n + 63) / 64;
     const int64_t n_waves = (int64_t)gridDim.x * 4;
+    float gmax = 0.0f;   // largest |feature gradient| of this lane's scattering samples
     for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave; chunk < n_chunks; chunk += n_waves) {
         const int64_t q = chunk * 64 + lane;
         const bool live = q < a.n;
@@ -429,11 +432,22 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
                 const float4 *mine = reinterpret_cast<const float4 *>(dx + lane * NF);
                 float4 *dst = reinterpret_cast<float4 *>(a.dx0 + q * NF);
 #pragma unroll
-                for (int k = 0; k < NF / 4; ++k) dst[k] = mine[k];
+                for (int k = 0; k < NF / 4; ++k) {
+                    const float4 v = mine[k];
+                    dst[k] = v;
+                    if (scatter)
+                        gmax = fmaxf(gmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+                }
                 a.sflag[q] = scatter ? 1 : 0;
             }
         }
     }
+    // the step's bound on the grid contributions (|w g| <= |g|, weights <= 1):
+    // the scale of the fixed-point sums and of 16-bit contribution records
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, off));
+    const float cmax = gmax * a.loss_scale;
+    if (lane == 0 && cmax == cmax && cmax > 0.0f) atomicMax(a.vmax, f2u(cmax));
     // this wave's weight gradient to a row of its own; k_dw_sum adds the rows
     // (no atomics, and a fixed summation order).  Tile element r of lane (g, j)
     // is row 16 ob + 4 g + r, column 16 ib + j of the layer's matrix.
@@ -515,11 +529,13 @@ struct ScatterArgs {
     uint32_t *bin_start;       // [bins + 1]
     uint32_t *work_start;      // [bins + 1] first accumulating workgroup of each bin
     uint32_t *split;           // [bins + 1] bins split over several workgroups, in order; [bins] count
-    uint32_t *vmax;            // [0] bits of the largest |contribution| of the step (>= 0 floats
-                               // order as integers), [1] records of the fullest bin
+    uint32_t *vmax;            // [0] bits of a bound M on every |contribution| of the step, set by
+                               // the backward (>= 0 floats order as integers), [1] records of
+                               // the fullest bin
     long long *parts;          // [accumulating workgroup][2 kBinEntries] fixed-point partial sums
     uint16_t *keys;            // [records] entry index within its bin
-    float2 *vals;              // [records] contributions of the two features
+    float2 *vals;              // [records] contributions of the two features (FP32 records)
+    uint32_t *vals16;          // [records] the same as an FP16 pair scaled by 2^(14 - e) (16-bit records)
     float *grads;              // grid part of the gradient: [entries][2]
     int64_t n, n_entries;
     int32_t n_levels, n_bins;
@@ -603,6 +619,11 @@ __host__ __device__ constexpr int write_wave_bytes(int n_levels)
 // the other.  The records are then stored in that order, so consecutive lanes
 // write consecutive slots of a bin's segment (runs of ~16 records on a hashed
 // level instead of single 4- and 8-byte stores).
+// H16 (the FP16 training path): records carry the contributions as an FP16
+// pair scaled by 2^(14 - e), M < 2^e, so every value is below 2^14 and keeps
+// 11 significant bits (the operands of that path are FP16 already); 6 bytes
+// per record instead of 10.
+template <bool H16>
 __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArgs a)
 {
     __shared__ uint32_t cnt[kMaxBins];
@@ -620,7 +641,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
     __syncthreads();
     const int64_t n_chunks = (a.n + 63) / 64;
     ConstLevels lvs = (ConstLevels)a.model;
-    float vmax = 0.0f;
+    [[maybe_unused]] float rs = 1.0f;
+    if constexpr (H16) {
+        int e;
+        (void)frexpf(u2f(a.vmax[0]), &e);
+        rs = ldexpf(1.0f, 14 - e);
+    }
     for (int64_t chunk = (int64_t)blockIdx.x * kScatterWaves + wave; chunk < n_chunks;
          chunk += (int64_t)gridDim.x * kScatterWaves) {
         const int64_t q0 = chunk * 64;
@@ -669,26 +695,23 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
                 for (int c = 0; c < 8; ++c) {
                     if (slot[c] == ~0u) continue;
                     const float v0 = w[c] * g0, v1 = w[c] * g1;
-                    stage[lstart[rb[c]] + slot[c]] = (u4){bbase[rb[c]] + slot[c], idx[c], f2u(v0), f2u(v1)};
-                    vmax = fmaxf(vmax, fmaxf(fabsf(v0), fabsf(v1)));
+                    if constexpr (H16)
+                        stage[lstart[rb[c]] + slot[c]] =
+                            (u4){bbase[rb[c]] + slot[c], idx[c], Prec<NIV_FP16>::pack(v0 * rs, v1 * rs), 0u};
+                    else
+                        stage[lstart[rb[c]] + slot[c]] = (u4){bbase[rb[c]] + slot[c], idx[c], f2u(v0), f2u(v1)};
                 }
                 wave_lds_sync();
                 for (uint32_t k = lane; k < total; k += 64) {
                     const u4 e = stage[k];
                     a.keys[e.x] = (uint16_t)(e.y & (kBinEntries - 1));
-                    a.vals[e.x] = make_float2(u2f(e.z), u2f(e.w));
+                    if constexpr (H16) a.vals16[e.x] = e.z;
+                    else a.vals[e.x] = make_float2(u2f(e.z), u2f(e.w));
                 }
                 wave_lds_sync();   // hist and stage are reused
             }
         }
     }
-    // the step's largest |contribution|, for the fixed-point sums
-    __shared__ uint32_t smax;
-    if (threadIdx.x == 0) smax = 0u;
-    __syncthreads();
-    if (vmax == vmax) atomicMax(&smax, f2u(vmax));   // NaN contributions are left out
-    __syncthreads();
-    if (threadIdx.x == 0 && smax) atomicMax(a.vmax, smax);
 }
 
 // Per bin (one workgroup of kScatterBlocks threads): exclusive scan of the
@@ -818,6 +841,7 @@ __device__ inline int fixed_shift(const uint32_t *vmax)
 // sums do not depend on the order).  A bin taken by one workgroup is stored
 // as is (every entry, zeros included); a shared bin (the coarse dense
 // levels) stores each part's integer sums, which k_grid_merge adds.
+template <bool H16>
 __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
 {
     __shared__ unsigned long long acc[2 * kBinEntries];
@@ -841,8 +865,22 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     const uint32_t r0 = b0 + part * (uint32_t)kAccumRecords;
     const uint32_t r1 = parts == 1 ? b1 : (r0 + kAccumRecords < b1 ? r0 + kAccumRecords : b1);
     const int sh = fixed_shift(a.vmax);
-    const double up = ldexp(1.0, sh), down = ldexp(1.0, -sh);
+    const double down = ldexp(1.0, -sh);
+    double up = ldexp(1.0, sh);
+    if constexpr (H16) {   // records hold v 2^(14 - e)
+        int e;
+        (void)frexpf(u2f(a.vmax[0]), &e);
+        up = ldexp(1.0, sh - (14 - e));
+    }
     auto fx = [&](float v) { return (unsigned long long)(long long)__builtin_rint((double)v * up); };
+    auto val = [&](uint32_t r) -> float2 {
+        if constexpr (H16) {
+            const f2 h = Prec<NIV_FP16>::unpack(a.vals16[r]);
+            return make_float2(h.x, h.y);
+        } else {
+            return a.vals[r];
+        }
+    };
     uint32_t r = r0 + threadIdx.x;
     // eight records per thread in flight before the LDS adds
     for (; r + 7 * 1024 < r1; r += 8 * 1024) {
@@ -851,7 +889,7 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             i[k] = a.keys[r + k * 1024];
-            v[k] = a.vals[r + k * 1024];
+            v[k] = val(r + k * 1024);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -861,7 +899,7 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     }
     for (; r < r1; r += 1024) {
         const uint32_t i = a.keys[r];
-        const float2 v = a.vals[r];
+        const float2 v = val(r);
         atomicAdd(&acc[2 * i], fx(v.x));
         atomicAdd(&acc[2 * i + 1], fx(v.y));
     }
@@ -1007,7 +1045,7 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
     L.keys_off = L.split_off + align256((kMaxBins + 1) * 4);
     const int64_t records = n * S::L * 8;
     L.vals_off = L.keys_off + align256(records * 2);
-    L.dw_off = L.vals_off + align256(records * 8);
+    L.dw_off = L.vals_off + align256(records * (B::F32 ? 8 : 4));   // FP32 pairs or scaled FP16 pairs
     // one weight-gradient row per backward wave: 4 per workgroup, at most
     // one workgroup per 4 chunks and kBwdMaxBlocks in all
     const int64_t bwd_blocks = std::min<int64_t>(kBwdMaxBlocks, std::max<int64_t>(1, (nc + 3) / 4));
@@ -1099,6 +1137,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     ba.dw_part = reinterpret_cast<float *>(ws + L.dw_off);
     ba.dx0 = reinterpret_cast<float *>(ws + L.dx0_off);
     ba.sflag = ws + L.sflag_off;
+    ba.vmax = status;
     ba.n = b.count;
     ba.n_grid = m.n_grid_values;
     ba.loss_scale = loss_scale;
@@ -1153,6 +1192,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.parts = reinterpret_cast<long long *>(ws + L.parts_off);
     sa.keys = reinterpret_cast<uint16_t *>(ws + L.keys_off);
     sa.vals = reinterpret_cast<float2 *>(ws + L.vals_off);
+    sa.vals16 = reinterpret_cast<uint32_t *>(ws + L.vals_off);
     sa.grads = st.grads;
     sa.n = b.count;
     sa.n_entries = m.n_grid_values / 2;
@@ -1167,18 +1207,19 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
     const int write_lds = kScatterWaves * write_wave_bytes(sa.n_levels);
+    constexpr bool H16 = !B::F32;
     static bool write_lds_set = false;   // dynamic LDS beyond 64 KB must be allowed per kernel
     if (!write_lds_set) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_grid_write),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_grid_write<H16>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kScatterWaves * write_wave_bytes(kScatterMaxLevels));
         if (e != hipSuccess) return e;
         write_lds_set = true;
     }
-    hipLaunchKernelGGL(k_grid_write, dim3(kScatterBlocks), dim3(kScatterThreads), (size_t)write_lds,
+    hipLaunchKernelGGL(k_grid_write<H16>, dim3(kScatterBlocks), dim3(kScatterThreads), (size_t)write_lds,
                        stream, sa);
     const int64_t acc_groups = acc_group_bound(b.count, m.cfg.n_levels, sa.n_bins);
-    hipLaunchKernelGGL(k_grid_accum, dim3((unsigned)acc_groups), dim3(1024), 0, stream, sa);
+    hipLaunchKernelGGL(k_grid_accum<H16>, dim3((unsigned)acc_groups), dim3(1024), 0, stream, sa);
     // a split bin holds more than kAccumRecords records
     const int64_t records = b.count * (int64_t)m.cfg.n_levels * 8;
     const int64_t max_split = std::min<int64_t>(sa.n_bins, records / (kAccumRecords + 1));
