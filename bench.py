@@ -522,6 +522,10 @@ def bench_field_4k(args, dev):
     s = rng.choice(len(mask), 8192, replace=False)
     s = s[mask[s] > 0]
     pos, nrm = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3)
+    f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"], extra=(0.37,))
+    tune = m.autotune([f], "bf16")
+    log(f"[bench] room_4k_6d autotune: block {tune['block']} x {tune['blocks_per_cu']} per CU, "
+        f"xcd order {tune['xcd_order']}")
     for tv in w.extra_values:
         f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"], extra=(tv,))
         graph = m.capture([f], "bf16")

@@ -350,16 +350,6 @@ __device__ inline void pos_code_axis(float uh, float ul, float *sv, float *cv)
     }
 }
 
-template <int P>
-__device__ inline f2 load_latent(const uint8_t *grid, uint32_t entry)
-{
-    if constexpr (P == NIV_FP32) {
-        return reinterpret_cast<const f2 *>(grid)[entry];
-    } else {
-        return Prec<P>::unpack(reinterpret_cast<const uint32_t *>(grid)[entry]);
-    }
-}
-
 // Cell, corner indices (within the whole grid) and trilinear weights of one
 // level (Sec. 4.1).  Corner c = cx + 2cy + 4cz.
 template <class LV>
@@ -591,86 +581,52 @@ __device__ inline LevelRegs load_level(const LevelConst *lp)
     return r;
 }
 
+// Issue phase of a level that differs between lanes: cell, corner offsets
+// and the eight loads with one set of instructions for dense and hashed
+// levels (the level's kind is a per-lane value here, so a branch on it would
+// diverge): corner c reads ((xb + cx EB) ^ t_c) + o_c, where a hashed level
+// has xb = x << SH, t_c its masked y/z hash terms and o_c its first entry, a
+// dense level xb = (x + (N+1)(y + (N+1) z)) << SH, t_c = 0 and o_c its first
+// entry plus the corner's y/z steps.
 template <int P, bool TRACE = false>
-__device__ inline f2 encode_level_vec(const LevelRegs &lv, const double p[3], uint32_t hmask,
-                                      __amdgpu_buffer_rsrc_t rsrc, uint32_t *trace = nullptr)
+__device__ inline void level_issue_vec(const LevelRegs &lv, const double p[3], uint32_t hmask,
+                                       __amdgpu_buffer_rsrc_t rsrc, LevelFetch<P> &out,
+                                       uint32_t *trace = nullptr)
 {
     constexpr int SH = (P == NIV_FP32) ? 3 : 2;
     constexpr uint32_t EB = 1u << SH;
     int32_t ci[3];
-    float fr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
         int32_t c = (int32_t)s;
         c = c < lv.nm1 ? c : lv.nm1;
         ci[a] = c;
-        fr[a] = (float)(s - (double)c);
+        out.fr[a] = (float)(s - (double)c);
     }
-    [[maybe_unused]] int nt = 0;
-    auto ld = [&](uint32_t voff) -> f2 {
-        if constexpr (TRACE) trace[nt++] = voff >> SH;
-        if constexpr (P == NIV_FP32) {
-            u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, 0, 0);
-            return (f2){u2f(w.x), u2f(w.y)};
-        } else {
-            return Prec<P>::unpack(__builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, 0, 0));
-        }
-    };
+    const bool dn = lv.dense != 0;
+    const uint32_t bd = ((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH;
+    const uint32_t xb = dn ? bd : ((uint32_t)ci[0] << SH);
+    const uint32_t m = dn ? 0u : (hmask << SH);
+    const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH;
+    const uint32_t y0 = (uint32_t)ci[1] * p1, y1 = y0 + p1;
+    const uint32_t z0 = (uint32_t)ci[2] * p2, z1 = z0 + p2;
+    const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
+    const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
     const uint32_t o = lv.off << SH;
-    f2 v[8];
-    if (lv.dense) {
-        const uint32_t b = (((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH) + o;
-        const uint32_t dy = lv.s1 << SH, dz = lv.s2 << SH;
-        v[0] = ld(b); v[1] = ld(b + EB);
-        v[2] = ld(b + dy); v[3] = ld(b + dy + EB);
-        v[4] = ld(b + dz); v[5] = ld(b + dz + EB);
-        v[6] = ld(b + dz + dy); v[7] = ld(b + dz + dy + EB);
-    } else {
-        const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH, m = hmask << SH;
-        const uint32_t x0 = (uint32_t)ci[0] << SH, x1 = x0 + EB;
-        const uint32_t y0 = (uint32_t)ci[1] * p1, y1 = y0 + p1;
-        const uint32_t z0 = (uint32_t)ci[2] * p2, z1 = z0 + p2;
-        const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
-        const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
-        v[0] = ld((x0 ^ t00) + o); v[1] = ld((x1 ^ t00) + o);
-        v[2] = ld((x0 ^ t10) + o); v[3] = ld((x1 ^ t10) + o);
-        v[4] = ld((x0 ^ t01) + o); v[5] = ld((x1 ^ t01) + o);
-        v[6] = ld((x0 ^ t11) + o); v[7] = ld((x1 ^ t11) + o);
-    }
-    const float wx1 = fr[0], wx0 = 1.0f - fr[0];
-    const float wy1 = fr[1], wy0 = 1.0f - fr[1];
-    const float wz1 = fr[2], wz0 = 1.0f - fr[2];
-    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
-    const float w[8] = {wx0 * w00, wx1 * w00, wx0 * w10, wx1 * w10,
-                        wx0 * w01, wx1 * w01, wx0 * w11, wx1 * w11};
-    f2 acc = {0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
-        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
-    }
-    return acc;
-}
-
-// Trilinear blend of one level (Sec. 4.1).  Returns the F = 2 features.
-template <int P, class LV>
-__device__ inline f2 encode_level(const LV &lv, const double p[3], uint32_t hmask,
-                                  const uint8_t *grid)
-{
-    uint32_t idx[8];
-    float w[8];
-    level_corners(lv, p, hmask, idx, w);
-    f2 v[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = load_latent<P>(grid, idx[c]);
-    f2 acc = {0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
-        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
-    }
-    return acc;
+    const uint32_t o10 = dn ? (lv.off + lv.s1) << SH : o, o01 = dn ? (lv.off + lv.s2) << SH : o;
+    const uint32_t o11 = dn ? (lv.off + lv.s2 + lv.s1) << SH : o;
+    [[maybe_unused]] int nt = 0;
+    auto ld = [&](int c, uint32_t voff) {
+        if constexpr (TRACE) trace[nt++] = voff >> SH;
+        if constexpr (P == NIV_FP32) out.v[c] = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, 0, 0);
+        else out.v[c] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, 0, 0);
+    };
+    const uint32_t x0 = xb, x1 = xb + EB;
+    ld(0, (x0 ^ t00) + o);   ld(1, (x1 ^ t00) + o);
+    ld(2, (x0 ^ t10) + o10); ld(3, (x1 ^ t10) + o10);
+    ld(4, (x0 ^ t01) + o01); ld(5, (x1 ^ t01) + o01);
+    ld(6, (x0 ^ t11) + o11); ld(7, (x1 ^ t11) + o11);
 }
 
 }  // namespace niv

@@ -306,7 +306,9 @@ __global__ __launch_bounds__(256) void k_trace_corners(const uint8_t *__restrict
         f2 f;
         if constexpr (SLICED) {
             const LevelRegs lc = load_level(lvs + l);
-            f = encode_level_vec<P, true>(lc, p, hmask, rsrc, o + 8 * l);
+            LevelFetch<P> lf;
+            level_issue_vec<P, true>(lc, p, hmask, rsrc, lf, o + 8 * l);
+            f = level_blend<P>(lf);
         } else {
             if constexpr (F32C) {
                 f = encode_level_buf<P, F32C, true>(lvs[l], p, hmask, rsrc, pf, o + 8 * l);

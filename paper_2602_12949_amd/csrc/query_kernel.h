@@ -220,14 +220,27 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 }
             }
             // grid levels 4s + g: the level's constants are per-lane LDS reads
+            // (one set of loads for dense and hashed levels, the next slot's
+            // gathers in flight while a slot is blended)
             const LevelConst *lt = reinterpret_cast<const LevelConst *>(smem + O::W_BYTES);
+            LevelFetch<P> cur[TB], nxt[TB];
+            {
+                const LevelRegs lc = load_level(lt + g);
+#pragma unroll
+                for (int tt = 0; tt < TB; ++tt) level_issue_vec<P>(lc, pd[tt], a.hash_mask, grid_rsrc, cur[tt]);
+            }
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) {
-                __builtin_amdgcn_sched_barrier(0);  // one slot of gathers in flight at a time
-                const LevelRegs lc = load_level(lt + 4 * s2 + g);
+                if (s2 + 1 < 4) {
+                    const LevelRegs lc = load_level(lt + 4 * (s2 + 1) + g);
+#pragma unroll
+                    for (int tt = 0; tt < TB; ++tt)
+                        level_issue_vec<P>(lc, pd[tt], a.hash_mask, grid_rsrc, nxt[tt]);
+                }
 #pragma unroll
                 for (int tt = 0; tt < TB; ++tt) {
-                    const f2 f = encode_level_vec<P>(lc, pd[tt], a.hash_mask, grid_rsrc);
+                    const f2 f = level_blend<P>(cur[tt]);
+                    cur[tt] = nxt[tt];
                     if constexpr (P == NIV_FP32) {
                         sl[0][tt][2 * s2] = f2u(f.x);
                         sl[0][tt][2 * s2 + 1] = f2u(f.y);
