@@ -20,13 +20,15 @@ Also measured, as extra fields of the same JSON line:
               scene variable t in {0, 0.37, 1}, MLP 64-128^4-3, BF16; then the
               dynamic ambient occlusion pass over the frame (Sec. 4.4: the
               icospheres' 40,960 triangles, 16 rays per pixel within 1 m);
-  table1      room_1080p_pe16/32/64: the same 1080p G-buffer under the
-              grid-free models of Table 1 (eight-band positional code of x,
-              three hidden layers of width 16, 32 or 64), FP16;
+  table1      room_1080p_pe16/32/64 and room_1080p_g2/4/6/8: the same 1080p
+              G-buffer under the networks of Table 1: grid-free (eight-band
+              positional code of x, three hidden layers of width 16, 32 or
+              64) and grid (2, 4, 6 or 8 levels of four features, T = 2^17,
+              three hidden layers of width 64), FP16;
   half        half-resolution rendering of the 1080p G-buffer (Table 1's
               "half" column): the query at a quarter of the pixels, joint
               bilateral upsampling with the G-buffer as guide, full-resolution
-              albedo; for the grid model and the three grid-free models, FP16.
+              albedo; for the room model and every network of Table 1, FP16.
 
 Kernel times come from HIP events recorded on the stream the kernels are
 launched on (torch's current stream).  Prints one JSON line on stdout;
@@ -34,7 +36,7 @@ progress goes to stderr.
 
 `--profile CASE` runs only that case's kernel a few times (for rocprofv3
 counter and trace runs): query_fp16, query_fp32, query_bf16, field_4k,
-train_step, mc, pe16, pe32, pe64, half, gather (the gather-rate probes), copy (a 1 GiB device copy that calibrates
+train_step, mc, pe16, pe32, pe64, g2, g4, g6, g8, half, gather (the gather-rate probes), copy (a 1 GiB device copy that calibrates
 the HBM byte counters).
 """
 import argparse
@@ -590,8 +592,15 @@ def bench_dynamic_ao(args, w, g, d, outs, s_near_seed):
             "sampled_max_hit_difference": int(dh.max())}
 
 
+# Table 1 (RTX 4090, full HD, half precision): full and half ms per frame
+# of each network, for context (other hardware).
+TABLE1_PAPER_MS = {"pe16": (0.19, 0.029), "pe32": (0.20, 0.031), "pe64": (0.25, 0.069),
+                   "g2": (0.31, 0.088), "g4": (0.67, 0.18), "g6": (1.06, 0.26), "g8": (1.35, 0.37)}
+
+
 def bench_table1(args, dev):
-    """The grid-free rows of Table 1 on the room_1080p G-buffer, FP16."""
+    """The rows of Table 1 on the room_1080p G-buffer, FP16: the grid-free
+    networks and the grid networks of 2 to 8 levels of four features."""
     import torch
     import oracle as O
     from niv_synth import get_workload, make_params, make_room_gbuffer
@@ -608,10 +617,10 @@ def bench_table1(args, dev):
     s = s[mask[s] > 0]
     pos, nrm = g["pos"].reshape(-1, 3), g["nrm"].reshape(-1, 3)
     rows = {}
-    for width in (16, 32, 64):
-        w = get_workload(f"room_1080p_pe{width}")
+    for key in TABLE1_PAPER_MS:
+        w = get_workload(f"room_1080p_{key}")
         m = NIV(w.model_dict())
-        params = make_params(0, m.mat_shapes(), w.param_seed, *w.grid_init)
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
         pm = m.prepare(t(params), "fp16")
         f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"])
         tune = m.autotune([f], "fp16")
@@ -623,15 +632,17 @@ def bench_table1(args, dev):
         ref, _, _ = O.query(oc, round_params(params, "fp16"), pos[s], nrm[s])
         err = float(np.linalg.norm(E - ref) / np.linalg.norm(ref))
         fl = mlp_flops(w.model_dict()) * n_valid
-        rows[f"pe{width}"] = {
+        rows[key] = {
             **stats(tt, tp), "ms_per_frame": tt, "queries_per_s": n_valid / (tt * 1e-3),
             "params_MB_fp16": 2 * m.n_params / 1e6, "sampled_rel_l2": err,
             "mlp_tflops": fl / (tt * 1e-3) / 1e12,
+            "paper_rtx4090_ms": TABLE1_PAPER_MS[key][0],
             "autotune": {k: tune[k] for k in ("block", "blocks_per_cu", "xcd_order")}}
-        log(f"[bench] room_1080p_pe{width} fp16: {tt:.4f} ms/frame, sampled rel-L2 {err:.2e}")
+        log(f"[bench] room_1080p_{key} fp16: {tt:.4f} ms/frame, sampled rel-L2 {err:.2e}")
         del graph
-    return {"workload": "room_1080p G-buffer, grid-free models: u + 8-band positional code of x, "
-                        "SH-16, MLP 67-W-W-W-3 (W = 16, 32, 64), FP16",
+    return {"workload": "room_1080p G-buffer, FP16: grid-free models (u + 8-band positional "
+                        "code of x, SH-16, MLP 67-W-W-W-3, W = 16, 32, 64) and grid models "
+                        "(2/4/6/8 levels of 4 features, T = 2^17, SH-16, MLP (4L+16)-64-64-64-3)",
             "valid_pixels": n_valid, "rows": rows}
 
 
@@ -652,7 +663,7 @@ def bench_half(args, dev):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     d = dict(pos=t(g["pos"]), nrm=t(g["nrm"]), alb=t(g["albedo"]), mask=t(g["mask"]))
     rows = {}
-    for name in ("room_1080p", "room_1080p_pe16", "room_1080p_pe32", "room_1080p_pe64"):
+    for name in ("room_1080p",) + tuple(f"room_1080p_{k}" for k in TABLE1_PAPER_MS):
         w = get_workload(name)
         m = NIV(w.model_dict())
         params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
@@ -661,7 +672,9 @@ def bench_half(args, dev):
         up = m.upsample_params()
         tt, tp = time_steps(lambda: m.query_half(f, "fp16", up), args.steps, args.warmup)
         ut, upr = time_steps(lambda: m.upsample(f, up), args.steps, args.warmup)
-        rows[name] = {**stats(tt, tp), "ms_per_frame": tt, "upsample_ms": ut,
+        key = name[len("room_1080p_"):]
+        ctx = {"paper_rtx4090_ms": TABLE1_PAPER_MS[key][1]} if key in TABLE1_PAPER_MS else {}
+        rows[name] = {**stats(tt, tp), "ms_per_frame": tt, "upsample_ms": ut, **ctx,
                       "query_ms": tt - ut, "half_pixels": ((Wd + 1) // 2) * ((Ht + 1) // 2),
                       "upsample_hbm_GBs": UPSAMPLE_BYTES_PER_PX * Wd * Ht / (ut * 1e-3) / 1e9}
         log(f"[bench] half {name} fp16: {tt:.4f} ms/frame (upsampling {ut:.4f} ms, "
@@ -735,7 +748,7 @@ def profile_case(case, steps, tune=None):
         log(f"[profile] train_step: HIP events in this process: mean {total:.4f} ms, p50 "
             f"{np.median(per):.4f} ms per step")
         return
-    if case.startswith("pe") and case[2:].isdigit():
+    if case in TABLE1_PAPER_MS:
         from niv_synth import get_workload, make_params, make_room_gbuffer
         from paper_2602_12949_amd import NIV
         w = get_workload(f"room_1080p_{case}")
@@ -743,7 +756,7 @@ def profile_case(case, steps, tune=None):
         m = NIV(w.model_dict())
         if tune:
             m.set_tune("fp16", *tune)
-        params = make_params(0, m.mat_shapes(), w.param_seed, *w.grid_init)
+        params = make_params(m.n_grid_values, m.mat_shapes(), w.param_seed, *w.grid_init)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         pm = m.prepare(t(params), "fp16")
         f, _ = m.frame(t(g["pos"]), t(g["nrm"]), pm, albedo=t(g["albedo"]), mask=t(g["mask"]))

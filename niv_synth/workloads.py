@@ -1,4 +1,4 @@
-"""The five synthetic workloads, named by what they are.
+"""The synthetic workloads, named by what they are.
 
 Model hyper-parameters follow Sec. 4.1 (hash table size, latent size, level
 scale and coarsest resolution) where a workload does not fix them; the network
@@ -103,6 +103,18 @@ for _w in (16, 32, 64):
         width=_w, n_hidden=3, n_out=3, aabb_min=ROOM_LO, aabb_max=ROOM_HI,
         grid_init=(0.0, 0.0), frames=((1920, 1080),), scene_seeds=(2001,),
         param_seed=2002 + _w, precision="fp16", pos_bands=8)
+
+
+# The room G-buffer under the grid networks of Table 1: 2, 4, 6 or 8 levels
+# of four features (Sec. 4.1: T = 2^17, coarsest side 16, scale sqrt(2)), a
+# four-layer network of width 64.
+for _l in (2, 4, 6, 8):
+    WORKLOADS[f"room_1080p_g{_l}"] = Workload(
+        name=f"room_1080p_g{_l}", n_levels=_l, log2_T=17, n_features=4, base_res=16.0,
+        per_level_scale=math.sqrt(2.0), sh_bands=4, n_extra=0, extra_bands=0,
+        width=64, n_hidden=3, n_out=3, aabb_min=ROOM_LO, aabb_max=ROOM_HI,
+        grid_init=(-0.5, 0.5), frames=((1920, 1080),), scene_seeds=(2001,),
+        param_seed=2100 + _l, precision="fp16")
 
 
 # On-GPU training of the field with one scene variable (Sec. 6): the room of

@@ -78,12 +78,22 @@ niv_status check_config(const niv_config *c)
 int kernel_kind(const Model &m)
 {
     const niv_config &c = m.cfg;
-    if (c.n_features != 2 || c.sh_bands != 4 || c.n_out != 3) return -1;
+    if ((c.n_features != 2 && c.n_features != 4) || c.sh_bands != 4 || c.n_out != 3) return -1;
     if (c.n_extra > 0 && c.extra_bands != 8) return -1;
     // hashed levels rely on corner coordinates below T
     for (int l = 0; l < c.n_levels; ++l)
         if (!m.dense[l] && m.res[l] + 1 > (int64_t(1) << c.log2_T)) return -1;
     if (m.n_entries > (int64_t)0xFFFFFFFF / 2) return -1;
+    if (c.n_features == 4) {  // grid networks of Table 1
+        if (c.pos_bands != 0 || c.n_extra != 0 || c.width != 64 || c.n_hidden != 3) return -1;
+        switch (c.n_levels) {
+        case 2: return kT1L2;
+        case 4: return kT1L4;
+        case 6: return kT1L6;
+        case 8: return kT1L8;
+        default: return -1;
+        }
+    }
     if (c.n_levels == 0) {  // grid-free models of Table 1
         if (c.pos_bands != 8 || c.n_extra != 0 || c.n_hidden != 3) return -1;
         return c.width == 16 ? kPE16 : c.width == 32 ? kPE32 : c.width == 64 ? kPE64 : -1;

@@ -124,29 +124,30 @@ template <> struct Prec<NIV_FP32> {
 // variables][0 ...] so that 16-bit pairs never straddle two parts, padded
 // with zero columns to a multiple of 16; in_col maps a kernel column to its
 // parameter column (or -1 for a zero column).
-template <int L_, int NEX_, int W_, int H_, bool SL_ = false, int PB_ = 0> struct Shape {
-    static constexpr int L = L_, NEX = NEX_, W = W_, H = H_, PB = PB_;
+template <int L_, int NEX_, int W_, int H_, bool SL_ = false, int PB_ = 0, int F_ = 2> struct Shape {
+    static constexpr int L = L_, NEX = NEX_, W = W_, H = H_, PB = PB_, F = F_;
     static constexpr bool SL = SL_;
+    static constexpr int GF = F * L;                              // grid features
     static constexpr int PEW_IN = PB > 0 ? 3 + 6 * PB : 0;       // positional code
     static constexpr int PEW = PB > 0 ? PEW_IN + 1 : 0;           // with its zero column
-    static constexpr int DIN_IN = 2 * L + PEW_IN + 16 + 16 * NEX; // F = 2, 16 SH, 16 per variable
-    static constexpr int DIN = (2 * L + PEW + 16 + 16 * NEX + 15) / 16 * 16;
+    static constexpr int DIN_IN = GF + PEW_IN + 16 + 16 * NEX;    // 16 SH, 16 per variable
+    static constexpr int DIN = (GF + PEW + 16 + 16 * NEX + 15) / 16 * 16;
     static constexpr int KLG = DIN / 4;                // input slots per lane group
     static constexpr int NOB = W / 16;                 // 16-row output blocks
-    static_assert(!SL || (L == 16 && DIN == 64 && PB == 0), "lane slices need 16 levels and 64 inputs");
-    static_assert(L % 4 == 0 && W % 16 == 0 && W >= 16, "shape");
+    static_assert(!SL || (L == 16 && F == 2 && DIN == 64 && PB == 0), "lane slices need 16 levels and 64 inputs");
+    static_assert((F == 2 || F == 4) && GF % 4 == 0 && W % 16 == 0 && W >= 16, "shape");
     static_assert(PB == 0 || L == 0, "positional code only without grid levels");
     __host__ __device__ static constexpr int in_col(int kc)
     {
-        if (kc < 2 * L) return kc;
-        int r = kc - 2 * L;
+        if (kc < GF) return kc;
+        int r = kc - GF;
         if (PB > 0) {
-            if (r < 6 * PB) return 2 * L + 3 + r;          // bands
-            if (r < 6 * PB + 3) return 2 * L + (r - 6 * PB);  // u
+            if (r < 6 * PB) return GF + 3 + r;          // bands
+            if (r < 6 * PB + 3) return GF + (r - 6 * PB);  // u
             if (r == 6 * PB + 3) return -1;
             r -= PEW;
         }
-        return r < 16 + 16 * NEX ? 2 * L + PEW_IN + r : -1;
+        return r < 16 + 16 * NEX ? GF + PEW_IN + r : -1;
     }
 };
 
@@ -160,6 +161,8 @@ template <int P> using ShapeWide6DFor =
 template <int W> using ShapePE = Shape<0, 0, W, 3, false, 8>;
 // the room network with one scene variable (Sec. 6), trainable
 using ShapeRoom6D = Shape<16, 1, 64, 3>;
+// Table 1's grid rows: 2, 4, 6 or 8 levels of 4 features, width 64
+template <int L> using ShapeT1 = Shape<L, 0, 64, 3, false, 0, 4>;
 
 // Lane-sliced layer-0 input order.  Virtual element v (0..15) of lane group
 // g: v < 8 is feature v % 2 of level 4 (v / 2) + g; then SH coefficients
@@ -554,6 +557,85 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
     }
     f.fr[0] = fr[0]; f.fr[1] = fr[1]; f.fr[2] = fr[2];
     return level_blend<P>(f);
+}
+
+// A level of four features per entry (Table 1's grid rows): eight
+// corner entries of 8 bytes (16-bit) or 16 bytes (FP32), the storage kind as a
+// branch as in encode_level_buf, FP32 trilinear blend of the four features.
+template <int P, bool F32C = false, bool TRACE = false, class LV>
+__device__ inline f4 encode_level_buf4(const LV &lv, const double p[3], uint32_t hmask,
+                                       __amdgpu_buffer_rsrc_t rsrc, const float *pf = nullptr,
+                                       uint32_t *trace = nullptr)
+{
+    constexpr int SH = (P == NIV_FP32) ? 4 : 3;   // log2 of the entry size in bytes
+    constexpr uint32_t EB = 1u << SH;
+    int32_t ci[3];
+    float fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (F32C) {
+            const float s = __builtin_fmaf(pf[a], lv.kf[a], lv.of[a]);
+            int32_t c = (int32_t)s;
+            c = c < lv.nm1 ? c : lv.nm1;
+            ci[a] = c;
+            fr[a] = s - (float)c;
+        } else {
+            double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+            int32_t c = (int32_t)s;
+            c = c < lv.nm1 ? c : lv.nm1;
+            ci[a] = c;
+            fr[a] = (float)(s - (double)c);
+        }
+    }
+    f4 v[8];
+    [[maybe_unused]] int nt = 0;
+    auto ld = [&](int c, uint32_t voff, uint32_t soff) {
+        if constexpr (TRACE) trace[nt++] = (voff + soff) >> SH;
+        if constexpr (P == NIV_FP32) {
+            const u4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0);
+            v[c] = (f4){u2f(w.x), u2f(w.y), u2f(w.z), u2f(w.w)};
+        } else {
+            const u2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
+            const f2 a = Prec<P>::unpack(w.x), b = Prec<P>::unpack(w.y);
+            v[c] = (f4){a.x, a.y, b.x, b.y};
+        }
+    };
+    if (lv.dense) {
+        const uint32_t b = ((uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2])) << SH;
+        const uint32_t o00 = lv.off << SH, o10 = (lv.off + lv.s1) << SH;
+        const uint32_t o01 = (lv.off + lv.s2) << SH, o11 = (lv.off + lv.s2 + lv.s1) << SH;
+        ld(0, b, o00); ld(1, b + EB, o00);
+        ld(2, b, o10); ld(3, b + EB, o10);
+        ld(4, b, o01); ld(5, b + EB, o01);
+        ld(6, b, o11); ld(7, b + EB, o11);
+    } else {
+        const uint32_t p1 = kPrime1 << SH, p2 = kPrime2 << SH, m = hmask << SH;
+        const uint32_t x0 = (uint32_t)ci[0] << SH, x1 = x0 + EB;
+        const uint32_t y0 = (uint32_t)ci[1] * p1, y1 = y0 + p1;
+        const uint32_t z0 = (uint32_t)ci[2] * p2, z1 = z0 + p2;
+        const uint32_t t00 = (y0 ^ z0) & m, t10 = (y1 ^ z0) & m;
+        const uint32_t t01 = (y0 ^ z1) & m, t11 = (y1 ^ z1) & m;
+        const uint32_t o = lv.off << SH;
+        ld(0, x0 ^ t00, o); ld(1, x1 ^ t00, o);
+        ld(2, x0 ^ t10, o); ld(3, x1 ^ t10, o);
+        ld(4, x0 ^ t01, o); ld(5, x1 ^ t01, o);
+        ld(6, x0 ^ t11, o); ld(7, x1 ^ t11, o);
+    }
+    const float wx1 = fr[0], wx0 = 1.0f - fr[0];
+    const float wy1 = fr[1], wy0 = 1.0f - fr[1];
+    const float wz1 = fr[2], wz0 = 1.0f - fr[2];
+    const float w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+    const float w[8] = {wx0 * w00, wx1 * w00, wx0 * w10, wx1 * w10,
+                        wx0 * w01, wx1 * w01, wx0 * w11, wx1 * w11};
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        acc.x = __builtin_fmaf(w[c], v[c].x, acc.x);
+        acc.y = __builtin_fmaf(w[c], v[c].y, acc.y);
+        acc.z = __builtin_fmaf(w[c], v[c].z, acc.z);
+        acc.w = __builtin_fmaf(w[c], v[c].w, acc.w);
+    }
+    return acc;
 }
 
 // The same blend for a level that differs between lanes (lane-sliced

@@ -81,8 +81,9 @@ struct QueryArgs {
 };
 
 // Shapes the fused kernels are instantiated for.
+// kT1L2..kT1L8: Table 1's grid networks, 2 to 8 levels of four features.
 enum ModelKind { kUnitCube = 0, kRoom = 1, kWide6D = 2, kPE16 = 3, kPE32 = 4, kPE64 = 5, kRoom6D = 6,
-                 kNumKinds = 7 };
+                 kT1L2 = 7, kT1L4 = 8, kT1L6 = 9, kT1L8 = 10, kNumKinds = 11 };
 
 // Launch shape of the fused query: workgroup size and resident workgroups
 // per CU (0 = as many as fit); chosen by niv_autotune, else defaults.

@@ -72,6 +72,10 @@ OpLayout op_layout(int kind, niv_precision prec)
     case kPE32: return layout_of<P, ShapePE<32>>();                     \
     case kPE64: return layout_of<P, ShapePE<64>>();                     \
     case kRoom6D: return layout_of<P, ShapeRoom6D>();                   \
+    case kT1L2: return layout_of<P, ShapeT1<2>>();                      \
+    case kT1L4: return layout_of<P, ShapeT1<4>>();                      \
+    case kT1L6: return layout_of<P, ShapeT1<6>>();                      \
+    case kT1L8: return layout_of<P, ShapeT1<8>>();                      \
     default: return layout_of<P, ShapeWide6DFor<P>>();                  \
     }
     if (prec == NIV_FP32) { NIV_LAYOUT(NIV_FP32) }
@@ -141,6 +145,10 @@ hipError_t launch_prepare(const Model &m, const float *params, void *prepared,
     case kPE32: return prepare_t<P, ShapePE<32>>(m, params, prepared, st);              \
     case kPE64: return prepare_t<P, ShapePE<64>>(m, params, prepared, st);              \
     case kRoom6D: return prepare_t<P, ShapeRoom6D>(m, params, prepared, st);            \
+    case kT1L2: return prepare_t<P, ShapeT1<2>>(m, params, prepared, st);               \
+    case kT1L4: return prepare_t<P, ShapeT1<4>>(m, params, prepared, st);               \
+    case kT1L6: return prepare_t<P, ShapeT1<6>>(m, params, prepared, st);               \
+    case kT1L8: return prepare_t<P, ShapeT1<8>>(m, params, prepared, st);               \
     default: return prepare_t<P, ShapeWide6DFor<P>>(m, params, prepared, st);           \
     }
     if (prec == NIV_FP32) { NIV_PREP(NIV_FP32) }
@@ -269,6 +277,16 @@ hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const 
         if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeRoom6D, true, 4>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeRoom6D, true, 4>(a, tu, st);
         return query_b<NIV_BF16, ShapeRoom6D, true, 4>(a, tu, st);
+#define NIV_T1(K, NL)                                                                  \
+    case K:                                                                            \
+        if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeT1<NL>, true, 4>(a, tu, st);  \
+        if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeT1<NL>, true, 4>(a, tu, st);  \
+        return query_b<NIV_BF16, ShapeT1<NL>, true, 4>(a, tu, st);
+    NIV_T1(kT1L2, 2)
+    NIV_T1(kT1L4, 4)
+    NIV_T1(kT1L6, 6)
+    NIV_T1(kT1L8, 8)
+#undef NIV_T1
     default:  // lane-sliced encoding: the LDS holds the whole weight block
         if (prec == NIV_FP32) return query_b<NIV_FP32, ShapeWide6DFor<NIV_FP32>, false, 2>(a, tu, st);
         if (prec == NIV_FP16) return query_b<NIV_FP16, ShapeWide6D, true, 2>(a, tu, st);
@@ -280,7 +298,7 @@ hipError_t launch_query(const Model &m, QueryArgs &a, niv_precision prec, const 
 // the position clamped to the box as in k_query, then the same encoding
 // function the fused kernel runs for this model and precision, which
 // records each corner's entry.  Non-finite positions give 0xFFFFFFFF.
-template <int P, bool F32C, bool SLICED>
+template <int P, bool F32C, bool SLICED, bool F4 = false>
 __global__ __launch_bounds__(256) void k_trace_corners(const uint8_t *__restrict__ model,
                                                        uint64_t grid_off, uint32_t grid_bytes,
                                                        uint32_t hmask, const Box6 box,
@@ -304,7 +322,10 @@ __global__ __launch_bounds__(256) void k_trace_corners(const uint8_t *__restrict
     const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
     for (int l = 0; l < n_levels; ++l) {
         f2 f;
-        if constexpr (SLICED) {
+        if constexpr (F4) {
+            const f4 f4v = encode_level_buf4<P, F32C, true>(lvs[l], p, hmask, rsrc, pf, o + 8 * l);
+            f = (f2){f4v.x, f4v.y};
+        } else if constexpr (SLICED) {
             const LevelRegs lc = load_level(lvs + l);
             LevelFetch<P> lf;
             level_issue_vec<P, true>(lc, p, hmask, rsrc, lf, o + 8 * l);
@@ -338,7 +359,17 @@ hipError_t launch_trace_corners(const Model &m, niv_precision prec, bool train, 
     const dim3 grid((unsigned)((count + 255) / 256)), blk(256);
     const int nl = m.cfg.n_levels;
     const bool sliced = m.kind == kWide6D && prec != NIV_FP32;
-    if (prec == NIV_FP32)
+    if (m.cfg.n_features == 4) {
+        if (prec == NIV_FP32)
+            hipLaunchKernelGGL((k_trace_corners<NIV_FP32, false, false, true>), grid, blk, 0, st, md, goff,
+                               gbytes, hmask, box, pos, count, nl, out);
+        else if (prec == NIV_FP16)
+            hipLaunchKernelGGL((k_trace_corners<NIV_FP16, true, false, true>), grid, blk, 0, st, md, goff,
+                               gbytes, hmask, box, pos, count, nl, out);
+        else
+            hipLaunchKernelGGL((k_trace_corners<NIV_BF16, false, false, true>), grid, blk, 0, st, md, goff,
+                               gbytes, hmask, box, pos, count, nl, out);
+    } else if (prec == NIV_FP32)
         hipLaunchKernelGGL((k_trace_corners<NIV_FP32, false, false>), grid, blk, 0, st, md, goff, gbytes,
                            hmask, box, pos, count, nl, out);
     else if (sliced && prec == NIV_FP16)

@@ -40,11 +40,20 @@ __device__ inline void wave_lds_fence()
 }
 
 // ---------------------------------------------------------------- fused query
+// Waves per SIMD the register allocation must allow: 4 for the FP16 query
+// of the staged grid shapes (at most 128 VGPRs; the LDS of a 512-thread workgroup
+// allows two workgroups per CU, i.e. four waves per SIMD), else no bound.
+template <int P, class S, bool TRAIN> constexpr int query_min_waves()
+{
+    return (P == NIV_FP16 && !TRAIN && !S::SL && S::PB == 0) ? 4 : 1;
+}
+
 // PROBE (measurement only): the encoding stage alone, with the launch shape,
 // pixel order and encoding functions of the query, writing one word per
 // pixel (E[3q]) instead of running the network.
 template <int P, class S, bool WLDS, int TB, bool TRAIN, int BLOCK, bool PROBE = false>
-__global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(query_min_waves<P, S, TRAIN>())))
+void k_query(const QueryArgs a)
 {
     static_assert(!PROBE || (!TRAIN && !S::SL), "probe: staged query encoding");
     constexpr int kWavesPerBlock = BLOCK / 64;
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         // the FP32 and BF16 queries overlap the levels' gathers; the FP16
         // query and the training forward go level by level (measured faster:
         // paired dense loads, and the training kernel's registers)
-        constexpr bool PIPE = !F32C && !TRAIN;
+        constexpr bool PIPE = !F32C && !TRAIN && S::F == 2;
         if constexpr (S::L > 0 && PIPE) {
             // grid levels for every lane (lanes without work encode the box
             // corner and store zeros), so that the gathers are not inside a
@@ -367,7 +376,26 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
             }
         }
         if (work) {
-            if constexpr (S::L > 0 && !PIPE) {
+            if constexpr (S::L > 0 && S::F == 4) {
+                // four features per entry: one 8- or 16-byte load per corner
+                const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
+#pragma unroll
+                for (int l = 0; l < S::L; ++l) {
+                    const f4 f = encode_level_buf4<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
+                    if constexpr (P == NIV_FP32) {
+                        row[4 * l] = f2u(f.x);
+                        row[4 * l + 1] = f2u(f.y);
+                        row[4 * l + 2] = f2u(f.z);
+                        row[4 * l + 3] = f2u(f.w);
+                    } else if constexpr (O::NS == 2) {
+                        Prec<P>::split(f.x, f.y, row[2 * l], row[O::PART_DW + 2 * l]);
+                        Prec<P>::split(f.z, f.w, row[2 * l + 1], row[O::PART_DW + 2 * l + 1]);
+                    } else {
+                        row[2 * l] = Prec<P>::pack(f.x, f.y);
+                        row[2 * l + 1] = Prec<P>::pack(f.z, f.w);
+                    }
+                }
+            } else if constexpr (S::L > 0 && !PIPE) {
                 // level by level, the storage kind as a branch (paired 8-byte
                 // loads on dense levels)
                 const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
@@ -409,23 +437,24 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
                 pe[6 * S::PB + 3] = 0.0f;
                 if constexpr (P == NIV_FP32) {
 #pragma unroll
-                    for (int k = 0; k < S::PEW; ++k) row[2 * S::L + k] = f2u(pe[k]);
+                    for (int k = 0; k < S::PEW; ++k) row[S::GF + k] = f2u(pe[k]);
                 } else {
 #pragma unroll
                     for (int k = 0; k < S::PEW / 2; ++k) {
                         if constexpr (O::NS == 2)
-                            Prec<P>::split(pe[2 * k], pe[2 * k + 1], row[S::L + k], row[O::PART_DW + S::L + k]);
+                            Prec<P>::split(pe[2 * k], pe[2 * k + 1], row[S::GF / 2 + k],
+                                           row[O::PART_DW + S::GF / 2 + k]);
                         else
-                            row[S::L + k] = Prec<P>::pack(pe[2 * k], pe[2 * k + 1]);
+                            row[S::GF / 2 + k] = Prec<P>::pack(pe[2 * k], pe[2 * k + 1]);
                     }
                 }
             }
             const float rn = __builtin_amdgcn_rsqf(n2);
             float sh[16];
             sh16(nx * rn, ny * rn, nz * rn, sh);
-            constexpr int base = (P == NIV_FP32) ? 2 * S::L + S::PEW : S::L + S::PEW / 2;
+            constexpr int base = (P == NIV_FP32) ? S::GF + S::PEW : (S::GF + S::PEW) / 2;
             // zero columns that pad the input to a multiple of 16
-            constexpr int used = 2 * S::L + S::PEW + 16 + 16 * S::NEX;
+            constexpr int used = S::GF + S::PEW + 16 + 16 * S::NEX;
             if constexpr (P == NIV_FP32) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) row[base + k] = f2u(sh[k]);
@@ -458,7 +487,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(const QueryArgs a)
         } else {
             // no bias anywhere: an all-zero input gives E = 0 (the
             // pipelined grid columns are already zero)
-            constexpr int done = !PIPE ? 0 : (P == NIV_FP32 ? 2 * S::L : S::L);
+            constexpr int done = !PIPE ? 0 : (P == NIV_FP32 ? S::GF : S::GF / 2);
 #pragma unroll
             for (int k = 0; k < O::NS * O::PART_DW; ++k)
                 if (k % O::PART_DW >= done) row[k] = 0u;

@@ -71,7 +71,7 @@ template <int P, class S> struct Bwd {
     static constexpr int T_HID = NOB * NIB;
     static constexpr int N_TILES = T_OUT + (S::H - 1) * T_HID + NOB * (S::DIN / 16);
     static constexpr int tile_base(int k) { return T_OUT + (S::H - 1 - k) * T_HID; }
-    static_assert(S::L % 8 == 0, "grid rows come in blocks of 16");
+    static_assert(S::L % 8 == 0 && S::F == 2, "grid rows come in blocks of 16, two features a level");
     static_assert(S::DIN % 16 == 0, "input rows come in blocks of 16");
 };
 

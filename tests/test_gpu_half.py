@@ -81,7 +81,8 @@ def test_upsampler_parity(W, H):
 
 
 @pytest.mark.parametrize("wname,prec", [("room_1080p", "fp32"), ("room_1080p", "fp16"),
-                                        ("room_1080p", "bf16"), ("room_1080p_pe64", "fp16")])
+                                        ("room_1080p", "bf16"), ("room_1080p_pe64", "fp16"),
+                                        ("room_1080p_g8", "fp16"), ("room_1080p_g8", "fp32")])
 def test_query_half_parity(wname, prec):
     """The whole half-resolution path on the 1920x1080 room G-buffer."""
     w, oc, m, params = _model(wname)

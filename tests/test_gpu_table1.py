@@ -1,0 +1,148 @@
+"""Parity of the fused query for the grid networks of Table 1 (2, 4, 6 or 8
+levels of four features per entry, T = 2^17, width 64, four layers) with
+the FP64 oracle, through the C interface, on the GPU.  Same bars as the
+two-feature models: FP32 max relative error <= 1e-5 (term scale), FP16/BF16
+per-image relative L2 <= 2e-3 against the oracle on the same rounded
+parameters; flags exact away from sign ties; corner indices bit-exact on the
+FP64-coordinate paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from niv_synth import get_workload, make_params
+from niv_metrics import term_scale, max_rel_fp32, max_rel_floored, rel_l2, assert_flags, sign_margin
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+LEVELS = (2, 4, 6, 8)
+
+
+def _round(p, prec):
+    if prec == "fp32":
+        return p.astype(np.float64)
+    if prec == "fp16":
+        return p.astype(np.float16).astype(np.float64)
+    return torch.from_numpy(p).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _check(prec, E, E_ref, scale):
+    if prec == "fp32":
+        err = max_rel_fp32(E, E_ref, scale)
+        assert err <= 1e-5, (err, max_rel_floored(E, E_ref))
+    else:
+        err = rel_l2(E, E_ref)
+        assert err <= 2e-3, err
+    return err
+
+
+@pytest.fixture(scope="module")
+def room_gbuffer(workload_gbuffer):
+    _, g = workload_gbuffer("room_1080p")
+    return {k: g[k].reshape(-1, g[k].shape[-1]) if g[k].ndim == 3 else g[k].reshape(-1)
+            for k in ("pos", "nrm", "albedo", "mask")}
+
+
+def _model(levels):
+    from paper_2602_12949_amd import NIV
+    w = get_workload(f"room_1080p_g{levels}")
+    oc = O.config_from_workload(w)
+    params = make_params(O.n_grid_values(oc), O.mat_shapes(oc), w.param_seed, *w.grid_init)
+    return w, oc, NIV(w.model_dict()), params
+
+
+def _t(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("levels", LEVELS)
+def test_grid_room_1080p_full_frame_parity(room_gbuffer, levels, prec):
+    """Every pixel of the 1920x1080 room G-buffer against the oracle."""
+    g = room_gbuffer
+    w, oc, m, params = _model(levels)
+    print(f"room_1080p_g{levels} {prec}", flush=True)
+    prepared = m.prepare(_t(params), prec)
+    E, L, fl = m.query(_t(g["pos"]), _t(g["nrm"]), prepared, prec, albedo=_t(g["albedo"]),
+                       mask=_t(g["mask"]))
+    torch.cuda.synchronize()
+    E, L, fl = (E.cpu().numpy().astype(np.float64), L.cpu().numpy().astype(np.float64),
+                fl.cpu().numpy())
+    pr = _round(params, prec)
+    E_ref, L_ref, fl_ref, x0 = O.query(oc, pr, g["pos"], g["nrm"], albedo=g["albedo"],
+                                       mask=g["mask"], want_x0=True)
+    sc = term_scale(O.split_params(oc, pr)[1:], x0)
+    ok = g["mask"].astype(bool)
+    err = _check(prec, E[ok], E_ref[ok], sc[ok])
+    _check(prec, L[ok], L_ref[ok], (sc * g["albedo"] / np.pi)[ok])
+    assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
+    assert (E[~ok] == 0).all()
+    print(f"  err {err:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("levels", [2, 6])
+def test_grid_encoded_inputs(room_gbuffer, levels, prec):
+    """The four interpolated features per level, the SH and the zero padding
+    the kernel feeds the network, in the parameter order, against the
+    oracle's input vector."""
+    g = room_gbuffer
+    w, oc, m, params = _model(levels)
+    rng = np.random.default_rng(23)
+    idx = rng.choice(np.nonzero(g["mask"])[0], 5000, replace=False)
+    pos, nrm = g["pos"][idx].copy(), g["nrm"][idx]
+    pos[:4] = [[-0.5, 2.0, 5.0], [10.0, 4.0, 10.0], [0.0, 0.0, 0.0], [5.0, 1.0, 2.5]]
+    prepared = m.prepare(_t(params), prec)
+    _, _, fl, x_in = m.query(_t(pos), _t(nrm), prepared, prec, want_inputs=True)
+    torch.cuda.synchronize()
+    x_in = x_in.cpu().numpy().astype(np.float64)
+    fl = fl.cpu().numpy()
+    _, _, fl_ref, x0 = O.query(oc, _round(params, prec), pos, nrm, want_x0=True)
+    assert x_in.shape == x0.shape == (5000, 4 * levels + 16)
+    tol = {"fp32": 2e-6, "fp16": 2.0 ** -10, "bf16": 2.0 ** -15}[prec]
+    err = np.abs(x_in - x0) / np.maximum(np.abs(x0), 1.0)
+    assert err.max() <= tol, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    assert (fl[:4] & 1).tolist() == [1, 0, 0, 0] and ((fl_ref[:4] & 1) == (fl[:4] & 1)).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_grid_corner_indices(room_gbuffer, prec):
+    """The entries the four-feature encoding reads for every corner of the
+    8-level network, against the oracle's corner indices: exact for the FP64
+    cell coordinates (FP32, BF16); the FP16 query's FP32 coordinates may
+    choose the neighbouring cell only on a cell face."""
+    w, oc, m, params = _model(8)
+    lt = O.level_table(oc)
+    prepared = m.prepare(_t(np.zeros_like(params)), prec)
+    pos = room_gbuffer["pos"][room_gbuffer["mask"] != 0][::3].astype(np.float32)
+    got = m.corner_indices(_t(pos), prepared, prec, False).cpu().numpy()
+    got = got.view(np.uint32).astype(np.int64) - lt["offset"][None, :, None]
+    ref = O.corners_many(oc, pos)
+    bad = got != ref
+    if prec != "fp16":
+        assert not bad.any(), np.argwhere(bad)[:4]
+    else:
+        lo, hi = np.array(oc.aabb_min[:3]), np.array(oc.aabb_max[:3])
+        p = np.clip(pos.astype(np.float64), lo, hi)
+        k = lt["res"][None, :, None] / (hi - lo)[None, None, :]
+        s = p[:, None, :] * k - (lo * k[0])[None]
+        face = (np.abs(s - np.rint(s)) < 1e-3).any(-1)
+        assert (face | ~bad.any(-1)).all()
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 4097])
+def test_grid_ragged_counts(room_gbuffer, n):
+    g = room_gbuffer
+    w, oc, m, params = _model(4)
+    pos, nrm, mask = g["pos"][-n:], g["nrm"][-n:], g["mask"][-n:]
+    prepared = m.prepare(_t(params), "fp32")
+    E, _, fl = m.query(_t(pos), _t(nrm), prepared, "fp32", mask=_t(mask))
+    torch.cuda.synchronize()
+    E = E.cpu().numpy().astype(np.float64)
+    E_ref, _, fl_ref, x0 = O.query(oc, params.astype(np.float64), pos, nrm, mask=mask,
+                                   want_x0=True)
+    sc = term_scale(O.split_params(oc, params.astype(np.float64))[1:], x0)
+    _check("fp32", E, E_ref, sc)
+    assert_flags(fl.cpu().numpy(), fl_ref, E_ref, sign_margin("fp32", E_ref, sc))
+

@@ -667,3 +667,31 @@ def test_corners_many_equals_brute_force():
                         h = ((v[0] * 1) ^ (v[1] * 2654435761) ^ (v[2] * 805459861)) & 0xFFFFFFFF
                         want = h & (T - 1)
                     assert many[q, l, k] == want, (name, q, l, k)
+
+
+def test_four_feature_levels_are_two_two_feature_grids():
+    """Four features per entry (Table 1's grid networks, Sec. 4.1): each
+    level's four interpolated features equal those of two-feature grids on the
+    same levels that hold the entries' first and second feature pairs."""
+    kw = dict(n_levels=4, log2_T=10, base_res=4.0, per_level_scale=math.sqrt(2.0),
+              width=16, n_hidden=2)
+    c4, c2 = _cfg(n_features=4, **kw), _cfg(n_features=2, **kw)
+    rng = np.random.default_rng(44)
+    g4 = rng.uniform(-1, 1, (O.n_grid_values(c4) // 4, 4))
+    m4 = np.zeros(O.n_params(c4) - g4.size)
+    m2 = np.zeros(O.n_params(c2) - g4.size // 2)
+    pos = rng.uniform(-0.1, 1.1, (500, 3)).astype(np.float32)
+    nrm = rng.normal(size=(500, 3)).astype(np.float32)
+    _, _, fl4, x4 = O.query(c4, np.concatenate([g4.ravel(), m4]), pos, nrm, want_x0=True)
+    halves = []
+    for h in range(2):
+        p2 = np.concatenate([np.ascontiguousarray(g4[:, 2 * h:2 * h + 2]).ravel(), m2])
+        _, _, fl2, x2 = O.query(c2, p2, pos, nrm, want_x0=True)
+        assert (fl2 == fl4).all()
+        halves.append(x2)
+    L = kw["n_levels"]
+    assert x4.shape[1] == 4 * L + 16 and halves[0].shape[1] == 2 * L + 16
+    for l in range(L):
+        np.testing.assert_array_equal(x4[:, 4 * l:4 * l + 2], halves[0][:, 2 * l:2 * l + 2])
+        np.testing.assert_array_equal(x4[:, 4 * l + 2:4 * l + 4], halves[1][:, 2 * l:2 * l + 2])
+    np.testing.assert_array_equal(x4[:, 4 * L:], halves[0][:, 2 * L:])
