@@ -63,7 +63,8 @@ template <int P, class S> struct Bwd {
     static constexpr int64_t CHUNK_BYTES = (int64_t)(S::DIN + S::H * S::W) * 64 * ES;
     static constexpr int NMLP = S::W * S::DIN + (S::H - 1) * S::W * S::W + 3 * S::W;
     static constexpr int GB_BYTES = S::W * 64 * ES;            // gradient, [neuron][64]
-    static constexpr int DX_BYTES = 64 * 2 * S::L * 4;         // grid-feature gradient, [64][2L]
+    static constexpr int NFP = 2 * S::L + 2;                  // padded row of the grid-feature gradient
+    static constexpr int DX_BYTES = 64 * NFP * 4;              // grid-feature gradient, [64][2L + 2]
     static constexpr int WB_BYTES = (GB_BYTES > DX_BYTES ? GB_BYTES : DX_BYTES) + 3 * 64 * 4;
     // weight-gradient tiles (16x16, f4 per lane) a wave accumulates in registers
     // over all its chunks: the output layer's, then layer H-1 down to 0
@@ -147,7 +148,7 @@ struct BwdArgs {
     const uint8_t *model;      // prepared model (level table first)
     float *grads;              // [n_params]
     float *dw_part;            // [wave][weights] each wave's weight gradient
-    float *dx0;                // [n][2L] gradient of each sample's grid features
+    float *dx0;                // [chunk][L][64] float pairs: gradient of each sample's grid features
     uint8_t *sflag;            // [n] 1: the sample's features scatter into the grid
     uint32_t *vmax;            // step word [0]: largest |feature gradient| x loss_scale of a
                                // scattering sample (float bits; bounds every contribution)
@@ -405,15 +406,17 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
 #pragma unroll
                 for (int ob = 0; ob < B::NOB; ++ob) G[t][ob] = Gn[t][ob];
         }
-        // ---- grid-feature gradients: rows 16ib + 4g + r of sample 16t + j -> [sample][2L]
+        // ---- grid-feature gradients: rows 16ib + 4g + r of sample 16t + j,
+        // through LDS ([sample][2L], rows padded by two floats so that a
+        // level's column spreads over the banks), out as [chunk][level][64]
+        // float pairs (one coalesced store per level)
         {
             float *dx = reinterpret_cast<float *>(wbuf);
-            constexpr int NF = 2 * S::L;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int ib = 0; ib < B::GIB; ++ib) {
-                    float *d = dx + (16 * t + j) * NF + 16 * ib + 4 * g;
+                    float *d = dx + (16 * t + j) * B::NFP + 16 * ib + 4 * g;
                     d[0] = G[t][ib].x; d[1] = G[t][ib].y; d[2] = G[t][ib].z; d[3] = G[t][ib].w;
                 }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -429,14 +432,13 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
                 for (int c = 0; c < 3; ++c) scatter &= __builtin_isfinite(a.x[3 * q + c]);
             }
             if (live) {
-                const float4 *mine = reinterpret_cast<const float4 *>(dx + lane * NF);
-                float4 *dst = reinterpret_cast<float4 *>(a.dx0 + q * NF);
+                const float2 *mine = reinterpret_cast<const float2 *>(dx + lane * B::NFP);
+                float2 *dst = reinterpret_cast<float2 *>(a.dx0) + chunk * 64 * S::L + lane;
 #pragma unroll
-                for (int k = 0; k < NF / 4; ++k) {
-                    const float4 v = mine[k];
-                    dst[k] = v;
-                    if (scatter)
-                        gmax = fmaxf(gmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+                for (int l = 0; l < S::L; ++l) {
+                    const float2 v = mine[l];
+                    dst[l * 64] = v;
+                    if (scatter) gmax = fmaxf(gmax, fmaxf(fabsf(v.x), fabsf(v.y)));
                 }
                 a.sflag[q] = scatter ? 1 : 0;
             }
@@ -522,7 +524,7 @@ constexpr int kStatusWords = 4;
 
 struct ScatterArgs {
     const float *x;            // [n][3] sample positions
-    const float *dx0;          // [n][2L]
+    const float *dx0;          // [chunk][L][64] float pairs
     const uint8_t *sflag;      // [n]
     const uint8_t *model;      // prepared model (level table first)
     uint32_t *counts;          // [bins][kScatterBlocks] per workgroup, then their offsets
@@ -547,9 +549,9 @@ struct ScatterArgs {
 // Both passes: one wave takes a 64-sample chunk through every level (the
 // level is wave-uniform, so its constants are scalar loads), with the chunks
 // strided identically, so a workgroup writes exactly the records it counted.
-constexpr int kScatterWaves = 8;
+constexpr int kScatterWaves = 16;
 constexpr int kScatterThreads = 64 * kScatterWaves;
-constexpr int kScatterMaxLevels = 16;          // levels of the trainable shapes (LDS of the write pass)
+constexpr int kScatterMaxLevels = 16;          // levels of the trainable shapes
 
 __device__ inline void wave_lds_sync()
 {
@@ -603,16 +605,16 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_count(const ScatterArg
         a.counts[(int64_t)b * kScatterBlocks + blockIdx.x] = cnt[b];
 }
 
-// Per-wave LDS of the write pass: the chunk's feature gradients as [64][L + 1]
-// float pairs (one pad pair per row spreads a level's column over the
-// banks), 512 staged records, and three 64-entry per-bin arrays.
-__host__ __device__ constexpr int write_wave_bytes(int n_levels)
+// Per-wave LDS of the write pass: 512 staged records and three 64-entry
+// per-bin arrays.
+__host__ __device__ constexpr int write_wave_bytes()
 {
-    return 64 * (n_levels + 1) * 8 + 512 * 16 + 3 * 64 * 4;
+    return 512 * 16 + 3 * 64 * 4;
 }
 
-// Write pass.  The chunk's feature gradients are read once, coalesced, into
-// LDS.  Per level, the wave orders its 512 records by bin in LDS: a histogram
+// Write pass.  Per level the chunk's feature gradients are one coalesced
+// load (the backward stores them level-major per chunk), and the wave
+// orders its 512 records by bin in LDS: a histogram
 // over (a window of 64 of) the level's bins gives each record its rank in its
 // bin, one counter update per bin reserves the wave's run in the workgroup's
 // segment of that bin, and a scan of the histogram places the runs one after
@@ -631,10 +633,9 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
     typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int L = a.n_levels;
-    uint8_t *mine = dyn + wave * write_wave_bytes(L);
-    float2 *gblk = reinterpret_cast<float2 *>(mine);
-    u4 *stage = reinterpret_cast<u4 *>(mine + 64 * (L + 1) * 8);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(mine + 64 * (L + 1) * 8 + 512 * 16);
+    uint8_t *mine = dyn + wave * write_wave_bytes();
+    u4 *stage = reinterpret_cast<u4 *>(mine);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(mine + 512 * 16);
     uint32_t *bbase = hist + 64, *lstart = hist + 128;
     for (int b = threadIdx.x; b < a.n_bins; b += kScatterThreads)
         cnt[b] = a.bin_start[b] + a.counts[(int64_t)b * kScatterBlocks + blockIdx.x];
@@ -650,20 +651,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
     for (int64_t chunk = (int64_t)blockIdx.x * kScatterWaves + wave; chunk < n_chunks;
          chunk += (int64_t)gridDim.x * kScatterWaves) {
         const int64_t q0 = chunk * 64;
-        const int rows = (int)(a.n - q0 < 64 ? a.n - q0 : 64);
-        const float2 *src = reinterpret_cast<const float2 *>(a.dx0) + q0 * L;
-        for (int u = lane; u < rows * L; u += 64) {   // pair u = (sample u / L, level u % L)
-            const int r = u / L;
-            gblk[r * (L + 1) + (u - r * L)] = src[u];
-        }
+        const float2 *src = reinterpret_cast<const float2 *>(a.dx0) + q0 * L + lane;
         double p[3] = {a.lo[0], a.lo[1], a.lo[2]};
         const bool live = scatter_sample(a, q0 + lane, p);
-        wave_lds_sync();
         for (int l = 0; l < L; ++l) {
             uint32_t idx[8];
             float w[8];
             level_corners(lvs[l], p, a.hash_mask, idx, w);
-            const float2 gg = gblk[lane * (L + 1) + l];
+            const float2 gg = live ? src[l * 64] : make_float2(0.0f, 0.0f);
             const float g0 = gg.x * a.loss_scale, g1 = gg.y * a.loss_scale;
             const uint32_t off = lvs[l].off;
             const uint32_t size = lvs[l].dense ? lvs[l].s1 * lvs[l].s2 : a.hash_mask + 1u;
@@ -1037,7 +1032,7 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
     L.mask_off = L.x_off + align256(nc * B::CHUNK_BYTES);
     L.dE_off = L.mask_off + align256(nc * S::H * (S::W / 32) * 64 * 4);
     L.dx0_off = L.dE_off + align256(n * 3 * 4);
-    L.sflag_off = L.dx0_off + align256(n * 2 * S::L * 4);
+    L.sflag_off = L.dx0_off + align256((n + 63) / 64 * 64 * 2 * S::L * 4);
     L.counts_off = L.sflag_off + align256(n);
     L.start_off = L.counts_off + align256((int64_t)kMaxBins * kScatterBlocks * 4);
     L.work_off = L.start_off + align256((kMaxBins + 1) * 4);
@@ -1206,13 +1201,13 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
     hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
-    const int write_lds = kScatterWaves * write_wave_bytes(sa.n_levels);
+    const int write_lds = kScatterWaves * write_wave_bytes();
     constexpr bool H16 = !B::F32;
     static bool write_lds_set = false;   // dynamic LDS beyond 64 KB must be allowed per kernel
     if (!write_lds_set) {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_grid_write<H16>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kScatterWaves * write_wave_bytes(kScatterMaxLevels));
+                                kScatterWaves * write_wave_bytes());
         if (e != hipSuccess) return e;
         write_lds_set = true;
     }
