@@ -41,7 +41,12 @@ template <> struct Prec<NIV_FP16> {
     }
     // A K = 16 product issued as the K = 32 instruction with the upper half
     // of each lane's operands zero: lane (g, j) then pairs the same four
-    // products as the K = 16 layout, and the sum is unchanged.
+    // products as the K = 16 layout, and the sum is unchanged.  (The K = 16
+    // instruction reading as its accumulator the result of a K = 32 one
+    // needs 5 wait states between them on gfx950, measured; the compiler
+    // inserts none when the registers coincide exactly, as they do when a
+    // half-depth product continues a full one.  Same-opcode chains are
+    // correct with none.)
     __device__ static f4 mma_half(u2 a, u2 b, f4 c) {
         return mma((u4){a.x, a.y, 0u, 0u}, (u4){b.x, b.y, 0u, 0u}, c);
     }
@@ -68,8 +73,8 @@ template <> struct Prec<NIV_BF16> {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
                                                        __builtin_bit_cast(bf8, b), c, 0, 0, 0);
     }
-    // as for FP16: the K = 16 BF16 instruction gave wrong accumulators for
-    // the last tile of a wave on this target, the zero-padded K = 32 one not
+    // as for FP16 (the K = 16 BF16 instruction has the same dependency on a
+    // K = 32 one that wrote its accumulator)
     __device__ static f4 mma_half(u2 a, u2 b, f4 c) {
         return mma((u4){a.x, a.y, 0u, 0u}, (u4){b.x, b.y, 0u, 0u}, c);
     }

@@ -66,6 +66,9 @@ template <int P, class S> struct Bwd {
     static constexpr int NFP = 2 * S::L + 2;                  // padded row of the grid-feature gradient
     static constexpr int DX_BYTES = 64 * NFP * 4;              // grid-feature gradient, [64][2L + 2]
     static constexpr int WB_BYTES = (GB_BYTES > DX_BYTES ? GB_BYTES : DX_BYTES) + 3 * 64 * 4;
+    // LDS of a workgroup: four waves' blocks, reused at the end for the
+    // workgroup's weight gradient
+    static constexpr int LDS_BYTES = 4 * WB_BYTES > NMLP * 4 ? 4 * WB_BYTES : NMLP * 4;
     // weight-gradient tiles (16x16, f4 per lane) a wave accumulates in registers
     // over all its chunks: the output layer's, then layer H-1 down to 0
     static constexpr int T_OUT = S::W / 16;
@@ -147,7 +150,7 @@ struct BwdArgs {
     const float *x;            // [n][3] sample positions
     const uint8_t *model;      // prepared model (level table first)
     float *grads;              // [n_params]
-    float *dw_part;            // [wave][weights] each wave's weight gradient
+    float *dw_part;            // [workgroup][weights] each workgroup's weight gradient
     float *dx0;                // [chunk][L][64] float pairs: gradient of each sample's grid features
     uint8_t *sflag;            // [n] 1: the sample's features scatter into the grid
     uint32_t *vmax;            // step word [0]: largest |feature gradient| x loss_scale of a
@@ -450,38 +453,49 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
     for (int off = 32; off >= 1; off >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, off));
     const float cmax = gmax * a.loss_scale;
     if (lane == 0 && cmax == cmax && cmax > 0.0f) atomicMax(a.vmax, f2u(cmax));
-    // this wave's weight gradient to a row of its own; k_dw_sum adds the rows
-    // (no atomics, and a fixed summation order).  Tile element r of lane (g, j)
-    // is row 16 ob + 4 g + r, column 16 ib + j of the layer's matrix.
-    float *row = a.dw_part + ((int64_t)blockIdx.x * 4 + wave) * B::NMLP;
-    {
-        const int woff = S::W * S::DIN + (S::H - 1) * S::W * S::W;   // output layer [3][W]
+    // the workgroup's weight gradient: the four waves add their tiles into
+    // one LDS copy, wave after wave, and it goes out as one row; k_dw_sum adds
+    // the rows (no atomics, a fixed summation order).  Tile element r of lane
+    // (g, j) is row 16 ob + 4 g + r, column 16 ib + j of the layer's matrix.
+    __syncthreads();   // every wave is done with its block
+    float *red = reinterpret_cast<float *>(smem);
+    for (int k = threadIdx.x; k < B::NMLP; k += 256) red[k] = 0.0f;
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+            {
+                const int woff = S::W * S::DIN + (S::H - 1) * S::W * S::W;   // output layer [3][W]
 #pragma unroll
-        for (int nb = 0; nb < S::W / 16; ++nb)
-            if (g == 0) {
-                row[woff + 0 * S::W + 16 * nb + j] = dwacc[nb].x;
-                row[woff + 1 * S::W + 16 * nb + j] = dwacc[nb].y;
-                row[woff + 2 * S::W + 16 * nb + j] = dwacc[nb].z;
+                for (int nb = 0; nb < S::W / 16; ++nb)
+                    if (g == 0) {
+                        red[woff + 0 * S::W + 16 * nb + j] += dwacc[nb].x;
+                        red[woff + 1 * S::W + 16 * nb + j] += dwacc[nb].y;
+                        red[woff + 2 * S::W + 16 * nb + j] += dwacc[nb].z;
+                    }
             }
-    }
 #pragma unroll
-    for (int k = S::H - 1; k >= 0; --k) {
-        const int dk = (k == 0) ? S::DIN : S::W;
-        const int woff = (k == 0) ? 0 : S::W * S::DIN + (k - 1) * S::W * S::W;
-        const int tb = B::tile_base(k);
+            for (int k = S::H - 1; k >= 0; --k) {
+                const int dk = (k == 0) ? S::DIN : S::W;
+                const int woff = (k == 0) ? 0 : S::W * S::DIN + (k - 1) * S::W * S::W;
+                const int tb = B::tile_base(k);
 #pragma unroll
-        for (int ob = 0; ob < B::NOB; ++ob)
+                for (int ob = 0; ob < B::NOB; ++ob)
 #pragma unroll
-            for (int ib = 0; ib < (S::DIN > S::W ? S::DIN : S::W) / 16; ++ib) {
-                if (ib * 16 >= dk) break;
-                const f4 v = dwacc[tb + ob * (dk / 16) + ib];
-                float *dst = row + woff + (16 * ob + 4 * g) * dk + 16 * ib + j;
-                dst[0] = v.x;
-                dst[dk] = v.y;
-                dst[2 * dk] = v.z;
-                dst[3 * dk] = v.w;
+                    for (int ib = 0; ib < (S::DIN > S::W ? S::DIN : S::W) / 16; ++ib) {
+                        if (ib * 16 >= dk) break;
+                        const f4 v = dwacc[tb + ob * (dk / 16) + ib];
+                        float *dst = red + woff + (16 * ob + 4 * g) * dk + 16 * ib + j;
+                        dst[0] += v.x;
+                        dst[dk] += v.y;
+                        dst[2 * dk] += v.z;
+                        dst[3 * dk] += v.w;
+                    }
             }
+        }
+        __syncthreads();
     }
+    float *row = a.dw_part + (int64_t)blockIdx.x * B::NMLP;
+    for (int k = threadIdx.x; k < B::NMLP; k += 256) row[k] = red[k];
 }
 
 // Column sums of the per-workgroup weight gradients: rows r, r + Y, r + 2Y,
@@ -947,15 +961,56 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, floa
                        int64_t n_grid)
 {
     if (status && status[2] != 0u) return;
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto step = [&](float pv, float g, float mv, float vv, float &mk, float &vk) {
+        mk = b1 * mv + (1.0f - b1) * g;
+        vk = b2 * vv + (1.0f - b2) * g * g;
+        return pv - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+    };
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; k < n; k += stride) {
-        const float g = gr[k];
-        const float mk = b1 * m[k] + (1.0f - b1) * g;
-        const float vk = b2 * v[k] + (1.0f - b2) * g * g;
+    // four values per thread and iteration (16-byte accesses) where every
+    // pointer is 16-byte aligned
+    const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(gr) |
+                       reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v) |
+                       reinterpret_cast<uintptr_t>(grid_out)) & 15u) == 0;
+    int64_t k0 = 0;
+    if (vec) {
+        const int64_t n4 = n / 4;
+        for (int64_t i = tid; i < n4; i += stride) {
+            const f4 pv = reinterpret_cast<const f4 *>(p)[i], g = reinterpret_cast<const f4 *>(gr)[i];
+            const f4 mv = reinterpret_cast<const f4 *>(m)[i], vv = reinterpret_cast<const f4 *>(v)[i];
+            float mk4[4], vk4[4], pk4[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pk4[c] = step(pv[c], g[c], mv[c], vv[c], mk4[c], vk4[c]);
+            const f4 mk = {mk4[0], mk4[1], mk4[2], mk4[3]}, vk = {vk4[0], vk4[1], vk4[2], vk4[3]};
+            const f4 pk = {pk4[0], pk4[1], pk4[2], pk4[3]};
+            reinterpret_cast<f4 *>(m)[i] = mk;
+            reinterpret_cast<f4 *>(v)[i] = vk;
+            reinterpret_cast<f4 *>(p)[i] = pk;
+            if (grid_out && 4 * i + 4 > n_grid && 4 * i < n_grid) {   // the group the grid ends in
+                const float e[4] = {pk.x, pk.y, pk.z, pk.w};
+                for (int c = 0; 4 * i + c < n_grid; ++c) {
+                    if constexpr (GP == NIV_FP32) reinterpret_cast<float *>(grid_out)[4 * i + c] = e[c];
+                    else reinterpret_cast<_Float16 *>(grid_out)[4 * i + c] = (_Float16)e[c];
+                }
+            } else if (grid_out && 4 * i < n_grid) {
+                if constexpr (GP == NIV_FP32) {
+                    reinterpret_cast<f4 *>(grid_out)[i] = pk;
+                } else {
+                    const h2 a = __builtin_convertvector((f2){pk.x, pk.y}, h2);
+                    const h2 b = __builtin_convertvector((f2){pk.z, pk.w}, h2);
+                    reinterpret_cast<u2 *>(grid_out)[i] =
+                        (u2){__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)};
+                }
+            }
+        }
+        k0 = n4 * 4;
+    }
+    for (int64_t k = k0 + tid; k < n; k += stride) {
+        float mk, vk;
+        const float pk = step(p[k], gr[k], m[k], v[k], mk, vk);
         m[k] = mk;
         v[k] = vk;
-        const float pk = p[k] - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
         p[k] = pk;
         if (grid_out && k < n_grid) {
             if constexpr (GP == NIV_FP32) reinterpret_cast<float *>(grid_out)[k] = pk;
@@ -1044,7 +1099,7 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
     // one weight-gradient row per backward wave: 4 per workgroup, at most
     // one workgroup per 4 chunks and kBwdMaxBlocks in all
     const int64_t bwd_blocks = std::min<int64_t>(kBwdMaxBlocks, std::max<int64_t>(1, (nc + 3) / 4));
-    L.parts_off = L.dw_off + align256(bwd_blocks * 4 * Bwd<P, S>::NMLP * 4);
+    L.parts_off = L.dw_off + align256(bwd_blocks * Bwd<P, S>::NMLP * 4);
     // fixed-point partial sums: one row per accumulating workgroup
     L.total = L.parts_off + align256(acc_group_bound(n, S::L, n_bins) * 2 * kBinEntries * 8);
     return L;
@@ -1140,7 +1195,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     for (int c = 0; c < 3; ++c) { ba.lo[c] = a.lo[c]; ba.hi[c] = a.hi[c]; }
     {
         auto kern = k_train_bwd<P, S>;
-        const size_t lds = 4 * (size_t)B::WB_BYTES;
+        const size_t lds = (size_t)B::LDS_BYTES;
         static int max_blocks = -1, n_cu = 0;
         if (max_blocks < 0) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1164,7 +1219,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // weight gradient: the workgroups' rows summed in two passes
         const unsigned cols = (unsigned)((B::NMLP + 255) / 256);
-        const int rows = (int)blocks * 4;   // one per wave
+        const int rows = (int)blocks;   // one per workgroup
         const int fold = rows < 32 ? rows : 32;   // the first pass writes rows 0 .. fold-1
         hipLaunchKernelGGL(k_dw_sum, dim3(cols, (unsigned)fold), dim3(256), 0, stream, ba.dw_part,
                            (int64_t)B::NMLP, rows, (float *)nullptr, 1.0f);
