@@ -2,7 +2,7 @@
 // backpropagation through the MLP on the matrix cores, scatter of the
 // encoding gradient into the hash grid, and Adam.
 //
-// A step runs three kernels on the caller's stream:
+// A step runs these stages on the caller's stream:
 //   1. the fused query kernel in training mode: encodes each sample, runs
 //      the MLP, saves every layer's input (per 64-sample chunk, row-major
 //      [neuron][sample], the layout the weight-gradient products read) and
@@ -498,25 +498,34 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
     for (int k = threadIdx.x; k < B::NMLP; k += 256) row[k] = red[k];
 }
 
-// Column sums of the per-workgroup weight gradients: rows r, r + Y, r + 2Y,
-// ... of column k are added into row r (Y = gridDim.y); with out given (and
-// Y = 1) the sum, scaled, is stored to the gradient instead.
-__global__ __launch_bounds__(256) void k_dw_sum(float *part, int64_t nmlp, int rows, float *out,
-                                               float scale)
+// Column sums of the per-workgroup weight gradients, scaled, into the
+// gradient: a workgroup takes 16 columns; its 16 row groups each add rows
+// g, g + 16, g + 32, ... of a column (eight loads in flight), and the 16
+// partial sums are added in row-group order (a fixed summation order).
+__global__ __launch_bounds__(256) void k_dw_sum(const float *__restrict__ part, int64_t nmlp, int rows,
+                                               float *__restrict__ out, float scale)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= nmlp) return;
-    const int r0 = blockIdx.y, step = gridDim.y;
-    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // eight loads in flight
-    int r = r0;
-    for (; r + 7 * step < rows; r += 8 * step)
+    __shared__ float ps[16][17];
+    const int c = threadIdx.x & 15, rg = threadIdx.x >> 4;
+    const int64_t k = (int64_t)blockIdx.x * 16 + c;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (k < nmlp) {
+        int r = rg;
+        for (; r + 7 * 16 < rows; r += 8 * 16)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(r + u * step) * nmlp + k];
-    for (; r < rows; r += step) s[0] += part[(int64_t)r * nmlp + k];
+            for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(r + 16 * u) * nmlp + k];
+        for (; r < rows; r += 16) s[0] += part[(int64_t)r * nmlp + k];
 #pragma unroll
-    for (int u = 1; u < 8; ++u) s[0] += s[u];
-    if (out) out[k] = s[0] * scale;
-    else part[(int64_t)r0 * nmlp + k] = s[0];
+        for (int u = 1; u < 8; ++u) s[0] += s[u];
+    }
+    ps[rg][c] = s[0];
+    __syncthreads();
+    if (rg == 0 && k < nmlp) {
+        float t = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) t += ps[g][c];
+        out[k] = t * scale;
+    }
 }
 
 // ---------------------------------------------------------------- grid scatter
@@ -723,108 +732,83 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
     }
 }
 
+// Inclusive scan over the 64 lanes of a wave.
+__device__ inline uint32_t wave_scan_incl(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
 // Per bin (one workgroup of kScatterBlocks threads): exclusive scan of the
 // workgroups' counts, in place; the bin's total goes to bin_start[b + 1].
 __global__ __launch_bounds__(kScatterBlocks) void k_grid_scan_bins(const ScatterArgs a)
 {
-    __shared__ uint32_t v[kScatterBlocks];
-    const int b = blockIdx.x, t = threadIdx.x;
+    constexpr int kW = kScatterBlocks / 64;
+    __shared__ uint32_t wsum[kW];
+    const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     uint32_t *row = a.counts + (int64_t)b * kScatterBlocks;
-    v[t] = row[t];
+    const uint32_t c = row[t];
+    const uint32_t incl = wave_scan_incl(c, lane);
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    for (int off = 1; off < kScatterBlocks; off <<= 1) {   // inclusive Hillis-Steele scan
-        const uint32_t add = t >= off ? v[t - off] : 0u;
-        __syncthreads();
-        v[t] += add;
-        __syncthreads();
+    uint32_t before = 0u, total = 0u;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+        before += k < wv ? wsum[k] : 0u;
+        total += wsum[k];
     }
-    row[t] = t > 0 ? v[t - 1] : 0u;
-    if (t == kScatterBlocks - 1) a.bin_start[b + 1] = v[t];
+    row[t] = before + incl - c;
+    if (t == 0) a.bin_start[b + 1] = total;
 }
 
-// Exclusive scan of the bin totals (one workgroup of 1024 threads).
+// Exclusive scans of the bin totals (one workgroup of 1024 threads, two bins
+// per thread): bin starts, first accumulating workgroup of each bin
+// (ceil(total / kAccumRecords) workgroups, at least one) and the list of
+// bins split over several workgroups; the three scans share one pass.
 __global__ __launch_bounds__(1024) void k_grid_scan_totals(const ScatterArgs a)
 {
-    __shared__ uint32_t v[kMaxBins];
-    const int t = threadIdx.x;
-    for (int b = t; b < kMaxBins; b += 1024) v[b] = b < a.n_bins ? a.bin_start[b + 1] : 0u;
-    __syncthreads();
-    for (int off = 1; off < kMaxBins; off <<= 1) {
-        uint32_t add[kMaxBins / 1024];
-#pragma unroll
-        for (int k = 0; k < kMaxBins / 1024; ++k) {
-            const int b = t + 1024 * k;
-            add[k] = b >= off ? v[b - off] : 0u;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kMaxBins / 1024; ++k) v[t + 1024 * k] += add[k];
-        __syncthreads();
-    }
-    uint32_t tot[kMaxBins / 1024];
-#pragma unroll
-    for (int k = 0; k < kMaxBins / 1024; ++k) {   // this thread's bin totals, before v is reused
-        const int b = t + 1024 * k;
-        tot[k] = b < a.n_bins ? a.bin_start[b + 1] : 0u;
-    }
-    __syncthreads();
-    for (int b = t; b <= a.n_bins; b += 1024) a.bin_start[b] = b > 0 ? v[b - 1] : 0u;
-    __syncthreads();
-    // workgroups per bin: ceil(total / kAccumRecords), at least one; exclusive scan
-#pragma unroll
-    for (int k = 0; k < kMaxBins / 1024; ++k) {
-        const int b = t + 1024 * k;
-        v[b] = b < a.n_bins ? (tot[k] > kAccumRecords ? (tot[k] + kAccumRecords - 1) / kAccumRecords : 1u)
-                            : 0u;
-    }
-    __syncthreads();
-    for (int off = 1; off < kMaxBins; off <<= 1) {
-        uint32_t add[kMaxBins / 1024];
-#pragma unroll
-        for (int k = 0; k < kMaxBins / 1024; ++k) {
-            const int b = t + 1024 * k;
-            add[k] = b >= off ? v[b - off] : 0u;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kMaxBins / 1024; ++k) v[t + 1024 * k] += add[k];
-        __syncthreads();
-    }
-    for (int b = t; b <= a.n_bins; b += 1024) a.work_start[b] = b > 0 ? v[b - 1] : 0u;
-    // the bins split over several workgroups, in bin order (k_grid_merge)
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kMaxBins / 1024; ++k) {
-        const int b = t + 1024 * k;
-        v[b] = (b < a.n_bins && tot[k] > kAccumRecords) ? 1u : 0u;
-    }
-    __syncthreads();
-    for (int off = 1; off < kMaxBins; off <<= 1) {
-        uint32_t add[kMaxBins / 1024];
-#pragma unroll
-        for (int k = 0; k < kMaxBins / 1024; ++k) {
-            const int b = t + 1024 * k;
-            add[k] = b >= off ? v[b - off] : 0u;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kMaxBins / 1024; ++k) v[t + 1024 * k] += add[k];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < kMaxBins / 1024; ++k) {
-        const int b = t + 1024 * k;
-        if (b < a.n_bins && tot[k] > kAccumRecords) a.split[v[b] - 1] = (uint32_t)b;
-    }
-    if (t == 0) a.split[a.n_bins] = v[kMaxBins - 1];
-    // records of the fullest bin: they bound the fixed-point sums
+    static_assert(kMaxBins == 2 * 1024, "two bins per thread");
+    __shared__ uint32_t ws[3][16];
     __shared__ uint32_t smax;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int b0 = 2 * t, b1 = 2 * t + 1;
+    const uint32_t tot0 = b0 < a.n_bins ? a.bin_start[b0 + 1] : 0u;
+    const uint32_t tot1 = b1 < a.n_bins ? a.bin_start[b1 + 1] : 0u;
+    auto groups = [&](int b, uint32_t tot) {
+        return b < a.n_bins ? (tot > kAccumRecords ? (tot + kAccumRecords - 1) / kAccumRecords : 1u) : 0u;
+    };
+    auto split = [&](int b, uint32_t tot) { return (b < a.n_bins && tot > kAccumRecords) ? 1u : 0u; };
+    const uint32_t v[3] = {tot0 + tot1, groups(b0, tot0) + groups(b1, tot1), split(b0, tot0) + split(b1, tot1)};
+    uint32_t incl[3], excl[3];
     if (t == 0) smax = 0u;
-    __syncthreads();
-    uint32_t mx = 0u;
 #pragma unroll
-    for (int k = 0; k < kMaxBins / 1024; ++k) mx = tot[k] > mx ? tot[k] : mx;
-    atomicMax(&smax, mx);
+    for (int k = 0; k < 3; ++k) {
+        incl[k] = wave_scan_incl(v[k], lane);
+        if (lane == 63) ws[k][wv] = incl[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        uint32_t before = 0u;
+        for (int u = 0; u < wv; ++u) before += ws[k][u];
+        excl[k] = before + incl[k] - v[k];   // before this thread's first bin
+    }
+    // bin starts (bin_start[b + 1] held the totals: every thread has read its own)
+    __syncthreads();
+    if (b0 <= a.n_bins) a.bin_start[b0] = excl[0];
+    if (b1 <= a.n_bins) a.bin_start[b1] = excl[0] + tot0;
+    if (b0 <= a.n_bins) a.work_start[b0] = excl[1];
+    if (b1 <= a.n_bins) a.work_start[b1] = excl[1] + groups(b0, tot0);
+    // the bins split over several workgroups, in bin order (k_grid_merge)
+    if (split(b0, tot0)) a.split[excl[2]] = (uint32_t)b0;
+    if (split(b1, tot1)) a.split[excl[2] + split(b0, tot0)] = (uint32_t)b1;
+    if (t == 1023) a.split[a.n_bins] = excl[2] + v[2];
+    // records of the fullest bin: they bound the fixed-point sums
+    atomicMax(&smax, tot0 > tot1 ? tot0 : tot1);
     __syncthreads();
     if (t == 0) a.vmax[1] = smax;
 }
@@ -1217,14 +1201,9 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
         blocks = blocks < 1 ? 1 : blocks;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, stream, ba);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // weight gradient: the workgroups' rows summed in two passes
-        const unsigned cols = (unsigned)((B::NMLP + 255) / 256);
-        const int rows = (int)blocks;   // one per workgroup
-        const int fold = rows < 32 ? rows : 32;   // the first pass writes rows 0 .. fold-1
-        hipLaunchKernelGGL(k_dw_sum, dim3(cols, (unsigned)fold), dim3(256), 0, stream, ba.dw_part,
-                           (int64_t)B::NMLP, rows, (float *)nullptr, 1.0f);
-        hipLaunchKernelGGL(k_dw_sum, dim3(cols, 1u), dim3(256), 0, stream, ba.dw_part, (int64_t)B::NMLP,
-                           fold, st.grads + m.n_grid_values, ba.loss_scale);
+        // weight gradient: the workgroups' rows summed, one row per workgroup
+        hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((B::NMLP + 15) / 16)), dim3(256), 0, stream, ba.dw_part,
+                           (int64_t)B::NMLP, (int)blocks, st.grads + m.n_grid_values, ba.loss_scale);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 3. grid scatter through bins
