@@ -535,11 +535,8 @@ void k_query(const QueryArgs a)
             continue;
         }
         }  // staged encoding
-        // LDS accesses of one wave complete in order; the fence keeps the
-        // compiler from moving the operand reads above the row writes.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the operand reads below must not move above the row writes
+        wave_lds_fence();
 
         // ---- 2/3. MLP on the matrix cores, TB tiles of 16 pixels at a time
         f4 acc_o[4];  // output layer per tile: RGB of pixel 16t + j in lane j

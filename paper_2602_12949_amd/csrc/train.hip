@@ -196,9 +196,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) debuf[c * 64 + lane] = dEl[c];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_fence();
         const uint8_t *xs = a.x_save + chunk * B::CHUNK_BYTES;
         const uint8_t *bw = a.bwd;
 
@@ -306,9 +304,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
                         gb[(16 * ob + 4 * g + 3) * 64 + 16 * t + j] = (_Float16)G[t][ob].w;
                     }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_lds_fence();
             // dW_k += G X_k^T over the chunk's 64 samples; the X_k operands do
             // not depend on the output block and are loaded together first
             constexpr int DK_MAX = S::DIN > S::W ? S::DIN : S::W;
@@ -422,9 +418,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(const BwdArgs a)
                     float *d = dx + (16 * t + j) * B::NFP + 16 * ib + 4 * g;
                     d[0] = G[t][ib].x; d[1] = G[t][ib].y; d[2] = G[t][ib].z; d[3] = G[t][ib].w;
                 }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_lds_fence();
             // a sample scatters when its dE is finite and not zero (a non-finite
             // dE marks the step non-finite in the forward and never reaches the grid)
             bool scatter = live && (dEl[0] != 0.f || dEl[1] != 0.f || dEl[2] != 0.f) &&
@@ -576,13 +570,6 @@ constexpr int kScatterWaves = 16;
 constexpr int kScatterThreads = 64 * kScatterWaves;
 constexpr int kScatterMaxLevels = 16;          // levels of the trainable shapes
 
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ inline bool scatter_sample(const ScatterArgs &a, int64_t q, double p[3])
 {
     if (q >= a.n || !a.sflag[q]) return false;
@@ -689,14 +676,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
             const uint32_t nlb = ((off + size - 1u) >> kBinShift) - fb + 1u;
             for (uint32_t w0 = 0; w0 < nlb; w0 += 64) {
                 hist[lane] = 0u;
-                wave_lds_sync();
+                wave_lds_fence();
                 uint32_t rb[8], slot[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     rb[c] = (idx[c] >> kBinShift) - fb - w0;      // >= 64 (wrapped) outside the window
                     slot[c] = (live && rb[c] < 64u) ? atomicAdd(&hist[rb[c]], 1u) : ~0u;
                 }
-                wave_lds_sync();
+                wave_lds_fence();
                 const uint32_t nb = hist[lane];
                 const uint32_t base = nb ? atomicAdd(&cnt[fb + w0 + lane], nb) : 0u;
                 uint32_t incl = nb;   // inclusive scan over the lanes
@@ -708,7 +695,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
                 const uint32_t total = __shfl(incl, 63);
                 bbase[lane] = base;
                 lstart[lane] = incl - nb;
-                wave_lds_sync();
+                wave_lds_fence();
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     if (slot[c] == ~0u) continue;
@@ -719,14 +706,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
                     else
                         stage[lstart[rb[c]] + slot[c]] = (u4){bbase[rb[c]] + slot[c], idx[c], f2u(v0), f2u(v1)};
                 }
-                wave_lds_sync();
+                wave_lds_fence();
                 for (uint32_t k = lane; k < total; k += 64) {
                     const u4 e = stage[k];
                     a.keys[e.x] = (uint16_t)(e.y & (kBinEntries - 1));
                     if constexpr (H16) a.vals16[e.x] = e.z;
                     else a.vals[e.x] = make_float2(u2f(e.z), u2f(e.w));
                 }
-                wave_lds_sync();   // hist and stage are reused
+                wave_lds_fence();   // hist and stage are reused
             }
         }
     }
