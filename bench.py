@@ -192,7 +192,12 @@ def bench_1080p(args, dev, precs):
     for prec in precs:
         prepared = m.prepare(d["params"], prec)
         frame, outs = m.frame(d["pos"], d["nrm"], prepared, albedo=d["alb"], mask=d["mask"])
-        tune = m.autotune([frame], prec)
+        if args.tune:
+            b_, c_, x_ = (int(v) for v in args.tune.split(","))
+            m.set_tune(prec, b_, c_, x_)
+            tune = {"block": b_, "blocks_per_cu": c_, "xcd_order": x_, "candidates": "fixed (--tune)"}
+        else:
+            tune = m.autotune([frame], prec)
         log(f"[bench] room_1080p {prec} autotune: block {tune['block']} x {tune['blocks_per_cu']}"
             f" per CU, xcd order {tune['xcd_order']}: {tune['candidates']}")
         total, per = time_steps(lambda: m.query_frames([frame], prec), args.steps, args.warmup)
@@ -818,7 +823,8 @@ def main():
                     help="steps of the stated room_train bake (2^18 points x 256 spp each)")
     ap.add_argument("--profile", default=None, help="run one kernel case for rocprofv3")
     ap.add_argument("--tune", default=None,
-                    help="launch shape for --profile: block,blocks_per_cu,xcd_order")
+                    help="launch shape block,blocks_per_cu,xcd_order: for --profile, and for the "
+                         "headline query instead of the autotuner (trace runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
