@@ -726,9 +726,10 @@ def profile_case(case, steps, tune=None):
         from paper_2602_12949_amd.niv import probe_gather
         table = torch.ones(1 << 21, dtype=torch.int32, device=dev)
         sink = torch.empty(2048 * 256, dtype=torch.int32, device=dev)
-        for mode in range(4):
-            total, _ = time_steps(lambda: probe_gather(mode, 1 << 18, table, sink), steps, steps)
-            log(f"[profile] gather mode {mode}: HIP events {total * 1e3:.1f} us per pass")
+        for mode in range(4):   # 2^21 x 128 gathers per pass, reported per 2^18 x 128
+            total, _ = time_steps(lambda: probe_gather(mode, 1 << 21, table, sink), steps, steps)
+            log(f"[profile] gather mode {mode}: HIP events {total * 1e3:.1f} us per pass, "
+                f"{total * 1e3 / 8:.1f} us per 2^18 x 128 gathers")
         return
     if case in ("train_step", "mc"):
         from niv_synth import get_workload, make_params, make_room

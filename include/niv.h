@@ -53,10 +53,13 @@ typedef enum { NIV_FP32 = 0, NIV_FP16 = 1, NIV_BF16 = 2 } niv_precision;
  * each scene variable the 2*extra_bands values sin(2^k pi t), cos(2^k pi t)
  * (Sec. 6).  Hidden layers are width wide with ReLU, no biases; the output
  * layer is linear.
- * Supported by the kernels: n_features = 2, sh_bands = 4, n_out = 3, and
- * either a grid (n_levels 8 or 16, pos_bands 0: width 64 with 2 or 3 hidden
- * layers, or width 128 with 4 hidden layers and one scene variable) or no
- * grid (n_levels 0, pos_bands 8, width 16, 32 or 64, 3 hidden layers). */
+ * Supported by the kernels: sh_bands = 4, n_out = 3, and either a grid of
+ * two features per entry (n_levels 8 or 16, pos_bands 0: width 64 with 2 or
+ * 3 hidden layers, or width 128 with 4 hidden layers and one scene
+ * variable), a grid of four features per entry (Table 1's grid networks:
+ * n_levels 2, 4, 6 or 8, width 64, 3 hidden layers, no scene variable;
+ * queries only, training gives NIV_ERR_UNSUPPORTED) or no grid (n_levels 0,
+ * pos_bands 8, width 16, 32 or 64, 3 hidden layers). */
 typedef struct {
     int32_t n_levels, log2_T, n_features;
     double  base_res, per_level_scale;

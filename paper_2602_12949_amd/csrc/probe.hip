@@ -37,11 +37,16 @@ __global__ __launch_bounds__(256) void k_probe_gather(const uint32_t *__restrict
             }
     } else {
         const uint32_t o = MODE == 1 ? lane : (MODE == 2 ? (lane >> 2) * 32u + (lane & 3u) : lane * 32u);
-        for (int s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256)
+        for (int s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256) {
+            // a wave-uniform shift per 64 samples, a multiple of the 128-byte
+            // line, so that every pass loads anew (loop-invariant addresses
+            // would be loaded once) with the same lines-per-instruction pattern
+            const uint32_t w = ((uint32_t)s >> 6) * 1056u;
             for (int k = 0; k < kLevels * 8; k += 8) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc += tab[(o + (uint32_t)(k + c) * 64u) & 4095u];
+                for (int c = 0; c < 8; ++c) acc += tab[(o + (uint32_t)(k + c) * 64u + w) & 4095u];
             }
+        }
     }
     out[blockIdx.x * 256 + threadIdx.x] = acc;
 }

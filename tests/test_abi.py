@@ -164,3 +164,26 @@ def test_lr_schedule_matches_oracle(niv):
                 (1, 10, 100, 1e-2, float("nan"))):
         with pytest.raises(niv.NivError):
             niv.lr_schedule(*bad)
+
+
+def test_four_feature_configs(niv):
+    """Grids of four features per entry are accepted for Table 1's level
+    counts (queries at every precision); other level counts are valid but not
+    covered by the kernels; training them reports NIV_ERR_UNSUPPORTED."""
+    import ctypes as C
+    base = dict(get_workload("room_1080p_g8").model_dict())
+    for levels in (2, 4, 6, 8):
+        d = dict(base, n_levels=levels)
+        m = niv.NIV(d)
+        oc = O.make_config(**d)
+        assert m.n_params == O.n_params(oc) and m.input_dim == O.input_dim(oc) == 4 * levels + 16
+        for prec in ("fp32", "fp16", "bf16"):
+            n_p, n_g, nb = m.sizes(prec)
+            assert n_g == O.n_grid_values(oc) and nb >= n_g * (4 if prec == "fp32" else 2)
+        nbytes = C.c_int64(0)
+        st = niv.lib().niv_train_sizes(m._h, 1, 1 << 10, C.byref(nbytes))
+        assert st == niv.NIV_ERR_UNSUPPORTED
+    m = niv.NIV(dict(base, n_levels=3))
+    with pytest.raises(niv.NivError) as e:
+        m.sizes("fp16")
+    assert e.value.status == niv.NIV_ERR_UNSUPPORTED
