@@ -53,12 +53,12 @@ def assert_flags(fl, fl_ref, E_ref, near):
 
 def sign_margin(prec, E_ref, scale):
     """How close to zero an output may be for its sign to be undecided:
-    1e-5 of the term scale for FP32; for FP16/BF16 2e-2 of the larger of the
-    term scale and the image's RMS output."""
+    1e-5 of the term scale for FP32, 1e-3 of it for FP16/BF16 (the 16-bit
+    queries stay within ~6e-6 of the term scale on the room frame, so this
+    leaves two orders of magnitude for other models and frames)."""
     if prec == "fp32":
         return 1e-5 * np.maximum(np.abs(E_ref), scale)
-    rms = np.sqrt(np.mean(E_ref ** 2))
-    return 2e-2 * np.maximum(scale, rms)
+    return 1e-3 * np.maximum(np.abs(E_ref), scale)
 
 
 def relu_margin(mats, x0):
