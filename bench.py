@@ -11,8 +11,9 @@ with its error against the FP64 oracle.
 Also measured, as extra fields of the same JSON line:
   train       room_train: niv_train_step at B = 2^18 (FP16), the Monte Carlo
               targets (256 spp, 3 bounces, NEE) and the sampler, and the whole
-              baking step (samples/s); then a model baked on the GPU judged
-              against 4096-spp Monte Carlo on 2^16 held-out points;
+              baking step (samples/s); the FP16 gradient of that batch against
+              the FP64 oracle per parameter block; then a model baked on the
+              GPU judged against 4096-spp Monte Carlo on 2^16 held-out points;
   batched     batched_8_rooms: eight uneven G-buffers (16.3 M pixels), eight
               models, one persistent launch replayed from a HIP graph, after
               the autotuner; with and without the Monte Carlo fallback (64 spp);
@@ -303,6 +304,38 @@ def cpu_baseline_1080p(w, g, params):
             "runs_s": runs}
 
 
+def gradient_check(w, m, params, x, n, E, valid, dev):
+    """The FP16 gradient of one full batch (2^18 samples: coarse grid bins
+    split over several accumulating workgroups) against the FP64 oracle on
+    the FP16-rounded parameters, per parameter block."""
+    import torch
+    import oracle as O
+    from paper_2602_12949_amd import Trainer
+    tr = Trainer(m, torch.from_numpy(params).to(dev), "fp16", max_batch=len(x))
+    loss = float(tr.backward(x, n, E, valid=valid).item())
+    g = tr.grads.cpu().numpy().astype(np.float64)
+    oc = O.config_from_workload(w)
+    p16 = params.astype(np.float16).astype(np.float64)
+    t0 = time.perf_counter()
+    l_ref, g_ref = O.loss_grad(oc, p16, x.cpu().numpy(), n.cpu().numpy(), E.cpu().numpy(),
+                               valid=valid.cpu().numpy())
+    cs = time.perf_counter() - t0
+    out = {"batch": len(x), "precision": "fp16", "loss_rel_err": abs(loss - l_ref) / abs(l_ref),
+           "oracle_s": cs, "blocks": {}}
+    k = 0
+    names = ["grid"] + [f"W{i}" for i in range(len(O.mat_shapes(oc)))]
+    sizes = [O.n_grid_values(oc)] + [o * i for o, i in O.mat_shapes(oc)]
+    for name, sz in zip(names, sizes):
+        a, b = g[k:k + sz], g_ref[k:k + sz]
+        k += sz
+        out["blocks"][name] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                               "max_over_max": float(np.abs(a - b).max() / np.abs(b).max())}
+    log("[bench] FP16 gradient at 2^18 vs oracle: " +
+        ", ".join(f"{k}: rel-L2 {v['rel_l2']:.2e}" for k, v in out["blocks"].items()) +
+        f" (loss rel err {out['loss_rel_err']:.1e})")
+    return out
+
+
 def bench_train(args, dev):
     import torch
     from niv_synth import get_workload, make_params, make_room
@@ -376,6 +409,7 @@ def bench_train(args, dev):
                                 "sample": "512 points x 4096 spp, 3 bounces, NEE, FP64 on the "
                                           "host threads (points/s scaled to 256 spp)"}
         log(f"[bench] MC oracle: 512 x 4096 spp in {cs:.2f} s")
+        res["gradient_vs_oracle"] = gradient_check(w, m, params, x, n, E, valid, dev)
     log(f"[bench] train: step {tt:.3f} ms ({B / (tt * 1e-3) / 1e6:.2f} M samples/s), "
         f"MC {mt:.1f} ms ({B / (mt * 1e-3) / 1e6:.3f} M points/s), bake step {et:.1f} ms")
     return res
