@@ -93,7 +93,7 @@ typedef const __attribute__((address_space(4))) Motion4 *ConstMotion;
 // the rectangles grouped by axis, then the disks, each list in primitive
 // order and each record 32 bytes with the primitive's index, so that the
 // closest-hit loop runs one kind at a time without a branch on the kind.
-struct TraceRec {
+struct __attribute__((aligned(32))) TraceRec {
     float a[3];      // box: min corner; rectangle: centre (plane coordinate on its axis)
     int32_t idx;     // primitive index
     float b[3];      // box: max corner; rectangle: half extents u, v, then the facing sign
@@ -165,19 +165,32 @@ __device__ inline void prim_hit(ConstPrims prims, int k, const Ray &r, float &be
 __device__ inline void trace_list(const SceneRefs &sc, const Ray &r, float &best, int &bp, bool &bback)
 {
     ConstRecs rb = sc.recs;
-#pragma unroll 2
+    // one 32-byte record per box, the next one loaded while this one is
+    // tested (the list ends with a padding record, so rb[k + 1] is in bounds)
+    auto load = [&](int k) {
+        TraceRec q;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { q.a[c] = rb[k].a[c]; q.b[c] = rb[k].b[c]; }
+        q.idx = rb[k].idx;
+        q.pad = 0;
+        return q;
+    };
+    TraceRec cur = load(0);
     for (int k = 0; k < sc.nb; ++k) {
-        const float x1 = slab(rb[k].a[0], r, 0), x2 = slab(rb[k].b[0], r, 0);
-        const float y1 = slab(rb[k].a[1], r, 1), y2 = slab(rb[k].b[1], r, 1);
-        const float z1 = slab(rb[k].a[2], r, 2), z2 = slab(rb[k].b[2], r, 2);
+        const TraceRec nxt = load(k + 1);
+        const float x1 = slab(cur.a[0], r, 0), x2 = slab(cur.b[0], r, 0);
+        const float y1 = slab(cur.a[1], r, 1), y2 = slab(cur.b[1], r, 1);
+        const float z1 = slab(cur.a[2], r, 2), z2 = slab(cur.b[2], r, 2);
         const float tn = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fminf(z1, z2));
         const float tf = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fmaxf(z1, z2));
         const bool front = tn > 0.0f;
         const float t = front ? tn : tf;      // from inside: the exit face, seen from behind
-        const bool take = (tn <= tf) && (t > 0.0f) && (t < best);
+        // t > 0 is tf > 0 here: with tn > 0, tn <= tf makes tf positive
+        const bool take = (tn <= tf) && (tf > 0.0f) && (t < best);
         best = take ? t : best;
-        bp = take ? rb[k].idx : bp;
+        bp = take ? cur.idx : bp;
         bback = take ? !front : bback;
+        cur = nxt;
     }
     rb += sc.nb;
     auto rects = [&](auto axis, int n) {
@@ -693,6 +706,9 @@ niv_status upload_trace_list(mc_scene *s)
         s->nk[l] = (int32_t)lists[l].size();
         all.insert(all.end(), lists[l].begin(), lists[l].end());
     }
+    TraceRec pad;   // read ahead by the box loop, never tested
+    memset(&pad, 0, sizeof(pad));
+    all.push_back(pad);
     niv_status st = hs(hipMalloc(&s->d_recs, sizeof(TraceRec) * all.size()));
     if (st == NIV_OK)
         st = hs(hipMemcpy(s->d_recs, all.data(), sizeof(TraceRec) * all.size(), hipMemcpyHostToDevice));
