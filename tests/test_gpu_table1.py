@@ -146,3 +146,31 @@ def test_grid_ragged_counts(room_gbuffer, n):
     _check("fp32", E, E_ref, sc)
     assert_flags(fl.cpu().numpy(), fl_ref, E_ref, sign_margin("fp32", E_ref, sc))
 
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_grid_edge_inputs(room_gbuffer, prec):
+    """Masked pixels, non-finite inputs, zero normals and points outside the
+    box under the 8-level four-feature network."""
+    g = room_gbuffer
+    w, oc, m, params = _model(8)
+    pos = g["pos"][:300].copy()
+    nrm = g["nrm"][:300].copy()
+    mask = np.ones(300, np.uint8)
+    pos[0] = [np.nan, 1.0, 1.0]
+    nrm[1] = [0.0, 0.0, 0.0]
+    pos[2] = [11.0, -1.0, 4.0]
+    nrm[3] = [np.inf, 0.0, 0.0]
+    mask[5:9] = 0
+    prepared = m.prepare(_t(params), prec)
+    E, _, fl = m.query(_t(pos), _t(nrm), prepared, prec, mask=_t(mask))
+    torch.cuda.synchronize()
+    E, fl = E.cpu().numpy().astype(np.float64), fl.cpu().numpy()
+    pr = _round(params, prec)
+    E_ref, _, fl_ref, x0 = O.query(oc, pr, pos, nrm, mask=mask, want_x0=True)
+    sc = term_scale(O.split_params(oc, pr)[1:], x0)
+    assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
+    assert fl[0] & 2 and fl[1] & 2 and fl[3] & 2 and fl[2] & 1
+    assert (E[[0, 1, 3]] == 0).all() and (E[5:9] == 0).all()
+    ok = mask.astype(bool) & ((fl_ref & 2) == 0)
+    _check(prec, E[ok], E_ref[ok], sc[ok])
