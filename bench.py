@@ -566,7 +566,7 @@ def bench_field_4k(args, dev):
     f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"], extra=(0.37,))
     tune = m.autotune([f], "bf16")
     log(f"[bench] room_4k_6d autotune: block {tune['block']} x {tune['blocks_per_cu']} per CU, "
-        f"xcd order {tune['xcd_order']}")
+        f"xcd order {tune['xcd_order']}: {tune['candidates']}")
     for tv in w.extra_values:
         f, outs = m.frame(d["pos"], d["nrm"], pm, albedo=d["alb"], mask=d["mask"], extra=(tv,))
         graph = m.capture([f], "bf16")

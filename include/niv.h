@@ -268,15 +268,17 @@ niv_status niv_query_half(niv_handle *h, const niv_half_frame *f, const niv_upsa
                           niv_precision prec, hipStream_t stream);
 
 /* Times the fused query on these frames for each candidate launch shape
- * (workgroup of 256 or 512 threads x 1, 2 or all-resident workgroups per
- * CU x tile order: plain, or XCD-grouped, where each of the 8 XCDs walks a
- * contiguous eighth of the tiles so that neighbouring pixels share an L2;
- * best of 10 launches) and keeps the fastest for later calls at this
- * precision.  Synchronises `stream`; the frames' outputs are overwritten. */
+ * (workgroup of 256 or 512 threads, and 768 for the lane-sliced 6-D field at
+ * FP16/BF16, x 1, 2 or all-resident workgroups per CU x tile order: plain,
+ * or XCD-grouped, where each of the 8 XCDs walks a contiguous eighth of the
+ * tiles so that neighbouring pixels share an L2; best of 10 launches) and
+ * keeps the fastest for later calls at this precision.  Synchronises
+ * `stream`; the frames' outputs are overwritten.  out (optional, host): the
+ * n <= 24 candidates and their times, and the chosen shape. */
 typedef struct {
     int32_t n;
-    int32_t block[16], blocks_per_cu[16], xcd_order[16];
-    float ms[16];
+    int32_t block[24], blocks_per_cu[24], xcd_order[24];
+    float ms[24];
     int32_t chosen_block, chosen_blocks_per_cu, chosen_xcd_order;
     float chosen_ms;
 } niv_tune_result;
@@ -284,9 +286,11 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
                         niv_precision prec, hipStream_t stream, niv_tune_result *out);
 
 /* Sets the launch shape of later queries at `prec` directly (for instance a
- * shape niv_autotune chose in an earlier process): block 256 or 512 threads,
- * blocks_per_cu 0 (all resident) or more, xcd_order 0 or 1.  Out-of-range
- * values give NIV_ERR_INVALID_ARG and change nothing. */
+ * shape niv_autotune chose in an earlier process): block 256, 512 or 768
+ * threads (768 takes effect for the lane-sliced 6-D field at FP16/BF16 and
+ * runs as 512 elsewhere), blocks_per_cu 0 (all resident) or more,
+ * xcd_order 0 or 1.  Out-of-range values give NIV_ERR_INVALID_ARG and
+ * change nothing. */
 niv_status niv_set_tune(niv_handle *h, niv_precision prec, int32_t block, int32_t blocks_per_cu,
                         int32_t xcd_order);
 

@@ -489,7 +489,8 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
     niv_status s = check_frames(h, frames, n_frames, prec);
     if (s != NIV_OK) return s;
     if (n_frames < 1 || n_frames > kMaxFrames) return NIV_ERR_INVALID_ARG;
-    static const int blocks[2] = {256, 512};
+    static const int blocks[3] = {256, 512, 768};   // 768: lane-sliced shapes only
+    const bool sliced = h->m.kind == kWide6D && prec != NIV_FP32;
     static const int per_cu[3] = {0, 1, 2};
     static const int orders[2] = {0, 1};
     hipEvent_t e0, e1;
@@ -499,7 +500,7 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
     float best_ms = 1e30f;
     int k = 0;
     niv_status st = NIV_OK;
-    for (int b = 0; b < 2 && st == NIV_OK; ++b)
+    for (int b = 0; b < (sliced ? 3 : 2) && st == NIV_OK; ++b)
         for (int c = 0; c < 3 && st == NIV_OK; ++c)
         for (int o = 0; o < 2 && st == NIV_OK; ++o, ++k) {
             LaunchTune tu = {blocks[b], per_cu[c], orders[o]};
@@ -518,7 +519,7 @@ niv_status niv_autotune(niv_handle *h, const niv_frame *frames, int32_t n_frames
                 if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = NIV_ERR_HIP; break; }
                 if (rep >= 2 && t < ms) ms = t;  // best of 10 after 2 warm-up launches
             }
-            if (out && k < 16) {
+            if (out && k < 24) {
                 out->block[k] = tu.block;
                 out->blocks_per_cu[k] = tu.blocks_per_cu;
                 out->xcd_order[k] = tu.xcd_order;
@@ -545,7 +546,7 @@ niv_status niv_set_tune(niv_handle *h, niv_precision prec, int32_t block, int32_
                         int32_t xcd_order)
 {
     if (!h || (prec != NIV_FP32 && prec != NIV_FP16 && prec != NIV_BF16)) return NIV_ERR_INVALID_ARG;
-    if ((block != 256 && block != 512) || blocks_per_cu < 0 || blocks_per_cu > 64 ||
+    if ((block != 256 && block != 512 && block != 768) || blocks_per_cu < 0 || blocks_per_cu > 64 ||
         (xcd_order != 0 && xcd_order != 1))
         return NIV_ERR_INVALID_ARG;
     h->m.tune[prec] = LaunchTune{block, blocks_per_cu, xcd_order};

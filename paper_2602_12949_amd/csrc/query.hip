@@ -209,6 +209,11 @@ static hipError_t query_t(QueryArgs &a, int blocks_per_cu, hipStream_t st)
 template <int P, class S, bool WLDS, int TB>
 static hipError_t query_b(QueryArgs &a, const LaunchTune &tu, hipStream_t st)
 {
+    // lane-sliced shapes keep no per-wave rows in LDS: a 768-thread
+    // workgroup (three waves per SIMD) fits beside their weights
+    if constexpr (S::SL) {
+        if (tu.block == 768) return query_t<P, S, WLDS, TB, 768>(a, tu.blocks_per_cu, st);
+    }
     // shapes whose 512-thread workgroup would not fit in LDS run 256 threads
     if constexpr (query_lds<P, S, WLDS, 512>() > kLdsPerCu) {
         return query_t<P, S, WLDS, TB, 256>(a, tu.blocks_per_cu, st);
@@ -242,8 +247,9 @@ hipError_t launch_query_probe(const Model &m, QueryArgs &a, niv_precision prec, 
 LaunchTune default_tune(int kind, niv_precision prec)
 {
     LaunchTune t;
-    // FP32 operands need twice the LDS per wave; smaller workgroups fit more of them
-    t.block = (prec == NIV_FP32 && kind != kWide6D) ? 256 : 512;
+    // FP32 operands need twice the LDS per wave; smaller workgroups fit more
+    // of them; the lane-sliced 6-D field runs three waves per SIMD
+    t.block = (prec == NIV_FP32 && kind != kWide6D) ? 256 : (kind == kWide6D && prec != NIV_FP32) ? 768 : 512;
     t.blocks_per_cu = 0;
     t.xcd_order = 1;
     return t;

@@ -65,8 +65,8 @@ class Fallback(C.Structure):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("n", C.c_int32), ("block", C.c_int32 * 16), ("blocks_per_cu", C.c_int32 * 16),
-                ("xcd_order", C.c_int32 * 16), ("ms", C.c_float * 16), ("chosen_block", C.c_int32),
+    _fields_ = [("n", C.c_int32), ("block", C.c_int32 * 24), ("blocks_per_cu", C.c_int32 * 24),
+                ("xcd_order", C.c_int32 * 24), ("ms", C.c_float * 24), ("chosen_block", C.c_int32),
                 ("chosen_blocks_per_cu", C.c_int32), ("chosen_xcd_order", C.c_int32),
                 ("chosen_ms", C.c_float)]
 

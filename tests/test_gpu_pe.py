@@ -174,3 +174,31 @@ def test_wide_6d_fp32_fp16(prec):
     sc = term_scale(O.split_params(oc, pr)[1:], x0)
     _check(prec, E, E_ref, sc)
     assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("block", [256, 768])
+def test_wide_6d_launch_shapes(prec, block):
+    """The lane-sliced width-128 6-D field at the launch shapes besides the
+    default 512 threads (768: three waves per SIMD), room points, one scene
+    variable, against the oracle at the 16-bit bar."""
+    from paper_2602_12949_amd import NIV
+    w = get_workload("room_4k_6d")
+    oc = O.config_from_workload(w)
+    params = make_params(O.n_grid_values(oc), O.mat_shapes(oc), w.param_seed, *w.grid_init)
+    m = NIV(w.model_dict())
+    m.set_tune(prec, block, 0, 1)
+    rng = np.random.default_rng(33)
+    n = 100000 + 37
+    pos = (rng.random((n, 3)) * [10.0, 4.0, 10.0]).astype(np.float32)
+    nrm = rng.normal(size=(n, 3)).astype(np.float32)
+    prepared = m.prepare(_t(params), prec)
+    E, _, fl = m.query(_t(pos), _t(nrm), prepared, prec, extra=(0.6,))
+    torch.cuda.synchronize()
+    E, fl = E.cpu().numpy().astype(np.float64), fl.cpu().numpy()
+    pr = _round(params, prec)
+    E_ref, _, fl_ref, x0 = O.query(oc, pr, pos, nrm, extra=np.full((n, 1), 0.6, np.float32),
+                                   want_x0=True)
+    sc = term_scale(O.split_params(oc, pr)[1:], x0)
+    _check(prec, E, E_ref, sc)
+    assert_flags(fl, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
