@@ -12,9 +12,10 @@
 //      MFMA (the gradient is transposed through LDS), the input gradients
 //      W_k^T G_{k+1} on MFMA with pre-permuted transposed weights so that
 //      they come out in the same lane layout as the forward activations;
-//      weight gradients accumulate in LDS per workgroup, each workgroup
-//      writes its sum to a row of its own, and k_dw_sum adds the rows; the
-//      gradient of each sample's grid features is written out;
+//      each wave keeps its weight gradient in the matrix-core accumulators
+//      over its chunks, a workgroup's four waves add theirs in LDS and
+//      write one row, and k_dw_sum adds the rows; the gradient of each
+//      sample's grid features is written out level-major per chunk;
 //   3. the scatter of those feature gradients to the 8 corners of every
 //      level, without global atomics (device-scope atomics execute at the
 //      memory side of this part, ~22 G/s): the contributions are counted
@@ -25,7 +26,8 @@
 //      point (k_grid_accum); a bin split over several workgroups has its
 //      integer partial sums added in a fixed order (k_grid_merge), so the
 //      whole grid gradient is independent of scheduling;
-//   4. k_adam over all parameters, then the prepared model is rebuilt.
+//   4. k_adam over all parameters (it also writes the prepared model's
+//      grid), then the prepared weight operands are rebuilt.
 // Gradients are carried unscaled through the network and multiplied by
 // 1/(3n) when they are added to the gradient buffer, so FP16 operands do not
 // underflow.
