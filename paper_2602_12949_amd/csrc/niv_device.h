@@ -122,10 +122,11 @@ template <> struct Prec<NIV_FP32> {
 // per 16-pixel tile), so no per-wave staging block in LDS is needed and the
 // whole LDS can hold the weights.
 // PB_: bands of the positional code of x (grid-free models, L_ = 0).
+// F_: features per grid entry (2, or 4 for Table 1's grid networks).
 //
 // Layer-0 columns.  The parameters of W_0 follow the input vector of the
-// model: [grid 2L][u 3, bands 6 PB][SH 16][scene variables 16 NEX].  The
-// kernels order the columns as [grid 2L][bands 6 PB][u 3][0][SH 16][scene
+// model: [grid F L][u 3, bands 6 PB][SH 16][scene variables 16 NEX].  The
+// kernels order the columns as [grid F L][bands 6 PB][u 3][0][SH 16][scene
 // variables][0 ...] so that 16-bit pairs never straddle two parts, padded
 // with zero columns to a multiple of 16; in_col maps a kernel column to its
 // parameter column (or -1 for a zero column).
