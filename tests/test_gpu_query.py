@@ -215,3 +215,42 @@ def test_room_1080p_full_frame_parity(room, prec):
     else:
         print(f"  max rel err {err:.3e} (floored at 1e-3 max: {max_rel_floored(E[ok], E_ref[ok]):.3e})",
               flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_largest_frame(prec):
+    """The largest frame one call takes, 2^28 - 1 points of the room model
+    (uniform positions in the box and beyond it, random normals, generated on
+    the GPU): sampled pixels, among them the first and last tiles, against
+    the oracle; 2^28 points are rejected before any launch."""
+    import torch
+    from paper_2602_12949_amd import niv as N
+    w = get_workload("room_1080p")
+    oc = O.config_from_workload(w)
+    params = make_params(O.n_grid_values(oc), O.mat_shapes(oc), w.param_seed, *w.grid_init)
+    m = _niv()(w.model_dict())
+    n = (1 << 28) - 1
+    print(f"room_1080p {prec}: {n} points", flush=True)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(28)
+    lo = torch.tensor([-0.5, -0.5, -0.5], device=DEV)
+    ext = torch.tensor([11.0, 5.0, 11.0], device=DEV)
+    pos = torch.rand((n, 3), generator=gen, device=DEV).mul_(ext).add_(lo)
+    nrm = torch.randn((n, 3), generator=gen, device=DEV)
+    prepared = m.prepare(torch.from_numpy(params).to(DEV), prec)
+    E, _, fl = m.query(pos, nrm, prepared, prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(29)
+    idx = np.concatenate([np.arange(64), np.arange(n - 64, n), rng.integers(0, n, 20000)])
+    it = torch.from_numpy(idx).to(DEV)
+    p_s, n_s = pos[it].cpu().numpy(), nrm[it].cpu().numpy()
+    E_s, fl_s = E[it].cpu().numpy().astype(np.float64), fl[it].cpu().numpy()
+    del pos, nrm, E, fl
+    E_ref, _, fl_ref, sc = _oracle(oc, params, prec, p_s, n_s)
+    _check(prec, E_s, E_ref, sc)
+    assert_flags(fl_s, fl_ref, E_ref, sign_margin(prec, E_ref, sc))
+    assert (fl_s & 1).any() and not (fl_s & 1).all()   # some points outside the box
+    small = torch.zeros((1 << 28, 3), dtype=torch.float32, device=DEV)
+    with pytest.raises(N.NivError) as e:
+        m.query(small, small, prepared, prec)
+    assert e.value.status == N.NIV_ERR_INVALID_ARG
