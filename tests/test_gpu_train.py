@@ -150,6 +150,21 @@ def test_full_batch_gradient_is_bit_reproducible():
     assert same
 
 
+def test_largest_batch_gradient_matches_oracle():
+    """The largest batch niv_backward takes, 2^24 samples (2^31 contribution
+    records on the 16-level room model; level 0's first bin alone gets ~1.1e8
+    records, summed in ~1,100 parts): FP16 gradient of every block against
+    the FP64 oracle at the bars of the small batches."""
+    n = 1 << 24
+    w, oc, params, x, nrm, tgt = _setup("room_1080p", n, seed=24)
+    print(f"room_1080p fp16 n={n}", flush=True)
+    loss, g = _gpu_grad(w, params, x, nrm, tgt, "fp16")
+    p16 = params.astype(np.float16).astype(np.float64)
+    l_ref, g_ref = O.loss_grad(oc, p16, x, nrm, tgt)
+    assert loss == pytest.approx(l_ref, rel=5e-3)
+    _compare(oc, g, g_ref, 2e-2, grid_bar=3e-2)
+
+
 def test_nonfinite_step_is_reported_and_skipped():
     """A non-finite target makes the step's loss non-finite: niv_train_step
     leaves parameters and moments as they were and niv_train_status reports
