@@ -20,7 +20,8 @@
 //      level, without global atomics (device-scope atomics execute at the
 //      memory side of this part, ~22 G/s): the contributions are counted
 //      per bin of 4096 grid entries and workgroup (k_grid_count), the
-//      counts are scanned (k_grid_scan_bins, k_grid_scan_totals), the
+//      counts are scanned (k_grid_scan_bins, and the bins' totals at the
+//      start of the write pass), the
 //      contributions are written bin by bin (k_grid_write), and one or more
 //      workgroups per bin sum their contributions in LDS in 64-bit fixed
 //      point (k_grid_accum); a bin split over several workgroups has its
@@ -531,7 +532,7 @@ constexpr int kBinShift = 12;                 // 4096 entries (32 KB of FP32 pai
 constexpr int kBinEntries = 1 << kBinShift;
 constexpr int kMaxBins = 2048;
 constexpr int kBwdMaxBlocks = 512;            // workgroups of the backward (4 dW rows each)
-constexpr int kScatterBlocks = 256;           // workgroups of the count and write passes
+constexpr int kScatterBlocks = 512;           // workgroups of the count and write passes
 constexpr int kAccumRecords = 98304;          // records one accumulating workgroup takes (1.5x a
                                               // hashed level's bin at 2^18 samples: those stay whole)
 
@@ -546,7 +547,9 @@ struct ScatterArgs {
     const float *dx0;          // [chunk][L][64] float pairs
     const uint8_t *sflag;      // [n]
     const uint8_t *model;      // prepared model (level table first)
-    uint32_t *counts;          // [bins][kScatterBlocks] per workgroup, then their offsets
+    uint32_t *counts;          // [kScatterBlocks][cstride] per workgroup and bin, then their
+                               // offsets within the bin
+    uint32_t *totals;          // [kMaxBins] records of each bin
     uint32_t *bin_start;       // [bins + 1]
     uint32_t *work_start;      // [bins + 1] first accumulating workgroup of each bin
     uint32_t *split;           // [bins + 1] bins split over several workgroups, in order; [bins] count
@@ -560,17 +563,30 @@ struct ScatterArgs {
     float *grads;              // grid part of the gradient: [entries][2]
     int64_t n, n_entries;
     int32_t n_levels, n_bins;
+    int32_t cstride;           // row length of counts: n_bins rounded up to 4
     uint32_t hash_mask;
     float loss_scale;
     double lo[3], hi[3];
 };
 
 // Both passes: one wave takes a 64-sample chunk through every level (the
-// level is wave-uniform, so its constants are scalar loads), with the chunks
-// strided identically, so a workgroup writes exactly the records it counted.
-constexpr int kScatterWaves = 16;
+// level is wave-uniform, so its constants are scalar loads); workgroup b
+// takes chunks kScatterWaves b + w, strided by kScatterWaves x the grid, in
+// both passes, so a workgroup writes exactly the records it counted.
+constexpr int kScatterWaves = 8;
 constexpr int kScatterThreads = 64 * kScatterWaves;
 constexpr int kScatterMaxLevels = 16;          // levels of the trainable shapes
+
+// Inclusive scan over the 64 lanes of a wave.
+__device__ inline uint32_t wave_scan_incl(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
 
 __device__ inline bool scatter_sample(const ScatterArgs &a, int64_t q, double p[3])
 {
@@ -613,26 +629,20 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_count(const ScatterArg
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < a.n_bins; b += kScatterThreads)
-        a.counts[(int64_t)b * kScatterBlocks + blockIdx.x] = cnt[b];
+    uint32_t *row = a.counts + (int64_t)blockIdx.x * a.cstride;
+    for (int b = threadIdx.x; b < a.cstride; b += kScatterThreads) row[b] = b < a.n_bins ? cnt[b] : 0u;
 }
 
-// Per-wave LDS of the write pass: 512 staged records and three 64-entry
-// per-bin arrays.
-__host__ __device__ constexpr int write_wave_bytes()
-{
-    return 512 * 16 + 3 * 64 * 4;
-}
-
-// Write pass.  Per level the chunk's feature gradients are one coalesced
-// load (the backward stores them level-major per chunk), and the wave
-// orders its 512 records by bin in LDS: a histogram
-// over (a window of 64 of) the level's bins gives each record its rank in its
-// bin, one counter update per bin reserves the wave's run in the workgroup's
-// segment of that bin, and a scan of the histogram places the runs one after
-// the other.  The records are then stored in that order, so consecutive lanes
-// write consecutive slots of a bin's segment (runs of ~16 records on a hashed
-// level instead of single 4- and 8-byte stores).
+// Write pass.  The waves of a workgroup order the records of their chunks
+// at one level together, so that each bin receives one run of consecutive
+// slots per workgroup (~128 records on a hashed level of 2^17 entries, for
+// 8 chunks of 64 samples): per window of 64 of the level's bins, a histogram in LDS
+// gives each record its rank in its bin, one wave scans the histogram and
+// reserves each bin's run in the workgroup's segment of that bin, the
+// records are staged in that order, and the workgroup stores them with
+// consecutive threads on consecutive slots.  The feature gradients of a
+// chunk are read one level at a time with a coalesced load (the backward
+// stores them level-major per chunk).
 // H16 (the FP16 training path): records carry the contributions as an FP16
 // pair scaled by 2^(14 - e), M < 2^e, so every value is below 2^14 and keeps
 // 11 significant bits (the operands of that path are FP16 already); 6 bytes
@@ -640,18 +650,84 @@ __host__ __device__ constexpr int write_wave_bytes()
 template <bool H16>
 __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArgs a)
 {
-    __shared__ uint32_t cnt[kMaxBins];
-    extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
+    // staged records: (bin in the window << 16 | entry within the bin) and
+    // the value(s)
+    using Val = typename std::conditional<H16, uint32_t, uint2>::type;
+    constexpr int kWindow = 64;                     // bins ordered per pass
+    __shared__ uint32_t cnt[kMaxBins];              // next free slot of each bin's segment
+    __shared__ uint32_t hist[kWindow], lst[kWindow], gofs[kWindow];
+    __shared__ uint32_t s_total;
+    __shared__ uint32_t skey[kScatterThreads * 8];
+    __shared__ Val sval[kScatterThreads * 8];
     typedef const __attribute__((address_space(4))) LevelConst *ConstLevels;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int L = a.n_levels;
-    uint8_t *mine = dyn + wave * write_wave_bytes();
-    u4 *stage = reinterpret_cast<u4 *>(mine);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(mine + 512 * 16);
-    uint32_t *bbase = hist + 64, *lstart = hist + 128;
-    for (int b = threadIdx.x; b < a.n_bins; b += kScatterThreads)
-        cnt[b] = a.bin_start[b] + a.counts[(int64_t)b * kScatterBlocks + blockIdx.x];
+    // Scans of the bins' totals, four bins per thread, in every workgroup:
+    // the first slot of each bin's segment of this workgroup; workgroup 0
+    // also stores the first record and the first accumulating workgroup
+    // (ceil(total / kAccumRecords), at least one) of each bin, the list of
+    // bins split over several workgroups and the records of the fullest bin.
+    static_assert(kScatterThreads * 4 == kMaxBins, "four bins per thread");
+    __shared__ uint32_t wtot[3][kScatterWaves];
+    __shared__ uint32_t s_max;
+    {
+        const uint32_t *crow = a.counts + (int64_t)blockIdx.x * a.cstride;
+        const int b0 = 4 * t;
+        const uint4 tv = reinterpret_cast<const uint4 *>(a.totals)[t];
+        const uint32_t tr[4] = {tv.x, tv.y, tv.z, tv.w};
+        uint32_t tot[4], grp[4], spl[4], v[3] = {0u, 0u, 0u}, mx = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool in = b0 + i < a.n_bins;
+            tot[i] = in ? tr[i] : 0u;
+            grp[i] = in ? (tot[i] > kAccumRecords ? (tot[i] + kAccumRecords - 1) / kAccumRecords : 1u) : 0u;
+            spl[i] = (in && tot[i] > kAccumRecords) ? 1u : 0u;
+            v[0] += tot[i]; v[1] += grp[i]; v[2] += spl[i];
+            mx = tot[i] > mx ? tot[i] : mx;
+        }
+        if (t == 0) s_max = 0u;
+        uint32_t incl[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            incl[k] = wave_scan_incl(v[k], lane);
+            if (lane == 63) wtot[k][wave] = incl[k];
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_xor(mx, d);
+            mx = o > mx ? o : mx;
+        }
+        __syncthreads();
+        if (lane == 0) atomicMax(&s_max, mx);
+        uint32_t ex[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint32_t before = 0u;
+            for (int u = 0; u < wave; ++u) before += wtot[k][u];
+            ex[k] = before + incl[k] - v[k];
+        }
+        uint32_t s0 = ex[0], s1 = ex[1], s2 = ex[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int b = b0 + i;
+            if (b < a.n_bins) cnt[b] = s0 + crow[b];
+            s0 += tot[i];
+            s1 += grp[i];
+            if (blockIdx.x == 0 && b < a.n_bins) {
+                a.bin_start[b + 1] = s0;
+                a.work_start[b + 1] = s1;
+                if (spl[i]) a.split[s2++] = (uint32_t)b;
+            }
+        }
+        if (blockIdx.x == 0 && t == 0) {
+            a.bin_start[0] = 0u;
+            a.work_start[0] = 0u;
+        }
+        if (blockIdx.x == 0 && t == kScatterThreads - 1) a.split[a.n_bins] = s2;
+    }
+    if (t < kWindow) hist[t] = 0u;
     __syncthreads();
+    if (blockIdx.x == 0 && t == 0) a.vmax[1] = s_max;
     const int64_t n_chunks = (a.n + 63) / 64;
     ConstLevels lvs = (ConstLevels)a.model;
     [[maybe_unused]] float rs = 1.0f;
@@ -660,146 +736,109 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
         (void)frexpf(u2f(a.vmax[0]), &e);
         rs = ldexpf(1.0f, 14 - e);
     }
-    for (int64_t chunk = (int64_t)blockIdx.x * kScatterWaves + wave; chunk < n_chunks;
-         chunk += (int64_t)gridDim.x * kScatterWaves) {
+    // the iteration count is uniform over the workgroup (barriers inside)
+    for (int64_t g0 = (int64_t)blockIdx.x * kScatterWaves; g0 < n_chunks;
+         g0 += (int64_t)gridDim.x * kScatterWaves) {
+        const int64_t chunk = g0 + wave;
         const int64_t q0 = chunk * 64;
         const float2 *src = reinterpret_cast<const float2 *>(a.dx0) + q0 * L + lane;
         double p[3] = {a.lo[0], a.lo[1], a.lo[2]};
-        const bool live = scatter_sample(a, q0 + lane, p);
+        const bool live = chunk < n_chunks && scatter_sample(a, q0 + lane, p);
         for (int l = 0; l < L; ++l) {
             uint32_t idx[8];
             float w[8];
             level_corners(lvs[l], p, a.hash_mask, idx, w);
             const float2 gg = live ? src[l * 64] : make_float2(0.0f, 0.0f);
-            const float g0 = gg.x * a.loss_scale, g1 = gg.y * a.loss_scale;
+            const float g0v = gg.x * a.loss_scale, g1v = gg.y * a.loss_scale;
             const uint32_t off = lvs[l].off;
             const uint32_t size = lvs[l].dense ? lvs[l].s1 * lvs[l].s2 : a.hash_mask + 1u;
             const uint32_t fb = off >> kBinShift;                  // first bin of the level
             const uint32_t nlb = ((off + size - 1u) >> kBinShift) - fb + 1u;
-            for (uint32_t w0 = 0; w0 < nlb; w0 += 64) {
-                hist[lane] = 0u;
-                wave_lds_fence();
+            for (uint32_t w0 = 0; w0 < nlb; w0 += kWindow) {
                 uint32_t rb[8], slot[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    rb[c] = (idx[c] >> kBinShift) - fb - w0;      // >= 64 (wrapped) outside the window
-                    slot[c] = (live && rb[c] < 64u) ? atomicAdd(&hist[rb[c]], 1u) : ~0u;
+                    rb[c] = (idx[c] >> kBinShift) - fb - w0;      // >= kWindow (wrapped) outside the window
+                    slot[c] = (live && rb[c] < (uint32_t)kWindow) ? atomicAdd(&hist[rb[c]], 1u) : ~0u;
                 }
-                wave_lds_fence();
-                const uint32_t nb = hist[lane];
-                const uint32_t base = nb ? atomicAdd(&cnt[fb + w0 + lane], nb) : 0u;
-                uint32_t incl = nb;   // inclusive scan over the lanes
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const uint32_t t = __shfl_up(incl, d);
-                    if (lane >= d) incl += t;
+                __syncthreads();
+                if (wave == 0) {
+                    // runs of the window's bins: a bin with records is a bin of
+                    // this level, so its cursor exists; one lane per bin
+                    const uint32_t nb = hist[lane];
+                    const uint32_t incl = wave_scan_incl(nb, lane);
+                    uint32_t base = 0u;
+                    if (nb) {
+                        base = cnt[fb + w0 + lane];
+                        cnt[fb + w0 + lane] = base + nb;
+                    }
+                    lst[lane] = incl - nb;
+                    gofs[lane] = base - (incl - nb);   // slot of staged record k: gofs[bin] + k
+                    hist[lane] = 0u;
+                    if (lane == 63) s_total = incl;
                 }
-                const uint32_t total = __shfl(incl, 63);
-                bbase[lane] = base;
-                lstart[lane] = incl - nb;
-                wave_lds_fence();
+                __syncthreads();
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     if (slot[c] == ~0u) continue;
-                    const float v0 = w[c] * g0, v1 = w[c] * g1;
-                    if constexpr (H16)
-                        stage[lstart[rb[c]] + slot[c]] =
-                            (u4){bbase[rb[c]] + slot[c], idx[c], Prec<NIV_FP16>::pack(v0 * rs, v1 * rs), 0u};
-                    else
-                        stage[lstart[rb[c]] + slot[c]] = (u4){bbase[rb[c]] + slot[c], idx[c], f2u(v0), f2u(v1)};
+                    const float v0 = w[c] * g0v, v1 = w[c] * g1v;
+                    const uint32_t k = lst[rb[c]] + slot[c];
+                    skey[k] = (rb[c] << 16) | (idx[c] & (kBinEntries - 1));
+                    if constexpr (H16) sval[k] = Prec<NIV_FP16>::pack(v0 * rs, v1 * rs);
+                    else sval[k] = make_uint2(f2u(v0), f2u(v1));
                 }
-                wave_lds_fence();
-                for (uint32_t k = lane; k < total; k += 64) {
-                    const u4 e = stage[k];
-                    a.keys[e.x] = (uint16_t)(e.y & (kBinEntries - 1));
-                    if constexpr (H16) a.vals16[e.x] = e.z;
-                    else a.vals[e.x] = make_float2(u2f(e.z), u2f(e.w));
+                __syncthreads();
+                const uint32_t total = s_total;
+                for (uint32_t k = t; k < total; k += kScatterThreads) {
+                    const uint32_t key = skey[k];
+                    const Val v = sval[k];
+                    const uint32_t dst = gofs[key >> 16] + k;
+                    a.keys[dst] = (uint16_t)(key & 0xFFFFu);
+                    if constexpr (H16) a.vals16[dst] = v;
+                    else a.vals[dst] = make_float2(u2f(v.x), u2f(v.y));
                 }
-                wave_lds_fence();   // hist and stage are reused
+                __syncthreads();   // the stage and the window's arrays are reused
             }
         }
     }
 }
 
-// Inclusive scan over the 64 lanes of a wave.
-__device__ inline uint32_t wave_scan_incl(uint32_t v, int lane)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
-
-// Per bin (one workgroup of kScatterBlocks threads): exclusive scan of the
-// workgroups' counts, in place; the bin's total goes to bin_start[b + 1].
+// Exclusive scans of the workgroups' counts of each bin, in place: workgroup
+// i of this kernel takes bins 4 i .. 4 i + 3 and thread t the counts of
+// workgroup t (one 16-byte piece of its row); the bins' totals go to
+// totals[b].
 __global__ __launch_bounds__(kScatterBlocks) void k_grid_scan_bins(const ScatterArgs a)
 {
     constexpr int kW = kScatterBlocks / 64;
-    __shared__ uint32_t wsum[kW];
-    const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    uint32_t *row = a.counts + (int64_t)b * kScatterBlocks;
-    const uint32_t c = row[t];
-    const uint32_t incl = wave_scan_incl(c, lane);
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    uint32_t before = 0u, total = 0u;
-#pragma unroll
-    for (int k = 0; k < kW; ++k) {
-        before += k < wv ? wsum[k] : 0u;
-        total += wsum[k];
-    }
-    row[t] = before + incl - c;
-    if (t == 0) a.bin_start[b + 1] = total;
-}
-
-// Exclusive scans of the bin totals (one workgroup of 1024 threads, two bins
-// per thread): bin starts, first accumulating workgroup of each bin
-// (ceil(total / kAccumRecords) workgroups, at least one) and the list of
-// bins split over several workgroups; the three scans share one pass.
-__global__ __launch_bounds__(1024) void k_grid_scan_totals(const ScatterArgs a)
-{
-    static_assert(kMaxBins == 2 * 1024, "two bins per thread");
-    __shared__ uint32_t ws[3][16];
-    __shared__ uint32_t smax;
+    __shared__ uint32_t wsum[4][kW];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int b0 = 2 * t, b1 = 2 * t + 1;
-    const uint32_t tot0 = b0 < a.n_bins ? a.bin_start[b0 + 1] : 0u;
-    const uint32_t tot1 = b1 < a.n_bins ? a.bin_start[b1 + 1] : 0u;
-    auto groups = [&](int b, uint32_t tot) {
-        return b < a.n_bins ? (tot > kAccumRecords ? (tot + kAccumRecords - 1) / kAccumRecords : 1u) : 0u;
-    };
-    auto split = [&](int b, uint32_t tot) { return (b < a.n_bins && tot > kAccumRecords) ? 1u : 0u; };
-    const uint32_t v[3] = {tot0 + tot1, groups(b0, tot0) + groups(b1, tot1), split(b0, tot0) + split(b1, tot1)};
-    uint32_t incl[3], excl[3];
-    if (t == 0) smax = 0u;
+    const int b0 = 4 * blockIdx.x;
+    uint4 *row = reinterpret_cast<uint4 *>(a.counts + (int64_t)t * a.cstride + b0);
+    const uint4 v = *row;
+    const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+    uint32_t incl[4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        incl[k] = wave_scan_incl(v[k], lane);
-        if (lane == 63) ws[k][wv] = incl[k];
+    for (int k = 0; k < 4; ++k) {
+        incl[k] = wave_scan_incl(c[k], lane);
+        if (lane == 63) wsum[k][wv] = incl[k];
     }
     __syncthreads();
+    uint32_t ex[4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        uint32_t before = 0u;
-        for (int u = 0; u < wv; ++u) before += ws[k][u];
-        excl[k] = before + incl[k] - v[k];   // before this thread's first bin
+    for (int k = 0; k < 4; ++k) {
+        // totals of the waves before this one: lane u < wv holds wave u's,
+        // summed over the whole wave
+        uint32_t before = lane < wv ? wsum[k][lane] : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) before += __shfl_xor(before, d);
+        ex[k] = before + incl[k] - c[k];
     }
-    // bin starts (bin_start[b + 1] held the totals: every thread has read its own)
-    __syncthreads();
-    if (b0 <= a.n_bins) a.bin_start[b0] = excl[0];
-    if (b1 <= a.n_bins) a.bin_start[b1] = excl[0] + tot0;
-    if (b0 <= a.n_bins) a.work_start[b0] = excl[1];
-    if (b1 <= a.n_bins) a.work_start[b1] = excl[1] + groups(b0, tot0);
-    // the bins split over several workgroups, in bin order (k_grid_merge)
-    if (split(b0, tot0)) a.split[excl[2]] = (uint32_t)b0;
-    if (split(b1, tot1)) a.split[excl[2] + split(b0, tot0)] = (uint32_t)b1;
-    if (t == 1023) a.split[a.n_bins] = excl[2] + v[2];
-    // records of the fullest bin: they bound the fixed-point sums
-    atomicMax(&smax, tot0 > tot1 ? tot0 : tot1);
-    __syncthreads();
-    if (t == 0) a.vmax[1] = smax;
+    *row = make_uint4(ex[0], ex[1], ex[2], ex[3]);
+    if (t < 4 && b0 + t < a.n_bins) {
+        uint32_t total = 0u;
+        for (int u = 0; u < kW; ++u) total += wsum[t][u];
+        a.totals[b0 + t] = total;
+    }
 }
 
 // Scale of the step's fixed-point sums: with M the largest |contribution| <
@@ -899,24 +938,37 @@ __global__ __launch_bounds__(1024) void k_grid_accum(const ScatterArgs a)
     }
 }
 
-// Bins split over several workgroups: their parts' integer sums added in
-// part order, then scaled once.  Workgroup (i, s) takes values 256 s .. 256 s
-// + 255 of the i-th split bin; the launch is sized by the most bins that can
-// be split, the workgroups beyond the step's count return at once.
+// Bins split over several workgroups: their parts' integer sums added, then
+// scaled once.  Job (i, s) takes values 256 s .. 256 s + 255
+// of the i-th split bin; a grid of at most kMergeBlocks workgroups walks the
+// step's jobs.
 constexpr int kMergeSlices = 2 * kBinEntries / 256;
+constexpr int kMergeBlocks = 512;
 __global__ __launch_bounds__(256) void k_grid_merge(const ScatterArgs a)
 {
-    const uint32_t i = blockIdx.x / kMergeSlices;
-    if (i >= a.split[a.n_bins]) return;
-    const int b = (int)a.split[i];
-    const int k = (blockIdx.x % kMergeSlices) * 256 + threadIdx.x;
-    const uint32_t w0 = a.work_start[b], parts = a.work_start[b + 1] - w0;
-    const int64_t en = ((int64_t)b << kBinShift) + (k >> 1);
-    if (en >= a.n_entries) return;
-    const long long *src = a.parts + (int64_t)w0 * (2 * kBinEntries) + k;
-    long long s = 0;
-    for (uint32_t p = 0; p < parts; ++p) s += src[(int64_t)p * (2 * kBinEntries)];
-    a.grads[2 * en + (k & 1)] = (float)((double)s * ldexp(1.0, -fixed_shift(a.vmax)));
+    const uint32_t jobs = a.split[a.n_bins] * (uint32_t)kMergeSlices;
+    const double down = ldexp(1.0, -fixed_shift(a.vmax));
+    for (uint32_t job = blockIdx.x; job < jobs; job += gridDim.x) {
+        const int b = (int)a.split[job / kMergeSlices];
+        const int k = (int)(job % kMergeSlices) * 256 + threadIdx.x;
+        const uint32_t w0 = a.work_start[b], parts = a.work_start[b + 1] - w0;
+        const int64_t en = ((int64_t)b << kBinShift) + (k >> 1);
+        if (en >= a.n_entries) continue;
+        const long long *src = a.parts + (int64_t)w0 * (2 * kBinEntries) + k;
+        // integer sums: any order gives the same value, so the parts' loads
+        // go out eight at a time
+        long long sum = 0;
+        uint32_t q = 0;
+        for (; q + 8 <= parts; q += 8) {
+            long long v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(q + u) * (2 * kBinEntries)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sum += v[u];
+        }
+        for (; q < parts; ++q) sum += src[(int64_t)q * (2 * kBinEntries)];
+        a.grads[2 * en + (k & 1)] = (float)((double)sum * down);
+    }
 }
 
 // ---------------------------------------------------------------- Adam
@@ -1031,7 +1083,7 @@ __global__ void k_init_params(const InitArgs a)
 
 // ---------------------------------------------------------------- host side
 struct TrainLayout {
-    int64_t bwd_off, x_off, mask_off, dE_off, dx0_off, sflag_off, counts_off, start_off, work_off,
+    int64_t bwd_off, x_off, mask_off, dE_off, dx0_off, sflag_off, counts_off, tot_off, start_off, work_off,
         split_off, vmax_off, keys_off, vals_off, dw_off, parts_off, total;
 };
 
@@ -1062,7 +1114,8 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
     L.dx0_off = L.dE_off + align256(n * 3 * 4);
     L.sflag_off = L.dx0_off + align256((n + 63) / 64 * 64 * 2 * S::L * 4);
     L.counts_off = L.sflag_off + align256(n);
-    L.start_off = L.counts_off + align256((int64_t)kMaxBins * kScatterBlocks * 4);
+    L.tot_off = L.counts_off + align256((int64_t)kMaxBins * kScatterBlocks * 4);
+    L.start_off = L.tot_off + align256(kMaxBins * 4);
     L.work_off = L.start_off + align256((kMaxBins + 1) * 4);
     L.split_off = L.work_off + align256((kMaxBins + 1) * 4);
     L.keys_off = L.split_off + align256((kMaxBins + 1) * 4);
@@ -1203,6 +1256,7 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.sflag = ba.sflag;
     sa.model = static_cast<const uint8_t *>(st.model);
     sa.counts = reinterpret_cast<uint32_t *>(ws + L.counts_off);
+    sa.totals = reinterpret_cast<uint32_t *>(ws + L.tot_off);
     sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
     sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
     sa.split = reinterpret_cast<uint32_t *>(ws + L.split_off);
@@ -1219,30 +1273,21 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     sa.hash_mask = a.hash_mask;
     sa.loss_scale = loss_scale;
     for (int c = 0; c < 3; ++c) { sa.lo[c] = a.lo[c]; sa.hi[c] = a.hi[c]; }
+    sa.cstride = (sa.n_bins + 3) & ~3;
     if (sa.n_bins > kMaxBins) return hipErrorInvalidValue;
     if (sa.n_levels > kScatterMaxLevels) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
-    hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.n_bins), dim3(kScatterBlocks), 0, stream, sa);
-    hipLaunchKernelGGL(k_grid_scan_totals, dim3(1), dim3(1024), 0, stream, sa);
-    const int write_lds = kScatterWaves * write_wave_bytes();
+    hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.cstride / 4), dim3(kScatterBlocks), 0, stream, sa);
     constexpr bool H16 = !B::F32;
-    static bool write_lds_set = false;   // dynamic LDS beyond 64 KB must be allowed per kernel
-    if (!write_lds_set) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_grid_write<H16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kScatterWaves * write_wave_bytes());
-        if (e != hipSuccess) return e;
-        write_lds_set = true;
-    }
-    hipLaunchKernelGGL(k_grid_write<H16>, dim3(kScatterBlocks), dim3(kScatterThreads), (size_t)write_lds,
-                       stream, sa);
+    hipLaunchKernelGGL(k_grid_write<H16>, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
     const int64_t acc_groups = acc_group_bound(b.count, m.cfg.n_levels, sa.n_bins);
     hipLaunchKernelGGL(k_grid_accum<H16>, dim3((unsigned)acc_groups), dim3(1024), 0, stream, sa);
     // a split bin holds more than kAccumRecords records
     const int64_t records = b.count * (int64_t)m.cfg.n_levels * 8;
     const int64_t max_split = std::min<int64_t>(sa.n_bins, records / (kAccumRecords + 1));
     if (max_split > 0)
-        hipLaunchKernelGGL(k_grid_merge, dim3((unsigned)(max_split * kMergeSlices)), dim3(256), 0, stream, sa);
+        hipLaunchKernelGGL(k_grid_merge, dim3((unsigned)std::min<int64_t>(max_split * kMergeSlices, kMergeBlocks)),
+                           dim3(256), 0, stream, sa);
     return hipGetLastError();
 }
 
