@@ -744,11 +744,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
         const float2 *src = reinterpret_cast<const float2 *>(a.dx0) + q0 * L + lane;
         double p[3] = {a.lo[0], a.lo[1], a.lo[2]};
         const bool live = chunk < n_chunks && scatter_sample(a, q0 + lane, p);
+        // the next level's feature gradients are loaded while a level is ordered
+        float2 gn = live ? src[0] : make_float2(0.0f, 0.0f);
         for (int l = 0; l < L; ++l) {
+            const float2 gg = gn;
+            if (l + 1 < L) gn = live ? src[(l + 1) * 64] : make_float2(0.0f, 0.0f);
             uint32_t idx[8];
             float w[8];
             level_corners(lvs[l], p, a.hash_mask, idx, w);
-            const float2 gg = live ? src[l * 64] : make_float2(0.0f, 0.0f);
             const float g0v = gg.x * a.loss_scale, g1v = gg.y * a.loss_scale;
             const uint32_t off = lvs[l].off;
             const uint32_t size = lvs[l].dense ? lvs[l].s1 * lvs[l].s2 : a.hash_mask + 1u;
