@@ -1371,12 +1371,15 @@ static niv_status adam_launch(const Model &m, const niv_train_state *st, const n
 {
     const double bc1 = 1.0 - pow((double)ad->beta1, (double)ad->step);
     const double bc2 = 1.0 - pow((double)ad->beta2, (double)ad->step);
+    // one group of four values per thread (up to 2^22 groups; more loop)
+    const int64_t groups = (m.n_params + 3) / 4;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 255) / 256, 16384));
     if (prec == NIV_FP32)
-        hipLaunchKernelGGL(k_adam<NIV_FP32>, dim3(2048), dim3(256), 0, stream, st->params, st->grads,
+        hipLaunchKernelGGL(k_adam<NIV_FP32>, dim3(blocks), dim3(256), 0, stream, st->params, st->grads,
                            st->adam_m, st->adam_v, m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps,
                            (float)bc1, (float)bc2, status, grid_out, m.n_grid_values);
     else
-        hipLaunchKernelGGL(k_adam<NIV_FP16>, dim3(2048), dim3(256), 0, stream, st->params, st->grads,
+        hipLaunchKernelGGL(k_adam<NIV_FP16>, dim3(blocks), dim3(256), 0, stream, st->params, st->grads,
                            st->adam_m, st->adam_v, m.n_params, ad->lr, ad->beta1, ad->beta2, ad->eps,
                            (float)bc1, (float)bc2, status, grid_out, m.n_grid_values);
     return hst(hipGetLastError());
