@@ -37,6 +37,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "niv_internal.h"
 #include "niv_device.h"
@@ -545,7 +546,8 @@ constexpr int kStatusWords = 4;
 struct ScatterArgs {
     const float *x;            // [n][3] sample positions
     const float *dx0;          // [chunk][L][64] float pairs
-    const uint8_t *sflag;      // [n]
+    const uint8_t *sflag;      // [n] 1: the sample's contributions are not zero (set by the backward)
+    const uint8_t *valid;      // [n] the batch's valid flags, or NULL
     const uint8_t *model;      // prepared model (level table first)
     uint32_t *counts;          // [kScatterBlocks][cstride] per workgroup and bin, then their
                                // offsets within the bin
@@ -588,12 +590,20 @@ __device__ inline uint32_t wave_scan_incl(uint32_t v, int lane)
     return v;
 }
 
+// The samples that have records: every valid sample of the batch with a
+// finite position (a superset of the samples that scatter, so the counts
+// need nothing from the backward); the records of a sample the backward
+// leaves out (sflag 0: its d loss / dE is zero, or the step is not finite)
+// carry zeros.  p: the position clamped to the box, as the forward takes it.
 __device__ inline bool scatter_sample(const ScatterArgs &a, int64_t q, double p[3])
 {
-    if (q >= a.n || !a.sflag[q]) return false;
+    if (q >= a.n || (a.valid && !a.valid[q])) return false;
+    const float x0 = a.x[3 * q], x1 = a.x[3 * q + 1], x2 = a.x[3 * q + 2];
+    if (!(__builtin_isfinite(x0) && __builtin_isfinite(x1) && __builtin_isfinite(x2))) return false;
+    const float xs[3] = {x0, x1, x2};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double v = a.x[3 * q + c];
+        const double v = xs[c];
         p[c] = v < a.lo[c] ? a.lo[c] : (v > a.hi[c] ? a.hi[c] : v);
     }
     return true;
@@ -744,11 +754,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_grid_write(const ScatterArg
         const float2 *src = reinterpret_cast<const float2 *>(a.dx0) + q0 * L + lane;
         double p[3] = {a.lo[0], a.lo[1], a.lo[2]};
         const bool live = chunk < n_chunks && scatter_sample(a, q0 + lane, p);
+        const bool sc = live && a.sflag[q0 + lane] != 0;   // else the records carry zeros
         // the next level's feature gradients are loaded while a level is ordered
-        float2 gn = live ? src[0] : make_float2(0.0f, 0.0f);
+        float2 gn = sc ? src[0] : make_float2(0.0f, 0.0f);
         for (int l = 0; l < L; ++l) {
             const float2 gg = gn;
-            if (l + 1 < L) gn = live ? src[(l + 1) * 64] : make_float2(0.0f, 0.0f);
+            if (l + 1 < L) gn = sc ? src[(l + 1) * 64] : make_float2(0.0f, 0.0f);
             uint32_t idx[8];
             float w[8];
             level_corners(lvs[l], p, a.hash_mask, idx, w);
@@ -1134,6 +1145,38 @@ template <int P, class S> TrainLayout train_layout_t(int64_t n, int64_t n_bins)
     return L;
 }
 
+// A second stream per device for work that runs beside the caller's stream
+// (created once, default priority, kept until the process ends), and the
+// two events of one fork and join (released when the call returns; an event
+// still pending is released once it completes).
+static std::mutex g_side_mu;
+static hipStream_t g_side[64];
+static hipError_t side_stream(hipStream_t *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    if (!g_side[dev] && (e = hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking)) != hipSuccess)
+        return e;
+    *out = g_side[dev];
+    return hipSuccess;
+}
+struct SideFork {
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        return e != hipSuccess ? e : hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    }
+    ~SideFork()
+    {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
 template <int P, class S>
 static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train_state &st,
                              hipStream_t stream)
@@ -1178,6 +1221,47 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     a.train_status = status;
     a.loss_scale = (float)(1.0 / (3.0 * (double)b.count));  // used by the forward's loss sum
     a.loss_eps = 0.01f;
+    // grid scatter arguments
+    ScatterArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.x = b.x;
+    sa.dx0 = reinterpret_cast<const float *>(ws + L.dx0_off);
+    sa.sflag = ws + L.sflag_off;
+    sa.valid = b.valid;
+    sa.model = static_cast<const uint8_t *>(st.model);
+    sa.counts = reinterpret_cast<uint32_t *>(ws + L.counts_off);
+    sa.totals = reinterpret_cast<uint32_t *>(ws + L.tot_off);
+    sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
+    sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
+    sa.split = reinterpret_cast<uint32_t *>(ws + L.split_off);
+    sa.vmax = status;
+    sa.parts = reinterpret_cast<long long *>(ws + L.parts_off);
+    sa.keys = reinterpret_cast<uint16_t *>(ws + L.keys_off);
+    sa.vals = reinterpret_cast<float2 *>(ws + L.vals_off);
+    sa.vals16 = reinterpret_cast<uint32_t *>(ws + L.vals_off);
+    sa.grads = st.grads;
+    sa.n = b.count;
+    sa.n_entries = m.n_grid_values / 2;
+    sa.n_levels = m.cfg.n_levels;
+    sa.n_bins = (int32_t)((sa.n_entries + kBinEntries - 1) >> kBinShift);
+    sa.hash_mask = a.hash_mask;
+    sa.loss_scale = (float)(1.0 / (3.0 * (double)b.count));
+    for (int c = 0; c < 3; ++c) { sa.lo[c] = a.lo[c]; sa.hi[c] = a.hi[c]; }
+    sa.cstride = (sa.n_bins + 3) & ~3;
+    if (sa.n_bins > kMaxBins) return hipErrorInvalidValue;
+    if (sa.n_levels > kScatterMaxLevels) return hipErrorInvalidValue;
+    // the count pass reads only the batch and the level table: it runs on a
+    // second stream beside the forward (an event fork and join with the
+    // caller's stream; both at the default priority)
+    SideFork ev;
+    hipStream_t side = nullptr;
+    if ((e = side_stream(&side)) != hipSuccess) return e;
+    if ((e = ev.create()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev.fork, stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side, ev.fork, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, side, sa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev.join, side)) != hipSuccess) return e;
     {
         constexpr int kBlock = 256, kWavesPerBlock = 4;
         auto kern = k_query<P, S, true, 4, true, kBlock>;
@@ -1251,35 +1335,8 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
                            (int64_t)B::NMLP, (int)blocks, st.grads + m.n_grid_values, ba.loss_scale);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // 3. grid scatter through bins
-    ScatterArgs sa;
-    memset(&sa, 0, sizeof(sa));
-    sa.x = b.x;
-    sa.dx0 = ba.dx0;
-    sa.sflag = ba.sflag;
-    sa.model = static_cast<const uint8_t *>(st.model);
-    sa.counts = reinterpret_cast<uint32_t *>(ws + L.counts_off);
-    sa.totals = reinterpret_cast<uint32_t *>(ws + L.tot_off);
-    sa.bin_start = reinterpret_cast<uint32_t *>(ws + L.start_off);
-    sa.work_start = reinterpret_cast<uint32_t *>(ws + L.work_off);
-    sa.split = reinterpret_cast<uint32_t *>(ws + L.split_off);
-    sa.vmax = status;
-    sa.parts = reinterpret_cast<long long *>(ws + L.parts_off);
-    sa.keys = reinterpret_cast<uint16_t *>(ws + L.keys_off);
-    sa.vals = reinterpret_cast<float2 *>(ws + L.vals_off);
-    sa.vals16 = reinterpret_cast<uint32_t *>(ws + L.vals_off);
-    sa.grads = st.grads;
-    sa.n = b.count;
-    sa.n_entries = m.n_grid_values / 2;
-    sa.n_levels = m.cfg.n_levels;
-    sa.n_bins = (int32_t)((sa.n_entries + kBinEntries - 1) >> kBinShift);
-    sa.hash_mask = a.hash_mask;
-    sa.loss_scale = loss_scale;
-    for (int c = 0; c < 3; ++c) { sa.lo[c] = a.lo[c]; sa.hi[c] = a.hi[c]; }
-    sa.cstride = (sa.n_bins + 3) & ~3;
-    if (sa.n_bins > kMaxBins) return hipErrorInvalidValue;
-    if (sa.n_levels > kScatterMaxLevels) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
+    // 3. grid scatter through bins (counted beside the forward, above)
+    if ((e = hipStreamWaitEvent(stream, ev.join, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_grid_scan_bins, dim3(sa.cstride / 4), dim3(kScatterBlocks), 0, stream, sa);
     constexpr bool H16 = !B::F32;
     hipLaunchKernelGGL(k_grid_write<H16>, dim3(kScatterBlocks), dim3(kScatterThreads), 0, stream, sa);
