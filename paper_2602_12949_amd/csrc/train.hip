@@ -19,13 +19,13 @@
 //   3. the scatter of those feature gradients to the 8 corners of every
 //      level, without global atomics (device-scope atomics execute at the
 //      memory side of this part, ~22 G/s): the contributions are counted
-//      per bin of 4096 grid entries and workgroup (k_grid_count), the
-//      counts are scanned (k_grid_scan_bins, and the bins' totals at the
-//      start of the write pass), the
-//      contributions are written bin by bin (k_grid_write), and one or more
-//      workgroups per bin sum their contributions in LDS in 64-bit fixed
-//      point (k_grid_accum); a bin split over several workgroups has its
-//      integer partial sums added in a fixed order (k_grid_merge), so the
+//      per bin of 4096 grid entries and workgroup (k_grid_count, on a
+//      second stream beside the forward: it needs only the batch), the
+//      counts are scanned (k_grid_scan_bins; the bins' totals at the start
+//      of the write pass), the contributions are written bin by bin
+//      (k_grid_write), and one or more workgroups per bin sum them in LDS
+//      in 64-bit fixed point (k_grid_accum); a bin split over several
+//      workgroups has its parts' integer sums added (k_grid_merge), so the
 //      whole grid gradient is independent of scheduling;
 //   4. k_adam over all parameters (it also writes the prepared model's
 //      grid), then the prepared weight operands are rebuilt.
