@@ -358,7 +358,11 @@ niv_status niv_train_sizes(const niv_handle *h, niv_precision prec, int64_t max_
  * to FP16 at a per-step power-of-two scale (11 significant bits, the
  * precision of that path's operands); with NIV_FP32 it is summed as computed.  A sample whose output or target gives a
  * non-finite d loss / dE marks the step non-finite (niv_train_status) and
- * contributes nothing to the grid. */
+ * contributes nothing to the grid.  One pass (the count of the grid scatter)
+ * runs on a second stream that the library creates once per device
+ * (default priority, kept until the process ends), forked from and joined
+ * back to `stream` with events: the call's work is complete when `stream`'s
+ * is. */
 niv_status niv_backward(niv_handle *h, const niv_batch *b, const niv_train_state *st,
                         niv_precision prec, hipStream_t stream);
 
