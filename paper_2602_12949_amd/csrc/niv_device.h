@@ -565,6 +565,32 @@ __device__ inline f2 encode_level_buf(const LV &lv, const double p[3], uint32_t 
     return level_blend<P>(f);
 }
 
+// A dense level read from a copy of its entries in LDS (tab[0] is the
+// level's first entry): the cell, fractions and blend of encode_level_buf
+// with FP64 cell coordinates, so the features are the same bit for bit.
+template <int P, class LV>
+__device__ inline f2 encode_dense_lds(const LV &lv, const double p[3], const uint32_t *tab)
+{
+    LevelFetch<P> f;
+    int32_t ci[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double s = __builtin_fma(p[a], lv.k[a], lv.o[a]);
+        int32_t c = (int32_t)s;
+        c = c < lv.nm1 ? c : lv.nm1;
+        ci[a] = c;
+        f.fr[a] = (float)(s - (double)c);
+    }
+    const uint32_t b = (uint32_t)ci[0] + lv.s1 * ((uint32_t)ci[1] + lv.s1 * (uint32_t)ci[2]);
+    const uint32_t o[4] = {b, b + lv.s1, b + lv.s2, b + lv.s2 + lv.s1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f.v[2 * k] = tab[o[k]];
+        f.v[2 * k + 1] = tab[o[k] + 1];
+    }
+    return level_blend<P>(f);
+}
+
 // A level of four features per entry (Table 1's grid rows): eight
 // corner entries of 8 bytes (16-bit) or 16 bytes (FP32), the storage kind as a
 // branch as in encode_level_buf, FP32 trilinear blend of the four features.

@@ -76,6 +76,8 @@ struct QueryArgs {
     float *loss;              // device scalar, accumulates the Eq. 3 loss
     uint32_t *train_status;   // step words of the training scratch; [2] set by a non-finite dE
     float loss_eps;           // 0.01 (Eq. 3)
+    uint32_t l0_words;        // FP16 training forward: entries of grid level 0 (dense) held in
+    uint32_t l0_off;          // LDS, or 0; and the level's first entry
     int32_t xcd_order;        // tile order, see LaunchTune
     FrameArgs f[kMaxFrames];
 };

@@ -102,6 +102,11 @@ void k_query(const QueryArgs a)
                     u4 *ldst = reinterpret_cast<u4 *>(smem + O::W_BYTES);
                     for (int k = threadIdx.x; k < kLevelBytes / 16; k += BLOCK) ldst[k] = lsrc[k];
                 }
+                if constexpr (TRAIN && P == NIV_FP16) {  // grid level 0 behind the staging blocks
+                    const uint32_t *gsrc = reinterpret_cast<const uint32_t *>(fmodel + a.grid_off) + a.l0_off;
+                    uint32_t *l0 = reinterpret_cast<uint32_t *>(smem + O::W_BYTES) + kWavesPerBlock * 64 * O::ROW_DW;
+                    for (uint32_t k = threadIdx.x; k < a.l0_words; k += BLOCK) l0[k] = gsrc[k];
+                }
                 __syncthreads();
                 staged = fi;
             }
@@ -401,7 +406,17 @@ void k_query(const QueryArgs a)
                 const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
 #pragma unroll
                 for (int l = 0; l < S::L; ++l) {
-                    const f2 f = encode_level_buf<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
+                    f2 f;
+                    if (TRAIN && P == NIV_FP16 && l == 0 && a.l0_words) {
+                        // the training forward's samples are spread over the
+                        // volume: level 0 comes from its LDS copy instead of
+                        // a gather touching a cache line per lane
+                        const uint32_t *l0 = reinterpret_cast<const uint32_t *>(smem + O::W_BYTES) +
+                                             kWavesPerBlock * 64 * O::ROW_DW;
+                        f = encode_dense_lds<P>(lvs[0], p, l0);
+                    } else {
+                        f = encode_level_buf<P, F32C>(lvs[l], p, a.hash_mask, grid_rsrc, pf);
+                    }
                     if constexpr (P == NIV_FP32) {
                         row[2 * l] = f2u(f.x);
                         row[2 * l + 1] = f2u(f.y);

@@ -46,7 +46,8 @@
 
 namespace niv {
 
-constexpr int kMaxMats = 12;   // weight matrices of a model (n_hidden + 1) niv_init_params takes
+constexpr int kMaxMats = 12;
+constexpr int kL0Words = 5120;   // LDS copy of grid level 0 in the FP16 training forward (20 KB)   // weight matrices of a model (n_hidden + 1) niv_init_params takes
 
 // ---------------------------------------------------------------- layouts
 template <int P, class S> struct Bwd {
@@ -1262,10 +1263,17 @@ static hipError_t backward_t(const Model &m, const niv_batch &b, const niv_train
     hipLaunchKernelGGL(k_grid_count, dim3(kScatterBlocks), dim3(kScatterThreads), 0, side, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipEventRecord(ev.join, side)) != hipSuccess) return e;
+    // FP16: grid level 0, when dense and at most kL0Words entries, is read
+    // from LDS (its random-sample gathers would touch a line per lane)
+    if (P == NIV_FP16 && m.cfg.n_levels > 0 && m.dense[0] && m.size[0] <= kL0Words) {
+        a.l0_words = (uint32_t)m.size[0];
+        a.l0_off = (uint32_t)m.offset[0];
+    }
     {
         constexpr int kBlock = 256, kWavesPerBlock = 4;
         auto kern = k_query<P, S, true, 4, true, kBlock>;
-        const size_t lds = O::W_BYTES + (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4;
+        const size_t lds = O::W_BYTES + (size_t)kWavesPerBlock * 64 * O::ROW_DW * 4 +
+                           (P == NIV_FP16 ? (size_t)kL0Words * 4 : 0);
         static int max_blocks = -1, n_cu = 0;
         if (max_blocks < 0) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
