@@ -46,8 +46,8 @@
 
 namespace niv {
 
-constexpr int kMaxMats = 12;
-constexpr int kL0Words = 5120;   // LDS copy of grid level 0 in the FP16 training forward (20 KB)   // weight matrices of a model (n_hidden + 1) niv_init_params takes
+constexpr int kMaxMats = 12;   // weight matrices of a model (n_hidden + 1) niv_init_params takes
+constexpr int kL0Words = 5120;  // LDS copy of grid level 0 in the FP16 training forward (20 KB)
 
 // ---------------------------------------------------------------- layouts
 template <int P, class S> struct Bwd {
