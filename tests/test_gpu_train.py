@@ -150,6 +150,44 @@ def test_full_batch_gradient_is_bit_reproducible():
     assert same
 
 
+def test_two_streams_at_once_match_one_at_a_time():
+    """Two training states on two streams with their calls interleaved (the
+    count passes of both go to the library's second stream, each call with
+    its own fork and join events): each gradient equals the same call made
+    alone, bit for bit, on every one of three rounds."""
+    n = 1 << 16
+    from paper_2602_12949_amd import NIV, Trainer
+    w, oc, params, x, nrm, tgt = _setup("room_1080p", n, seed=31)
+    _, _, _, x2, nrm2, tgt2 = _setup("room_1080p", n, seed=32)
+    m = NIV(w.model_dict())
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    pa, pb = t(params), t(params)
+    in_a, in_b = (t(x), t(nrm), t(tgt)), (t(x2), t(nrm2), t(tgt2))
+    ta = Trainer(m, pa, "fp16", max_batch=n)
+    tb = Trainer(m, pb, "fp16", max_batch=n)
+    ta.backward(*in_a)
+    tb.backward(*in_b)
+    torch.cuda.synchronize()
+    ga, gb = ta.grads.clone(), tb.grads.clone()
+    assert not torch.equal(ga, gb)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    cur = torch.cuda.current_stream()
+    for r in range(3):
+        ta.grads.zero_()
+        tb.grads.zero_()
+        s1.wait_stream(cur)
+        s2.wait_stream(cur)
+        with torch.cuda.stream(s1):
+            ta.backward(*in_a)
+        with torch.cuda.stream(s2):
+            tb.backward(*in_b)
+        cur.wait_stream(s1)
+        cur.wait_stream(s2)
+        torch.cuda.synchronize()
+        print(f"  round {r}: equal {torch.equal(ga, ta.grads)} {torch.equal(gb, tb.grads)}", flush=True)
+        assert torch.equal(ga, ta.grads) and torch.equal(gb, tb.grads)
+
+
 def test_largest_batch_gradient_matches_oracle():
     """The largest batch niv_backward takes, 2^24 samples (2^31 contribution
     records on the 16-level room model; level 0's first bin alone gets ~1.1e8
