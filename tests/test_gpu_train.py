@@ -188,6 +188,40 @@ def test_two_streams_at_once_match_one_at_a_time():
         assert torch.equal(ga, ta.grads) and torch.equal(gb, tb.grads)
 
 
+def test_gradient_pass_replays_from_a_graph():
+    """niv_backward captured in a HIP graph (its count pass on the library's
+    second stream becomes a fork and join inside the graph) and replayed
+    three times, with eager calls and synchronisations between the replays:
+    every replay and every eager call gives the first eager gradient bit for
+    bit, and its loss (a sum of per-wave float additions, whose order
+    varies) to 1e-6."""
+    n = 1 << 14
+    from paper_2602_12949_amd import NIV, Trainer
+    w, oc, params, x, nrm, tgt = _setup("room_1080p", n, seed=41)
+    m = NIV(w.model_dict())
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    tr = Trainer(m, t(params), "fp16", max_batch=n)
+    inp = (t(x), t(nrm), t(tgt))
+    loss = tr.backward(*inp)
+    torch.cuda.synchronize()
+    g_ref, l_ref = tr.grads.clone(), loss.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tr.backward(*inp)
+    for r in range(3):
+        tr.grads.zero_()
+        tr.loss.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        close = lambda: abs(float(tr.loss) - float(l_ref)) <= 1e-6 * abs(float(l_ref))
+        rep_ok = torch.equal(tr.grads, g_ref) and close()
+        tr.backward(*inp)
+        torch.cuda.synchronize()
+        eager_ok = torch.equal(tr.grads, g_ref) and close()
+        print(f"  replay {r}: {rep_ok}, eager after it: {eager_ok}", flush=True)
+        assert rep_ok and eager_ok
+
+
 def test_largest_batch_gradient_matches_oracle():
     """The largest batch niv_backward takes, 2^24 samples (2^31 contribution
     records on the 16-level room model; level 0's first bin alone gets ~1.1e8
